@@ -1,0 +1,198 @@
+/*
+ * pcfv.h -- C ABI of libpcfv: the hot path of the adjoint-based variational
+ * method for equilibria of plane Couette flow (Ashtari & Schneider,
+ * arXiv 2306.00165) on AMD MI355X (gfx950).
+ *
+ * The problem (Sec. 3.1): perturbation u about the laminar base flow
+ * u_b = y e_x (Sec. 5) in the box x in [0,Lx), y in [-1,1], z in [0,Lz),
+ * periodic in x and z, no-slip walls, Reynolds number Re.  The method
+ * (Sec. 2-4) minimises J^2 = <r(u), r(u)> by the forward-Euler descent
+ * u <- u + dtau f,  f = -P J*(u) r(u).
+ *
+ * Discretisation (Sec. 4, Fourier-Chebyshev-Fourier expansion):
+ *   Nx, Nz  = collocation points / FFT lengths in x and z;
+ *   retained |kx| <= Kx = Nx/3 - 1, 0 <= kz <= Kz = Nz/3 - 1 (2/3 rule);
+ *   Ny      = number of Chebyshev coefficients = Gauss-Lobatto points.
+ *
+ * Spectral field layout (every u, r, v, w, g argument below):
+ *   device memory, complex128 stored as interleaved (re, im) doubles,
+ *   index [c][ikx][kz][n] with c = 0,1,2 the velocity component (x, y, z),
+ *   ikx = 0..2Kx in FFT order (kx = 0,1,..,Kx,-Kx,..,-1), kz = 0..Kz and
+ *   n = 0..Ny-1 the Chebyshev index (fastest).  Length 3*(2Kx+1)*(Kz+1)*Ny
+ *   complex values.  On the kz = 0 plane both signs of kx are stored and
+ *   must be complex conjugates; the (0,0) mode is real.
+ *
+ * Operators (exact discrete definitions, all in FP64):
+ *   <a,b>_W   volume-averaged L2 inner product (Sec. 3.2, inner product of
+ *             the search space): sum over stored modes of w Re a^H G b, with
+ *             G the Chebyshev Gram matrix, w = 1/2 on kz = 0 and 1 otherwise.
+ *   r(u)      = lam S(M(u) + nu L u): one first-order IMEX step of size
+ *             dt_im of the NSE minus u, divided by dt_im (Sec. 4 steps (1)-(2));
+ *             lam = 1/dt_im, nu = 1/Re, L = D^2 - kappa^2, M(u) = -A[(U.grad)U]
+ *             with U = u_b + u evaluated on the Nx x Ny x Nz grid and A the
+ *             truncating analysis; S = Chebyshev-tau Stokes solve, done with
+ *             the influence-matrix method (Sec. 4), keeping div = 0 and
+ *             no-slip exact.
+ *   J(u)v     directional derivative of r (Sec. 2; App. A.1).
+ *   J*(u)w    its exact adjoint in <.,.>_W (Sec. 2 definition; the paper's
+ *             continuous form is Sec. 3.3 / App. A.2).
+ *   P         W-orthogonal projection onto divergence-free, no-slip fields
+ *             (Sec. 3.4).
+ *
+ * Conventions:
+ *   - All array arguments are caller-owned device pointers; the library never
+ *     frees them.  Inputs and outputs must not alias unless stated.
+ *   - Every call is enqueued on the context's HIP stream and returns without
+ *     synchronising, except calls that return a host value (*_host), which
+ *     synchronise the stream before returning.
+ *   - Errors are reported by return code; nothing is thrown across the ABI.
+ *     pcfv_last_error() gives a message for the last failure on a context.
+ *   - Inputs are assumed admissible (divergence-free, no-slip, Hermitian)
+ *     where stated; pcfv_check_state() measures the defects.
+ *   - One context per host thread; a context is not thread-safe.
+ */
+#ifndef PCFV_H
+#define PCFV_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pcfv_ctx pcfv_ctx;
+
+typedef enum {
+    PCFV_OK = 0,
+    PCFV_EINVAL = -1,     /* bad configuration or argument                        */
+    PCFV_ENOMEM = -2,     /* workspace too small                                  */
+    PCFV_EDEVICE = -3,    /* a HIP call failed                                    */
+    PCFV_ENAN = -4,       /* cost became NaN or Inf during descent                */
+    PCFV_EDIVERGED = -5,  /* cost grew beyond grow_tol and halvings ran out       */
+    PCFV_ENOTCONV = -6    /* max_steps reached above rel_tol (a local minimum of
+                             J, Sec. 2, or simply not enough steps)               */
+} pcfv_status;
+
+/* Problem definition (Sec. 3.1 and Sec. 5.1).  6 <= Nx, Nz <= 512 (any
+ * integers), 9 <= Ny <= 128.  precision must be 0 (FP64). */
+typedef struct {
+    double Lx, Lz, Re;
+    int Nx, Ny, Nz;
+    double dt_im;        /* Delta t of the Stokes step inside r(u); the paper uses 0.25 */
+    int precision;       /* 0 = FP64 */
+} pcfv_config;
+
+typedef struct {
+    int Kx, Kz, Ny, nkx, nkz;
+    long long n_modes;   /* nkx * nkz                                   */
+    long long n_complex; /* 3 * n_modes * Ny: complex values per field  */
+    long long n_state;   /* length of the minimal real state vector     */
+} pcfv_layout;
+
+/* Bytes of device workspace pcfv_create needs for this configuration;
+ * 0 if the configuration is invalid. */
+size_t pcfv_workspace_bytes(const pcfv_config* cfg);
+
+/* Build a context.  hip_stream: a hipStream_t (NULL = the default stream).
+ * workspace: caller-owned device memory of at least pcfv_workspace_bytes(cfg)
+ * bytes, 256-byte aligned; it holds every table and scratch buffer the
+ * context uses and must outlive the context.  The context's tables are
+ * computed on the host in extended precision and copied in (synchronously).
+ * Errors: PCFV_EINVAL (bad cfg or NULL out), PCFV_ENOMEM (NULL workspace),
+ * PCFV_EDEVICE. */
+pcfv_status pcfv_create(const pcfv_config* cfg, void* hip_stream, void* workspace,
+                        pcfv_ctx** out);
+
+/* Release host-side state; never touches caller memory.  Safe on NULL. */
+void pcfv_destroy(pcfv_ctx* ctx);
+
+pcfv_status pcfv_get_layout(const pcfv_ctx* ctx, pcfv_layout* out);
+pcfv_status pcfv_set_stream(pcfv_ctx* ctx, void* hip_stream);
+
+/* Residual r(u) (Sec. 4 steps (1)-(2), Sec. 3.2 residual).  u admissible.
+ * r may be NULL (then only the cost is formed).  cost_host, if non-NULL,
+ * receives J^2 = <r,r>_W and the call synchronises. */
+pcfv_status pcfv_residual(pcfv_ctx* ctx, const double* u, double* r, double* cost_host);
+
+/* J^2 = <r(u), r(u)>_W (Sec. 2 cost function); synchronises. */
+pcfv_status pcfv_cost(pcfv_ctx* ctx, const double* u, double* cost_host);
+
+/* Jv = J(u) v, the directional derivative of r at u along v (Sec. 2). */
+pcfv_status pcfv_jvp(pcfv_ctx* ctx, const double* u, const double* v, double* Jv);
+
+/* out = J*(u) w, the exact W-adjoint of J(u) (not projected).  w may be any
+ * Hermitian-consistent field. */
+pcfv_status pcfv_adjoint(pcfv_ctx* ctx, const double* u, const double* w, double* out);
+
+/* Pg = P g, the W-orthogonal projection onto divergence-free no-slip fields
+ * (Sec. 3.4). g any Hermitian-consistent field.  Pg may equal g (in place). */
+pcfv_status pcfv_project(pcfv_ctx* ctx, const double* g, double* Pg);
+
+/* One or more descent steps (Sec. 4 step (5)). */
+typedef struct {
+    long long max_steps;  /* steps to take at most                                  */
+    double dtau;          /* forward-Euler step (the paper: 0.03 at 32x31x32)         */
+    double rel_tol;       /* stop when ||r||_W / ||u_b + u||_W < rel_tol (0 = never)  */
+    int check_every;      /* cost read-back period in steps (>= 1)                    */
+    double grow_tol;      /* cost growth factor between checks that counts as
+                             divergence (<= 0: disabled)                             */
+    int max_halvings;     /* dtau halvings allowed on divergence                      */
+} pcfv_descent_opts;
+
+typedef struct {
+    long long steps;      /* steps taken                                             */
+    double tau;           /* fictitious time advanced                                */
+    double cost;          /* J^2 at the last check (of the final state if converged)  */
+    double rel_res;       /* ||r||_W / ||u_b + u||_W at the last check               */
+    double dtau_final;
+    int n_halvings;
+} pcfv_descent_report;
+
+/* Advance u in place.  Returns PCFV_OK when rel_tol was reached (or, with
+ * rel_tol = 0, after max_steps), PCFV_ENOTCONV when max_steps ran out above
+ * rel_tol, PCFV_ENAN on a non-finite cost, PCFV_EDIVERGED when the cost kept
+ * growing after max_halvings halvings (u is then the last checked state). */
+pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* opts,
+                         pcfv_descent_report* report);
+
+/* Norms: out_host[0] = ||u||_W, out_host[1] = ||u_b + u||_W,
+ * out_host[2] = D = <curl U, curl U>_W (so that laminar flow has D = 1,
+ * Table 2), synchronises. */
+pcfv_status pcfv_norms(pcfv_ctx* ctx, const double* u, double out_host[3]);
+
+/* Minimal real state vector psi (Sec. 6.2), length n_state doubles:
+ * (0,0) mode: u_x and u_z coefficients n = 0..Ny-3; then for each independent
+ * mode (kz > 0, or kz = 0 with kx > 0) in storage order: Re v, Im v for
+ * n = 0..Ny-5, Re eta, Im eta for n = 0..Ny-3, with v the wall-normal velocity
+ * and eta = i b u_x - i a u_z.  pack needs admissible u; unpack returns an
+ * admissible, Hermitian-consistent field. */
+pcfv_status pcfv_pack_state(pcfv_ctx* ctx, const double* u, double* psi);
+pcfv_status pcfv_unpack_state(pcfv_ctx* ctx, const double* psi, double* u);
+
+/* Admissibility defects of u: defects_host[0] = max |divergence coefficient|,
+ * [1] = max |wall value|, [2] = max Hermitian defect on kz = 0; synchronises. */
+pcfv_status pcfv_check_state(pcfv_ctx* ctx, const double* u, double defects_host[3]);
+
+/* Average device time per launch, in milliseconds, of each kernel of one
+ * descent step, measured with HIP events on the context stream over nrep
+ * launches each (u is left unchanged).  ms_out[0..4] = synthesis, forward
+ * products, residual/adjoint-solve per mode, adjoint products, gradient/
+ * projection/update per mode.  Returns the number of entries via *n_out. */
+pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* ms_out,
+                              int* n_out);
+
+const char* pcfv_last_error(const pcfv_ctx* ctx);
+
+/* Host-side copy of a constant table for cfg, computed without a device (for
+ * tests of the setup arithmetic).  which: 0 fixed matrices (M_COUNT slots of
+ * Ny x Ny, transposed), 1 per-mode scalars, 2 Helmholtz diagonals,
+ * 3 Poisson diagonals, 4 projection diagonals, 5 homogeneous v responses,
+ * 6 their derivatives, 7 inverse influence matrices, 8 eigenvalues of the tau
+ * second derivative.  Copies min(cap, size) doubles to out (if non-NULL) and
+ * returns the table size in doubles, or 0 if cfg or which is invalid. */
+size_t pcfv_host_table(const pcfv_config* cfg, int which, double* out, size_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCFV_H */

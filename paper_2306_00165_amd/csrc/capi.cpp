@@ -1,0 +1,505 @@
+// C ABI of libpcfv (declared in include/pcfv.h): context, workspace layout,
+// and the host-side sequencing of the kernels for each call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pcfv.h"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+using namespace pcfv;
+
+namespace {
+
+enum WsSlot {
+    W_MATS, W_MINFO, W_DH, W_DP, W_DPROJ, W_VK, W_DVK, W_AINV, W_TWX, W_TWZ, W_YGL, W_INDEP,
+    W_Y, W_YV, W_ATIL, W_P3, W_P6, W_A, W_R, W_CK, W_TMP, W_PART, W_SCAL, W_COUNT
+};
+
+struct WsLayout {
+    size_t off[W_COUNT];
+    size_t total;
+};
+
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxPlaneLds = 64 * 1024;
+
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool validate(const pcfv_config* c, std::string& e) {
+    if (!c) {
+        e = "config is NULL";
+        return false;
+    }
+    if (c->precision != 0) {
+        e = "only precision 0 (FP64) is supported";
+        return false;
+    }
+    if (c->Nx < 6 || c->Nz < 6 || c->Nx > 512 || c->Nz > 512) {
+        e = "Nx and Nz must lie in [6, 512]";
+        return false;
+    }
+    if (c->Ny < 9 || c->Ny > 128) {
+        e = "Ny must lie in [9, 128]";
+        return false;
+    }
+    if (!(c->Lx > 0) || !(c->Lz > 0) || !(c->Re > 0) || !(c->dt_im > 0) ||
+        !std::isfinite(c->Lx + c->Lz + c->Re + c->dt_im)) {
+        e = "Lx, Lz, Re and dt_im must be positive and finite";
+        return false;
+    }
+    return true;
+}
+
+KP base_kp(const pcfv_config& c) {
+    KP p{};
+    p.N = c.Ny;
+    p.Nx = c.Nx;
+    p.Nz = c.Nz;
+    p.Kx = c.Nx / 3 - 1;
+    p.Kz = c.Nz / 3 - 1;
+    p.nkx = 2 * p.Kx + 1;
+    p.nkz = p.Kz + 1;
+    p.nm = p.nkx * p.nkz;
+    // widest x slab (a divisor of Nx, at most 8) whose physical-space kernels
+    // fit in 64 KiB of LDS
+    p.XS = 1;
+    for (int xs = 8; xs >= 1; --xs) {
+        if (c.Nx % xs) continue;
+        p.XS = xs;
+        if (plane_lds_bytes(p, PLANE_ADJ) <= kMaxPlaneLds && plane_lds_bytes(p, PLANE_JVP) <= kMaxPlaneLds)
+            break;
+    }
+    p.NS = c.Nx / p.XS;
+    return p;
+}
+
+WsLayout layout(const pcfv_config& c) {
+    const KP p = base_kp(c);
+    const size_t N = p.N, nm = p.nm, NS = p.NS;
+    size_t sz[W_COUNT];
+    sz[W_MATS] = (size_t)M_COUNT * N * N * 8;
+    sz[W_MINFO] = nm * MI_STRIDE * 8;
+    sz[W_DH] = sz[W_DP] = sz[W_DPROJ] = nm * N * 8;
+    sz[W_VK] = sz[W_DVK] = nm * 4 * N * 8;
+    sz[W_AINV] = nm * 16 * 8;
+    sz[W_TWX] = (size_t)c.Nx * 16;
+    sz[W_TWZ] = (size_t)c.Nz * 16;
+    sz[W_YGL] = N * 8;
+    sz[W_INDEP] = nm * 4;
+    sz[W_Y] = sz[W_YV] = 6 * N * nm * 16;
+    sz[W_ATIL] = 3 * N * nm * 16;
+    sz[W_P3] = NS * 3 * N * nm * 16;
+    sz[W_P6] = NS * 6 * N * nm * 16;
+    sz[W_A] = sz[W_R] = sz[W_CK] = sz[W_TMP] = 3 * nm * N * 16;
+    sz[W_PART] = nm * 4 * 8;
+    sz[W_SCAL] = 64 * 8;
+    WsLayout L;
+    size_t o = 0;
+    for (int i = 0; i < W_COUNT; ++i) {
+        L.off[i] = o;
+        o += up(sz[i]);
+    }
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct pcfv_ctx {
+    pcfv_config cfg;
+    Tables t;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    WsLayout L;
+    KP kp;
+    double2 *Y, *Yv, *Atil, *P3, *P6, *a, *r, *ck, *tmp;
+    double *part, *scal;
+    std::string err;
+
+    template <class T>
+    T* at(int slot) { return reinterpret_cast<T*>(ws + L.off[slot]); }
+    long long nfield() const { return 3LL * kp.nm * kp.N; }  // complex values per field
+};
+
+namespace {
+
+pcfv_status fail(pcfv_ctx* c, pcfv_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+pcfv_status hip_check(pcfv_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return PCFV_OK;
+    return fail(c, PCFV_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define PCFV_TRY(expr, what)                                   \
+    do {                                                       \
+        pcfv_status _s = hip_check(ctx, (expr), what);         \
+        if (_s != PCFV_OK) return _s;                          \
+    } while (0)
+
+const double2* cd(const double* p) { return reinterpret_cast<const double2*>(p); }
+double2* dd(double* p) { return reinterpret_cast<double2*>(p); }
+
+// Residual of u into r (if r) and per-mode cost partials; Y must hold the
+// y-values of u.
+pcfv_status residual_core(pcfv_ctx* ctx, const double* u, double* r, bool cost) {
+    const KP& p = ctx->kp;
+    PCFV_TRY(launch_plane(p, ctx->stream, PLANE_FWD, ctx->Y, nullptr, ctx->P3), "plane fwd");
+    int flags = (r ? RES_WRITE_R : 0) | (cost ? RES_COST : 0);
+    PCFV_TRY(launch_mode_res(p, ctx->stream, flags, ctx->P3, cd(u), r ? dd(r) : ctx->r, ctx->part,
+                             nullptr, nullptr),
+             "mode res");
+    return PCFV_OK;
+}
+
+pcfv_status read_scalars(pcfv_ctx* ctx, int n, int stride, int op, double* host) {
+    PCFV_TRY(launch_reduce(ctx->stream, ctx->part, n, stride, op, ctx->scal), "reduce");
+    PCFV_TRY(hipMemcpyAsync(host, ctx->scal, stride * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+             "copy scalars");
+    PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
+    return PCFV_OK;
+}
+
+pcfv_status cost_and_norm(pcfv_ctx* ctx, const double* u, double* cost, double* ntot) {
+    pcfv_status s = residual_core(ctx, u, nullptr, true);
+    if (s != PCFV_OK) return s;
+    s = read_scalars(ctx, ctx->kp.nm, 1, 0, cost);
+    if (s != PCFV_OK) return s;
+    PCFV_TRY(launch_norms(ctx->kp, ctx->stream, cd(u), ctx->part), "norms");
+    double nrm[3];
+    s = read_scalars(ctx, ctx->kp.nm, 3, 0, nrm);
+    if (s != PCFV_OK) return s;
+    *ntot = std::sqrt(nrm[1]);
+    return PCFV_OK;
+}
+
+pcfv_status descent_step(pcfv_ctx* ctx, double* u, double dtau) {
+    const KP& p = ctx->kp;
+    hipStream_t s = ctx->stream;
+    PCFV_TRY(launch_plane(p, s, PLANE_FWD, ctx->Y, nullptr, ctx->P3), "plane fwd");
+    PCFV_TRY(launch_mode_res(p, s, RES_COST | RES_ADJ, ctx->P3, cd(u), nullptr, ctx->part, ctx->a,
+                             ctx->Atil),
+             "mode res");
+    PCFV_TRY(launch_plane(p, s, PLANE_ADJ, ctx->Y, ctx->Atil, ctx->P6), "plane adj");
+    PCFV_TRY(launch_mode_grad(p, s, GRAD_PROJECT | GRAD_UPDATE, ctx->P6, ctx->a, dtau, dd(u), ctx->Y),
+             "mode grad");
+    return PCFV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pcfv_workspace_bytes(const pcfv_config* cfg) {
+    std::string e;
+    if (!validate(cfg, e)) return 0;
+    return layout(*cfg).total;
+}
+
+pcfv_status pcfv_create(const pcfv_config* cfg, void* hip_stream, void* workspace, pcfv_ctx** out) {
+    if (!out) return PCFV_EINVAL;
+    *out = nullptr;
+    std::string e;
+    if (!validate(cfg, e)) return PCFV_EINVAL;
+    if (!workspace) return PCFV_ENOMEM;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return PCFV_EINVAL;
+    pcfv_ctx* ctx = new pcfv_ctx();
+    ctx->cfg = *cfg;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    ctx->ws = reinterpret_cast<char*>(workspace);
+    if (!build_tables(cfg->Lx, cfg->Lz, cfg->Re, cfg->Nx, cfg->Ny, cfg->Nz, cfg->dt_im, ctx->t, e)) {
+        delete ctx;
+        return PCFV_EINVAL;
+    }
+    ctx->L = layout(*cfg);
+    KP p = base_kp(*cfg);
+    const Tables& t = ctx->t;
+    p.lam = t.lam;
+    p.nu = t.nu;
+    p.alpha = t.alpha;
+    p.beta = t.beta;
+    p.M = ctx->at<double>(W_MATS);
+    p.minfo = ctx->at<double>(W_MINFO);
+    p.dH = ctx->at<double>(W_DH);
+    p.dP = ctx->at<double>(W_DP);
+    p.dproj = ctx->at<double>(W_DPROJ);
+    p.Vk = ctx->at<double>(W_VK);
+    p.DVk = ctx->at<double>(W_DVK);
+    p.Ainv = ctx->at<double>(W_AINV);
+    p.twx = ctx->at<double2>(W_TWX);
+    p.twz = ctx->at<double2>(W_TWZ);
+    p.ygl = ctx->at<double>(W_YGL);
+    p.indep = ctx->at<int>(W_INDEP);
+    ctx->kp = p;
+    ctx->Y = ctx->at<double2>(W_Y);
+    ctx->Yv = ctx->at<double2>(W_YV);
+    ctx->Atil = ctx->at<double2>(W_ATIL);
+    ctx->P3 = ctx->at<double2>(W_P3);
+    ctx->P6 = ctx->at<double2>(W_P6);
+    ctx->a = ctx->at<double2>(W_A);
+    ctx->r = ctx->at<double2>(W_R);
+    ctx->ck = ctx->at<double2>(W_CK);
+    ctx->tmp = ctx->at<double2>(W_TMP);
+    ctx->part = ctx->at<double>(W_PART);
+    ctx->scal = ctx->at<double>(W_SCAL);
+    struct Up {
+        int slot;
+        const void* src;
+        size_t bytes;
+    } ups[] = {
+        {W_MATS, t.mats.data(), t.mats.size() * 8},   {W_MINFO, t.minfo.data(), t.minfo.size() * 8},
+        {W_DH, t.dH.data(), t.dH.size() * 8},         {W_DP, t.dP.data(), t.dP.size() * 8},
+        {W_DPROJ, t.dproj.data(), t.dproj.size() * 8}, {W_VK, t.Vk.data(), t.Vk.size() * 8},
+        {W_DVK, t.DVk.data(), t.DVk.size() * 8},      {W_AINV, t.Ainv.data(), t.Ainv.size() * 8},
+        {W_TWX, t.twx.data(), t.twx.size() * 8},      {W_TWZ, t.twz.data(), t.twz.size() * 8},
+        {W_YGL, t.ygl.data(), t.ygl.size() * 8},      {W_INDEP, t.indep.data(), t.indep.size() * 4},
+    };
+    for (const Up& u : ups) {
+        hipError_t he = hipMemcpyAsync(ctx->ws + ctx->L.off[u.slot], u.src, u.bytes, hipMemcpyHostToDevice,
+                                       ctx->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+        if (he != hipSuccess) {
+            delete ctx;
+            return PCFV_EDEVICE;
+        }
+    }
+    *out = ctx;
+    return PCFV_OK;
+}
+
+void pcfv_destroy(pcfv_ctx* ctx) { delete ctx; }
+
+pcfv_status pcfv_get_layout(const pcfv_ctx* ctx, pcfv_layout* out) {
+    if (!ctx || !out) return PCFV_EINVAL;
+    const KP& p = ctx->kp;
+    out->Kx = p.Kx;
+    out->Kz = p.Kz;
+    out->Ny = p.N;
+    out->nkx = p.nkx;
+    out->nkz = p.nkz;
+    out->n_modes = p.nm;
+    out->n_complex = 3LL * p.nm * p.N;
+    out->n_state = ctx->t.n_state;
+    return PCFV_OK;
+}
+
+pcfv_status pcfv_set_stream(pcfv_ctx* ctx, void* hip_stream) {
+    if (!ctx) return PCFV_EINVAL;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return PCFV_OK;
+}
+
+pcfv_status pcfv_residual(pcfv_ctx* ctx, const double* u, double* r, double* cost_host) {
+    if (!ctx || !u) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    PCFV_TRY(launch_synth(ctx->kp, ctx->stream, cd(u), ctx->Y), "synth");
+    pcfv_status s = residual_core(ctx, u, r, cost_host != nullptr);
+    if (s != PCFV_OK || !cost_host) return s;
+    return read_scalars(ctx, ctx->kp.nm, 1, 0, cost_host);
+}
+
+pcfv_status pcfv_cost(pcfv_ctx* ctx, const double* u, double* cost_host) {
+    if (!ctx || !u || !cost_host) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    return pcfv_residual(ctx, u, nullptr, cost_host);
+}
+
+pcfv_status pcfv_jvp(pcfv_ctx* ctx, const double* u, const double* v, double* Jv) {
+    if (!ctx || !u || !v || !Jv) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    const KP& p = ctx->kp;
+    PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth u");
+    PCFV_TRY(launch_synth(p, ctx->stream, cd(v), ctx->Yv), "synth v");
+    PCFV_TRY(launch_plane(p, ctx->stream, PLANE_JVP, ctx->Y, ctx->Yv, ctx->P3), "plane jvp");
+    PCFV_TRY(launch_mode_res(p, ctx->stream, RES_WRITE_R, ctx->P3, cd(v), dd(Jv), ctx->part, nullptr,
+                             nullptr),
+             "mode res");
+    return PCFV_OK;
+}
+
+pcfv_status pcfv_adjoint(pcfv_ctx* ctx, const double* u, const double* w, double* out) {
+    if (!ctx || !u || !w || !out) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    const KP& p = ctx->kp;
+    PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth u");
+    PCFV_TRY(launch_mode_res(p, ctx->stream, RES_INPUT_W | RES_ADJ, ctx->P3, cd(w), nullptr, ctx->part,
+                             ctx->a, ctx->Atil),
+             "adjoint solve");
+    PCFV_TRY(launch_plane(p, ctx->stream, PLANE_ADJ, ctx->Y, ctx->Atil, ctx->P6), "plane adj");
+    PCFV_TRY(launch_mode_grad(p, ctx->stream, 0, ctx->P6, ctx->a, 0.0, dd(out), nullptr), "mode grad");
+    return PCFV_OK;
+}
+
+pcfv_status pcfv_project(pcfv_ctx* ctx, const double* g, double* Pg) {
+    if (!ctx || !g || !Pg) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    PCFV_TRY(launch_project(ctx->kp, ctx->stream, cd(g), dd(Pg)), "project");
+    return PCFV_OK;
+}
+
+pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
+                         pcfv_descent_report* rep) {
+    if (!ctx || !u || !o) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    if (o->max_steps < 0 || !(o->dtau > 0) || o->check_every < 1 || o->max_halvings < 0 ||
+        !(o->rel_tol >= 0))
+        return fail(ctx, PCFV_EINVAL, "invalid descent options");
+    const KP& p = ctx->kp;
+    const size_t fbytes = (size_t)ctx->nfield() * 16;
+    double dtau = o->dtau, tau = 0, cost = 0, ntot = 0;
+    long long steps = 0;
+    int halvings = 0;
+    pcfv_descent_report local{};
+    if (!rep) rep = &local;
+    auto report = [&](pcfv_status s) {
+        rep->steps = steps;
+        rep->tau = tau;
+        rep->cost = cost;
+        rep->rel_res = (ntot > 0) ? std::sqrt(std::max(cost, 0.0)) / ntot : 0.0;
+        rep->dtau_final = dtau;
+        rep->n_halvings = halvings;
+        return s;
+    };
+    PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth");
+    pcfv_status s = cost_and_norm(ctx, u, &cost, &ntot);
+    if (s != PCFV_OK) return s;
+    if (!std::isfinite(cost)) return report(fail(ctx, PCFV_ENAN, "cost is not finite"));
+    double cost_prev = cost;
+    if (o->rel_tol > 0 && std::sqrt(cost) / ntot < o->rel_tol) return report(PCFV_OK);
+    while (steps < o->max_steps) {
+        const long long k = std::min<long long>(o->check_every, o->max_steps - steps);
+        if (o->grow_tol > 0)
+            PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
+        for (long long i = 0; i < k; ++i) {
+            s = descent_step(ctx, u, dtau);
+            if (s != PCFV_OK) return s;
+        }
+        steps += k;
+        tau += k * dtau;
+        s = cost_and_norm(ctx, u, &cost, &ntot);
+        if (s != PCFV_OK) return s;
+        if (!std::isfinite(cost)) return report(fail(ctx, PCFV_ENAN, "cost is not finite"));
+        if (o->grow_tol > 0 && cost > o->grow_tol * cost_prev) {
+            if (halvings >= o->max_halvings) {
+                PCFV_TRY(hipMemcpyAsync(u, ctx->ck, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "restore");
+                PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
+                cost = cost_prev;
+                return report(fail(ctx, PCFV_EDIVERGED, "cost grew beyond grow_tol"));
+            }
+            PCFV_TRY(hipMemcpyAsync(u, ctx->ck, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "restore");
+            PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth");
+            steps -= k;
+            tau -= k * dtau;
+            dtau *= 0.5;
+            ++halvings;
+            cost = cost_prev;
+            continue;
+        }
+        cost_prev = cost;
+        if (o->rel_tol > 0 && std::sqrt(cost) / ntot < o->rel_tol) return report(PCFV_OK);
+    }
+    return report(o->rel_tol > 0 ? fail(ctx, PCFV_ENOTCONV, "max_steps reached above rel_tol") : PCFV_OK);
+}
+
+pcfv_status pcfv_norms(pcfv_ctx* ctx, const double* u, double out_host[3]) {
+    if (!ctx || !u || !out_host) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    PCFV_TRY(launch_norms(ctx->kp, ctx->stream, cd(u), ctx->part), "norms");
+    double v[3];
+    pcfv_status s = read_scalars(ctx, ctx->kp.nm, 3, 0, v);
+    if (s != PCFV_OK) return s;
+    out_host[0] = std::sqrt(std::max(v[0], 0.0));
+    out_host[1] = std::sqrt(std::max(v[1], 0.0));
+    out_host[2] = v[2];
+    return PCFV_OK;
+}
+
+pcfv_status pcfv_pack_state(pcfv_ctx* ctx, const double* u, double* psi) {
+    if (!ctx || !u || !psi) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    PCFV_TRY(launch_pack(ctx->kp, ctx->stream, cd(u), psi), "pack");
+    return PCFV_OK;
+}
+
+pcfv_status pcfv_unpack_state(pcfv_ctx* ctx, const double* psi, double* u) {
+    if (!ctx || !u || !psi) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    PCFV_TRY(launch_unpack(ctx->kp, ctx->stream, psi, dd(u)), "unpack");
+    return PCFV_OK;
+}
+
+pcfv_status pcfv_check_state(pcfv_ctx* ctx, const double* u, double defects_host[3]) {
+    if (!ctx || !u || !defects_host) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    PCFV_TRY(launch_check(ctx->kp, ctx->stream, cd(u), ctx->part), "check");
+    return read_scalars(ctx, ctx->kp.nm, 3, 1, defects_host);
+}
+
+pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* ms_out, int* n_out) {
+    if (!ctx || !u || !ms_out || nrep < 1) return fail(ctx, PCFV_EINVAL, "bad argument");
+    const KP& p = ctx->kp;
+    hipStream_t s = ctx->stream;
+    const size_t fbytes = (size_t)ctx->nfield() * 16;
+    PCFV_TRY(hipMemcpyAsync(ctx->tmp, u, fbytes, hipMemcpyDeviceToDevice, s), "copy");
+    PCFV_TRY(launch_synth(p, s, ctx->tmp, ctx->Y), "synth");
+    PCFV_TRY(launch_plane(p, s, PLANE_FWD, ctx->Y, nullptr, ctx->P3), "plane fwd");
+    PCFV_TRY(launch_mode_res(p, s, RES_COST | RES_ADJ, ctx->P3, ctx->tmp, nullptr, ctx->part, ctx->a,
+                             ctx->Atil),
+             "mode res");
+    hipEvent_t e0, e1;
+    PCFV_TRY(hipEventCreate(&e0), "event");
+    PCFV_TRY(hipEventCreate(&e1), "event");
+    for (int k = 0; k < 5; ++k) {
+        PCFV_TRY(hipEventRecord(e0, s), "record");
+        for (int i = 0; i < nrep; ++i) {
+            hipError_t he = hipSuccess;
+            switch (k) {
+                case 0: he = launch_synth(p, s, ctx->tmp, ctx->Yv); break;
+                case 1: he = launch_plane(p, s, PLANE_FWD, ctx->Y, nullptr, ctx->P3); break;
+                case 2:
+                    he = launch_mode_res(p, s, RES_COST | RES_ADJ, ctx->P3, ctx->tmp, nullptr, ctx->part,
+                                         ctx->a, ctx->Atil);
+                    break;
+                case 3: he = launch_plane(p, s, PLANE_ADJ, ctx->Y, ctx->Atil, ctx->P6); break;
+                case 4:
+                    he = launch_mode_grad(p, s, GRAD_PROJECT | GRAD_UPDATE, ctx->P6, ctx->a, 0.0, ctx->tmp,
+                                          ctx->Yv);
+                    break;
+            }
+            PCFV_TRY(he, "launch");
+        }
+        PCFV_TRY(hipEventRecord(e1, s), "record");
+        PCFV_TRY(hipEventSynchronize(e1), "event sync");
+        float ms = 0;
+        PCFV_TRY(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        ms_out[k] = ms / nrep;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (n_out) *n_out = 5;
+    return PCFV_OK;
+}
+
+const char* pcfv_last_error(const pcfv_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+size_t pcfv_host_table(const pcfv_config* cfg, int which, double* out, size_t cap) {
+    std::string e;
+    if (!validate(cfg, e)) return 0;
+    Tables t;
+    if (!build_tables(cfg->Lx, cfg->Lz, cfg->Re, cfg->Nx, cfg->Ny, cfg->Nz, cfg->dt_im, t, e)) return 0;
+    const std::vector<double>* v = nullptr;
+    switch (which) {
+        case 0: v = &t.mats; break;
+        case 1: v = &t.minfo; break;
+        case 2: v = &t.dH; break;
+        case 3: v = &t.dP; break;
+        case 4: v = &t.dproj; break;
+        case 5: v = &t.Vk; break;
+        case 6: v = &t.DVk; break;
+        case 7: v = &t.Ainv; break;
+        case 8: v = &t.mu; break;
+        default: return 0;
+    }
+    if (out) std::memcpy(out, v->data(), std::min(cap, v->size()) * sizeof(double));
+    return v->size();
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Device-side parameters and launch wrappers of the pcfv kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "tables.hpp"
+
+namespace pcfv {
+
+// Everything a kernel needs about the discretisation; passed by value.
+struct KP {
+    int N, Nx, Nz, nkx, nkz, nm, Kx, Kz;
+    int XS, NS;              // x-slab width of the physical-space kernels, number of slabs
+    double lam, nu, alpha, beta;
+    const double* M;         // M_COUNT fixed matrices, N x N slots, transposed
+    const double* minfo;     // per-mode scalars (MI_STRIDE each)
+    const double* dH;        // per-mode 1/(sigma - nu mu_k)
+    const double* dP;        // per-mode 1/(kappa^2 - mu_k)
+    const double* dproj;     // per-mode 1/(1 + Lambda_k / kappa^2)
+    const double* Vk;        // per-mode homogeneous v responses (4 x N)
+    const double* DVk;       // their derivatives
+    const double* Ainv;      // per-mode inverse influence matrices (4 x 4)
+    const double2* twx;      // exp(2 pi i k/Nx)
+    const double2* twz;      // exp(2 pi i k/Nz)
+    const double* ygl;       // Gauss-Lobatto points
+    const int* indep;        // independent-mode index (state vector)
+};
+
+// Physical-space kernel variants.
+enum PlaneMode { PLANE_FWD = 0, PLANE_JVP = 1, PLANE_ADJ = 2 };
+
+// Flags of the residual / transposed-solve mode kernel.
+enum ResFlags {
+    RES_INPUT_W = 1,   // skip the residual: the input field is taken as r
+    RES_WRITE_R = 2,   // write r
+    RES_COST = 4,      // write the per-mode cost partial
+    RES_ADJ = 8,       // form a = S* r and the synthesis values of a for the adjoint products
+};
+
+// Flags of the gradient mode kernel.
+enum GradFlags {
+    GRAD_PROJECT = 1,  // f = -P g instead of g
+    GRAD_UPDATE = 2,   // u += dtau f and synthesise the new u (descent step)
+};
+
+size_t plane_lds_bytes(const KP& p, int mode);
+size_t mode_lds_bytes(const KP& p);
+
+// All launches are asynchronous on `s`; they return the launch error code.
+hipError_t launch_synth(const KP& p, hipStream_t s, const double2* u, double2* Y);
+hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const double2* Y1,
+                        const double2* Y2, double2* out);
+hipError_t launch_mode_res(const KP& p, hipStream_t s, int flags, const double2* P3,
+                           const double2* u, double2* r, double* cost_part, double2* a,
+                           double2* Atil);
+hipError_t launch_mode_grad(const KP& p, hipStream_t s, int flags, const double2* P6,
+                            const double2* a, double dtau, double2* u_or_out, double2* Y);
+hipError_t launch_project(const KP& p, hipStream_t s, const double2* g, double2* out);
+hipError_t launch_reduce(hipStream_t s, const double* part, int n, int stride, int op,
+                         double* out);
+hipError_t launch_norms(const KP& p, hipStream_t s, const double2* u, double* part);
+hipError_t launch_check(const KP& p, hipStream_t s, const double2* u, double* part);
+hipError_t launch_pack(const KP& p, hipStream_t s, const double2* u, double* psi);
+hipError_t launch_unpack(const KP& p, hipStream_t s, const double* psi, double2* u);
+hipError_t launch_axpy(hipStream_t s, long long n, double a, const double* x, double* y);
+
+}  // namespace pcfv

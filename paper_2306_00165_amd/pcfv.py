@@ -1,0 +1,265 @@
+"""Thin ctypes binding of libpcfv (C ABI in include/pcfv.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libpcfv.so.  PyTorch provides device memory (the caller's fields
+and the context workspace) and the HIP stream.  Fields are complex128 tensors
+of shape (3, 2Kx+1, Kz+1, Ny) on the GPU (layout documented in pcfv.h).
+
+Importing this module loads libpcfv.so and fails loudly if it is missing: there
+is no fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libpcfv.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENAN, EDIVERGED, ENOTCONV = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "PCFV_OK", -1: "PCFV_EINVAL", -2: "PCFV_ENOMEM", -3: "PCFV_EDEVICE",
+                -4: "PCFV_ENAN", -5: "PCFV_EDIVERGED", -6: "PCFV_ENOTCONV"}
+
+EXPORTS = [
+    "pcfv_workspace_bytes", "pcfv_create", "pcfv_destroy", "pcfv_get_layout", "pcfv_set_stream",
+    "pcfv_residual", "pcfv_cost", "pcfv_jvp", "pcfv_adjoint", "pcfv_project", "pcfv_descend",
+    "pcfv_norms", "pcfv_pack_state", "pcfv_unpack_state", "pcfv_check_state",
+    "pcfv_time_kernels", "pcfv_last_error", "pcfv_host_table",
+]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_double), ("Lz", ctypes.c_double), ("Re", ctypes.c_double),
+                ("Nx", ctypes.c_int), ("Ny", ctypes.c_int), ("Nz", ctypes.c_int),
+                ("dt_im", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("Kx", ctypes.c_int), ("Kz", ctypes.c_int), ("Ny", ctypes.c_int),
+                ("nkx", ctypes.c_int), ("nkz", ctypes.c_int), ("n_modes", ctypes.c_longlong),
+                ("n_complex", ctypes.c_longlong), ("n_state", ctypes.c_longlong)]
+
+
+class DescentOpts(ctypes.Structure):
+    _fields_ = [("max_steps", ctypes.c_longlong), ("dtau", ctypes.c_double),
+                ("rel_tol", ctypes.c_double), ("check_every", ctypes.c_int),
+                ("grow_tol", ctypes.c_double), ("max_halvings", ctypes.c_int)]
+
+
+class DescentReport(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_longlong), ("tau", ctypes.c_double), ("cost", ctypes.c_double),
+                ("rel_res", ctypes.c_double), ("dtau_final", ctypes.c_double),
+                ("n_halvings", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def load_library(path=_LIB_PATH):
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpcfv.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, dp, i, d = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_double
+    cfgp = ctypes.POINTER(Config)
+    lib.pcfv_workspace_bytes.restype = ctypes.c_size_t
+    lib.pcfv_workspace_bytes.argtypes = [cfgp]
+    lib.pcfv_create.restype = i
+    lib.pcfv_create.argtypes = [cfgp, vp, vp, ctypes.POINTER(vp)]
+    lib.pcfv_destroy.restype = None
+    lib.pcfv_destroy.argtypes = [vp]
+    lib.pcfv_get_layout.restype = i
+    lib.pcfv_get_layout.argtypes = [vp, ctypes.POINTER(Layout)]
+    lib.pcfv_set_stream.restype = i
+    lib.pcfv_set_stream.argtypes = [vp, vp]
+    lib.pcfv_residual.restype = i
+    lib.pcfv_residual.argtypes = [vp, vp, vp, dp]
+    lib.pcfv_cost.restype = i
+    lib.pcfv_cost.argtypes = [vp, vp, dp]
+    for name in ("pcfv_jvp", "pcfv_adjoint"):
+        getattr(lib, name).restype = i
+        getattr(lib, name).argtypes = [vp, vp, vp, vp]
+    for name in ("pcfv_project", "pcfv_pack_state", "pcfv_unpack_state"):
+        getattr(lib, name).restype = i
+        getattr(lib, name).argtypes = [vp, vp, vp]
+    lib.pcfv_descend.restype = i
+    lib.pcfv_descend.argtypes = [vp, vp, ctypes.POINTER(DescentOpts), ctypes.POINTER(DescentReport)]
+    for name in ("pcfv_norms", "pcfv_check_state"):
+        getattr(lib, name).restype = i
+        getattr(lib, name).argtypes = [vp, vp, dp]
+    lib.pcfv_time_kernels.restype = i
+    lib.pcfv_time_kernels.argtypes = [vp, vp, i, dp, ctypes.POINTER(i)]
+    lib.pcfv_last_error.restype = ctypes.c_char_p
+    lib.pcfv_last_error.argtypes = [vp]
+    lib.pcfv_host_table.restype = ctypes.c_size_t
+    lib.pcfv_host_table.argtypes = [cfgp, i, dp, ctypes.c_size_t]
+    return lib
+
+
+_lib = load_library()
+
+
+class PcfvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def make_config(Nx, Ny, Nz, Lx=2 * np.pi / 1.14, Lz=2 * np.pi / 2.5, Re=400.0, dt_im=0.25):
+    return Config(float(Lx), float(Lz), float(Re), int(Nx), int(Ny), int(Nz), float(dt_im), 0)
+
+
+def workspace_bytes(cfg):
+    return int(_lib.pcfv_workspace_bytes(ctypes.byref(cfg)))
+
+
+def host_table(cfg, which):
+    """Host-side copy of a setup table (no device needed), as a numpy array."""
+    n = _lib.pcfv_host_table(ctypes.byref(cfg), int(which), None, 0)
+    if n == 0:
+        raise ValueError("invalid configuration or table index")
+    out = np.empty(n, dtype=np.float64)
+    _lib.pcfv_host_table(ctypes.byref(cfg), int(which),
+                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n)
+    return out
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One discretisation (box, Re, grid) on one GPU.  Owns its workspace tensor."""
+
+    def __init__(self, Nx, Ny, Nz, Lx=2 * np.pi / 1.14, Lz=2 * np.pi / 2.5, Re=400.0,
+                 dt_im=0.25, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.cfg = make_config(Nx, Ny, Nz, Lx, Lz, Re, dt_im)
+        nbytes = workspace_bytes(self.cfg)
+        if nbytes == 0:
+            raise PcfvError(EINVAL, "invalid configuration")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = ctypes.c_void_p(self.workspace.data_ptr() + off)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = _lib.pcfv_create(ctypes.byref(self.cfg), ctypes.c_void_p(stream.cuda_stream),
+                              self._ws_ptr, ctypes.byref(h))
+        if st != OK:
+            raise PcfvError(st, "pcfv_create failed")
+        self._h = h
+        lay = Layout()
+        _lib.pcfv_get_layout(self._h, ctypes.byref(lay))
+        self.layout = lay
+        self.shape = (3, lay.nkx, lay.nkz, lay.Ny)
+        self.n_state = lay.n_state
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.pcfv_destroy(h)
+            self._h = None
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, st):
+        if st != OK:
+            raise PcfvError(st, _lib.pcfv_last_error(self._h).decode())
+        return st
+
+    def _field(self, x):
+        t = self.torch
+        if not isinstance(x, t.Tensor):
+            x = t.as_tensor(np.asarray(x, dtype=np.complex128))
+        x = x.to(self.device, t.complex128).contiguous()
+        if tuple(x.shape) != self.shape:
+            raise ValueError(f"field shape {tuple(x.shape)} != {self.shape}")
+        return x
+
+    def empty(self):
+        return self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
+
+    # -- the C ABI -----------------------------------------------------------
+    def residual(self, u, want_cost=False):
+        u = self._field(u)
+        r = self.empty()
+        c = ctypes.c_double(0.0)
+        self._check(_lib.pcfv_residual(self._h, _ptr(u), _ptr(r), ctypes.byref(c) if want_cost else None))
+        return (r, c.value) if want_cost else r
+
+    def cost(self, u):
+        u = self._field(u)
+        c = ctypes.c_double(0.0)
+        self._check(_lib.pcfv_cost(self._h, _ptr(u), ctypes.byref(c)))
+        return c.value
+
+    def jvp(self, u, v):
+        u, v = self._field(u), self._field(v)
+        out = self.empty()
+        self._check(_lib.pcfv_jvp(self._h, _ptr(u), _ptr(v), _ptr(out)))
+        return out
+
+    def adjoint(self, u, w):
+        u, w = self._field(u), self._field(w)
+        out = self.empty()
+        self._check(_lib.pcfv_adjoint(self._h, _ptr(u), _ptr(w), _ptr(out)))
+        return out
+
+    def project(self, g, out=None):
+        g = self._field(g)
+        out = self.empty() if out is None else out
+        self._check(_lib.pcfv_project(self._h, _ptr(g), _ptr(out)))
+        return out
+
+    def descend(self, u, max_steps, dtau, rel_tol=0.0, check_every=None, grow_tol=0.0,
+                max_halvings=0):
+        """Advance u (a contiguous complex128 device tensor) in place; returns
+        (status, report dict)."""
+        if not (u.is_contiguous() and u.dtype == self.torch.complex128 and tuple(u.shape) == self.shape):
+            raise ValueError("u must be a contiguous complex128 device tensor of the context shape")
+        o = DescentOpts(int(max_steps), float(dtau), float(rel_tol),
+                        int(check_every or max(1, max_steps)), float(grow_tol), int(max_halvings))
+        rep = DescentReport()
+        st = _lib.pcfv_descend(self._h, _ptr(u), ctypes.byref(o), ctypes.byref(rep))
+        if st not in (OK, ENOTCONV, ENAN, EDIVERGED):
+            self._check(st)
+        return st, rep.as_dict()
+
+    def norms(self, u):
+        u = self._field(u)
+        out = (ctypes.c_double * 3)()
+        self._check(_lib.pcfv_norms(self._h, _ptr(u), out))
+        return tuple(out)
+
+    def check_state(self, u):
+        u = self._field(u)
+        out = (ctypes.c_double * 3)()
+        self._check(_lib.pcfv_check_state(self._h, _ptr(u), out))
+        return tuple(out)
+
+    def pack(self, u):
+        u = self._field(u)
+        psi = self.torch.empty(self.n_state, dtype=self.torch.float64, device=self.device)
+        self._check(_lib.pcfv_pack_state(self._h, _ptr(u), _ptr(psi)))
+        return psi
+
+    def unpack(self, psi):
+        t = self.torch
+        psi = t.as_tensor(psi).to(self.device, t.float64).contiguous()
+        if psi.numel() != self.n_state:
+            raise ValueError("psi has the wrong length")
+        u = self.empty()
+        self._check(_lib.pcfv_unpack_state(self._h, _ptr(psi), _ptr(u)))
+        return u
+
+    def time_kernels(self, u, nrep=20):
+        u = self._field(u)
+        out = (ctypes.c_double * 8)()
+        n = ctypes.c_int(0)
+        self._check(_lib.pcfv_time_kernels(self._h, _ptr(u), int(nrep), out, ctypes.byref(n)))
+        return list(out)[:n.value]
+
+    def synchronize(self):
+        self.stream.synchronize()

@@ -1,0 +1,150 @@
+"""CPU tests of the C-ABI library: it loads, exports every symbol declared in
+include/pcfv.h, validates configurations, and its host-side setup tables
+(computed without a device) reproduce the oracle's operators when the
+per-mode algorithm of the kernels is replayed on them in numpy."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import Grid
+from oracle.method import Method
+from paper_2306_00165_amd import inputs, pcfv
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pcfv.h")
+
+
+def test_library_exports_every_declared_symbol():
+    text = open(HEADER).read()
+    declared = set(re.findall(r"\b(pcfv_[a-z_]+)\s*\(", text))
+    assert declared == set(pcfv.EXPORTS)
+    lib = ctypes.CDLL(pcfv._LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("bad", [dict(Nx=4), dict(Ny=7), dict(Re=-1.0), dict(dt_im=0.0), dict(Nz=1000)])
+def test_invalid_configs_are_rejected(bad):
+    kw = dict(Nx=16, Ny=25, Nz=16, Re=400.0, dt_im=0.25)
+    kw.update(bad)
+    cfg = pcfv.make_config(kw["Nx"], kw["Ny"], kw["Nz"], Re=kw["Re"], dt_im=kw["dt_im"])
+    assert pcfv.workspace_bytes(cfg) == 0
+    h = ctypes.c_void_p()
+    assert pcfv._lib.pcfv_create(ctypes.byref(cfg), None, None, ctypes.byref(h)) == pcfv.EINVAL
+
+
+def _tables(dims, **kw):
+    cfg = pcfv.make_config(*dims, **kw)
+    N = dims[1]
+    t = {"mats": pcfv.host_table(cfg, 0).reshape(20, N, N)}
+    for name, idx, shape in [("minfo", 1, (-1, 8)), ("dH", 2, (-1, N)), ("dP", 3, (-1, N)),
+                             ("dproj", 4, (-1, N)), ("Vk", 5, (-1, 4, N)), ("DVk", 6, (-1, 4, N)),
+                             ("Ainv", 7, (-1, 4, 4)), ("mu", 8, (-1,))]:
+        t[name] = pcfv.host_table(cfg, idx).reshape(shape)
+    return t
+
+
+def _mat(t, slot, nout, nin):
+    return t["mats"][slot][:nin, :nout].T
+
+
+@pytest.mark.parametrize("dims", [(16, 25, 16), (12, 17, 9), (32, 33, 32)])
+def test_fixed_operators_match_oracle(dims):
+    g = Grid(*dims)
+    m = Method(g)
+    t = _tables(dims)
+    N = g.N
+    np.testing.assert_allclose(_mat(t, 4, N, N), m.D, atol=0)
+    np.testing.assert_allclose(_mat(t, 7, N, N), m.G, atol=1e-15)
+    np.testing.assert_allclose(_mat(t, 0, N, N), m.T.C, atol=2e-14)  # oracle evaluates cos of large unreduced angles
+    np.testing.assert_allclose(_mat(t, 2, N, N), m.T.Cinv, atol=1e-14)
+    np.testing.assert_allclose(_mat(t, 8, N, N), m.Ginv, atol=1e-12 * np.abs(m.Ginv).max())
+
+
+@pytest.mark.parametrize("dims", [(16, 25, 16), (32, 33, 32)])
+def test_tau_helmholtz_eigenbasis_solves_the_tau_system(dims):
+    """x = Pl diag(1/(s - c mu)) Pr f solves [(s - c D^2) x]_n = f_n (n <= N-3),
+    x(+-1) = 0, checked against a dense solve."""
+    N = dims[1]
+    M = N - 2
+    t = _tables(dims)
+    D = _mat(t, 4, N, N)
+    Pl, Pr = _mat(t, 9, N, M), _mat(t, 10, M, M)
+    rng = np.random.default_rng(1)
+    for s, c in [(4.0, 1 / 400), (4.0 + 7.3 / 400, 1 / 400), (0.37, 1.0), (12.0, 1.0)]:
+        f = rng.standard_normal(M) * np.exp(-0.2 * np.arange(M))
+        x = Pl @ ((Pr @ f) / (s - c * t["mu"]))
+        A = np.zeros((N, N))
+        A[:M] = (s * np.eye(N) - c * D @ D)[:M]
+        A[M] = 1.0
+        A[M + 1] = (-1.0) ** np.arange(N)
+        want = np.linalg.solve(A, np.concatenate([f, [0, 0]]))
+        np.testing.assert_allclose(x, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("dims", [(16, 25, 16), (32, 33, 32)])
+def test_influence_matrix_replay_matches_dense_tau_solve(dims):
+    """Replaying the kernel's influence-matrix algorithm on the library tables
+    reproduces the oracle's dense Chebyshev-tau Stokes solve, and its
+    transpose reproduces the oracle's transposed solve."""
+    g = Grid(*dims)
+    m = Method(g)
+    t = _tables(dims)
+    N, M = g.N, g.N - 2
+    D = _mat(t, 4, N, N)
+    Pl, Pr = _mat(t, 9, N, M), _mat(t, 10, M, M)
+    F = inputs.random_field(*dims, energy=1.0, seed=5)
+    F = F + 0.3 * np.roll(F, 1, axis=0)
+    ref = m.S.solve(F)
+    for (ikx, kz) in g.modes():
+        mm = ikx * g.nkz + kz
+        if mm == 0:
+            continue
+        a, b, k2, ik2, sig = t["minfo"][mm][:5]
+        Fx, Fy, Fz = F[:, ikx, kz]
+
+        def hs(f, d):
+            return Pl @ (d[:M] * (Pr @ f[:M]))
+
+        Fh, Fe = 1j * a * Fx + 1j * b * Fz, 1j * b * Fx - 1j * a * Fz
+        p0 = hs(-(D @ Fy + Fh), t["dP"][mm])
+        v0 = hs(Fy - D @ p0, t["dH"][mm])
+        Dv0 = D @ v0
+        e = np.array([Dv0.sum(), (Dv0 * (-1.0) ** np.arange(N)).sum(),
+                      sig * v0[N - 2] + 2 * (N - 1) * p0[N - 1] - Fy[N - 2], sig * v0[N - 1] - Fy[N - 1]])
+        c = -t["Ainv"][mm] @ e
+        v = v0 + t["Vk"][mm].T @ c
+        Dv = Dv0 + t["DVk"][mm].T @ c
+        eta = hs(Fe, t["dH"][mm])
+        out = np.array([ik2 * (1j * a * Dv - 1j * b * eta), v, ik2 * (1j * b * Dv + 1j * a * eta)])
+        np.testing.assert_allclose(out, ref[:, ikx, kz], rtol=0, atol=1e-14 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("dims", [(16, 25, 16), (12, 17, 9)])
+def test_projection_tables_replay_matches_oracle_projection(dims):
+    g = Grid(*dims)
+    m = Method(g)
+    t = _tables(dims)
+    N = g.N
+    D, G = _mat(t, 4, N, N), _mat(t, 7, N, N)
+    PvL, PiD = _mat(t, 17, N, N - 4), _mat(t, 19, N, N)
+    X = inputs.random_field(*dims, energy=1.0, seed=6)
+    X = X + 0.5 * np.roll(X, 1, axis=0)
+    ref = m.project(X)
+    for (ikx, kz) in g.modes():
+        mm = ikx * g.nkz + kz
+        gx, gy, gz = X[:, ikx, kz]
+        if mm == 0:
+            out = np.array([PiD @ gx, 0 * gy, PiD @ gz])
+        else:
+            a, b, k2, ik2 = t["minfo"][mm][:4]
+            gh, ge = 1j * a * gx + 1j * b * gz, 1j * b * gx - 1j * a * gz
+            bv = G @ gy - ik2 * (D.T @ (G @ gh))
+            v = PvL @ (t["dproj"][mm][:N - 4] * (PvL.T @ bv))
+            eta = PiD @ ge
+            Dv = D @ v
+            out = np.array([ik2 * (1j * a * Dv - 1j * b * eta), v, ik2 * (1j * b * Dv + 1j * a * eta)])
+        np.testing.assert_allclose(out, ref[:, ikx, kz], rtol=0, atol=1e-13 * np.abs(X).max())
