@@ -1,0 +1,197 @@
+"""Benchmark: FP64 adjoint-descent steps per second at 48 x 49 x 48 on one GPU.
+
+Workload (the steps/s metric): plane Couette flow, Re = 400, Lx = 2 pi/1.14,
+Lz = 2 pi/2.5, Nx x Ny x Nz = 48 x 49 x 48, Delta t = 0.25 inside r(u),
+forward-Euler dtau = 0.012 (below this grid's stability limit of ~0.014),
+one seeded initial guess with a k^(-5/3) spectrum, energy 0.03, seed 3.
+A step is the whole hot path: residual r(u), cost, transposed Stokes solve,
+adjoint products, J* r, projection and update.
+
+Prints one JSON line.  With --gpus > 1 it exits with a message: this build
+runs on one GPU.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("descent steps/s at 48x49x48; wall time to ‖r‖/‖u‖<1e-10, "
+          "FP64 plain vs chosen")
+GRID = (48, 49, 48)
+DTAU = 0.012
+SEED, ENERGY = 3, 0.03
+PEAK_FP64 = 78.6          # TFLOP/s, MI355X FP64 vector (the kernels do not use MFMA)
+PEAK_HBM = 8000.0         # GB/s
+KERNELS = ["synth", "plane_fwd", "mode_res", "plane_adj", "mode_grad"]
+
+
+def kernel_model(Nx, Ny, Nz):
+    """Algorithmic FLOPs and bytes per launch of each kernel (one launch
+    processes all Ny planes or all Fourier modes of one field set).
+
+    F1 = bytes of one complex scalar field of Ny x modes values.
+    Transforms are priced at 2.5 n log2 n FLOPs per real 2D FFT of n = Nx Nz
+    points; per-mode work is priced as complex-vector x real-matrix products
+    at 4 Ny^2 FLOPs each (the count of such products in each kernel)."""
+    import math
+    Kx, Kz = Nx // 3 - 1, Nz // 3 - 1
+    nm = (2 * Kx + 1) * (Kz + 1)
+    F1 = Ny * nm * 16
+    n = Nx * Nz
+    fft = 2.5 * n * math.log2(n)
+    mv = 4.0 * Ny * Ny
+    return {
+        "synth": (6 * mv * nm, 9 * F1),
+        "plane_fwd": (Ny * (15 * fft + 18 * n), 9 * F1),
+        "mode_res": (34 * mv * nm, 12 * F1),
+        "plane_adj": (Ny * (27 * fft + 27 * n), 15 * F1),
+        "mode_grad": (21 * mv * nm, 21 * F1),
+    }
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2306_00165_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_48x49x48.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    k = d.get("per_launch_bytes", {}).get(kernel)
+    return None if k is None else float(k)
+
+
+def cpu_baseline(seconds):
+    """Time the CPU oracle on a bounded sample of the same workload, in a child
+    process with single-threaded BLAS/FFT (started before the GPU is touched)."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                          "--cpu-seconds", str(seconds)], env=env, capture_output=True, text=True)
+    if res.returncode != 0:
+        return {"value": None, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                "sample": "failed: " + res.stderr[-300:]}
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
+def run_cpu_baseline_only(seconds):
+    from oracle import Grid
+    from oracle.method import Method
+    from paper_2306_00165_amd import inputs
+    g = Grid(*GRID)
+    m = Method(g)
+    u = inputs.metric_guess()
+    t0 = time.perf_counter()
+    u, _ = m.descent_step(u, DTAU)          # includes the one-off projection setup
+    setup = time.perf_counter() - t0
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        u, _ = m.descent_step(u, DTAU)
+        n += 1
+    dt = time.perf_counter() - t0
+    print(json.dumps({"value": n / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                      "sample": f"{n} descent steps of the 48x49x48 workload timed over {dt:.1f} s "
+                                f"after one untimed first step ({setup:.1f} s incl. setup); "
+                                "NumPy/SciPy FP64, single-threaded BLAS and FFT"}))
+
+
+def run_copy_calibration():
+    """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    nbytes = 256 << 20
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": nbytes, "launches": 5}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-only", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.cpu_baseline_only:
+        run_cpu_baseline_only(args.cpu_seconds)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU "
+              "sharding is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        run_copy_calibration()
+        return
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+
+    import torch
+    from paper_2306_00165_amd import inputs
+    from paper_2306_00165_amd.pcfv import Context
+
+    c = Context(*GRID, device="cuda:0")
+    u = torch.as_tensor(inputs.metric_guess()).to("cuda:0").contiguous()
+    if args.warmup > 0:
+        c.descend(u, max_steps=args.warmup, dtau=DTAU, check_every=args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rep = c.descend(u, max_steps=args.steps, dtau=DTAU, check_every=max(1, args.steps))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if st != 0:
+        raise RuntimeError(f"descent returned status {st}: {rep}")
+    steps_per_s = args.steps / dt
+
+    ms = c.time_kernels(u, nrep=50)
+    model = kernel_model(*GRID)
+    step_kernels = KERNELS[1:]
+    dom = max(step_kernels, key=lambda k: ms[KERNELS.index(k)])
+    t_dom = ms[KERNELS.index(dom)] * 1e-3
+    flops, nbytes = model[dom]
+    achieved = flops / t_dom / 1e12
+    roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP64,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 5),
+                "traffic": measured_traffic(dom),
+                "algorithmic_bytes": nbytes, "algorithmic_flops": flops,
+                "avg_launch_ms": round(ms[KERNELS.index(dom)], 5),
+                "hbm_GBps_algorithmic": round(nbytes / t_dom / 1e9, 2)}
+    out = {
+        "metric": METRIC, "value": round(steps_per_s, 2), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "PCF adjoint descent, FP64, 48x49x48, Re=400, Lx=2pi/1.14, "
+                               "Lz=2pi/2.5, dt_im=0.25, dtau=0.012, one k^-5/3 guess E=0.03 seed 3",
+                   "grid": list(GRID), "Re": 400.0, "dtau": DTAU, "batch": 1},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_ms": {k: round(v, 5) for k, v in zip(KERNELS, ms)},
+        "final_rel_res": rep["rel_res"],
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

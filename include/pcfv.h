@@ -181,6 +181,8 @@ pcfv_status pcfv_check_state(pcfv_ctx* ctx, const double* u, double defects_host
 pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* ms_out,
                               int* n_out);
 
+/* Message of the last failure on ctx; with ctx = NULL, the reason of the last
+ * failed pcfv_create on the calling thread.  Valid until the next call. */
 const char* pcfv_last_error(const pcfv_ctx* ctx);
 
 /* Host-side copy of a constant table for cfg, computed without a device (for

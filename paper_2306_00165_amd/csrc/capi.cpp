@@ -129,6 +129,8 @@ struct pcfv_ctx {
 
 namespace {
 
+thread_local std::string g_create_err;  // reason of the last failed pcfv_create on this thread
+
 pcfv_status fail(pcfv_ctx* c, pcfv_status s, const std::string& msg) {
     if (c) c->err = msg;
     return s;
@@ -205,17 +207,31 @@ size_t pcfv_workspace_bytes(const pcfv_config* cfg) {
 }
 
 pcfv_status pcfv_create(const pcfv_config* cfg, void* hip_stream, void* workspace, pcfv_ctx** out) {
-    if (!out) return PCFV_EINVAL;
+    g_create_err.clear();
+    if (!out) {
+        g_create_err = "out is NULL";
+        return PCFV_EINVAL;
+    }
     *out = nullptr;
     std::string e;
-    if (!validate(cfg, e)) return PCFV_EINVAL;
-    if (!workspace) return PCFV_ENOMEM;
-    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return PCFV_EINVAL;
+    if (!validate(cfg, e)) {
+        g_create_err = e;
+        return PCFV_EINVAL;
+    }
+    if (!workspace) {
+        g_create_err = "workspace is NULL";
+        return PCFV_ENOMEM;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) {
+        g_create_err = "workspace is not 256-byte aligned";
+        return PCFV_EINVAL;
+    }
     pcfv_ctx* ctx = new pcfv_ctx();
     ctx->cfg = *cfg;
     ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
     ctx->ws = reinterpret_cast<char*>(workspace);
     if (!build_tables(cfg->Lx, cfg->Lz, cfg->Re, cfg->Nx, cfg->Ny, cfg->Nz, cfg->dt_im, ctx->t, e)) {
+        g_create_err = "table construction failed: " + e;
         delete ctx;
         return PCFV_EINVAL;
     }
@@ -267,6 +283,7 @@ pcfv_status pcfv_create(const pcfv_config* cfg, void* hip_stream, void* workspac
                                        ctx->stream);
         if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
         if (he != hipSuccess) {
+            g_create_err = std::string("copying tables to the workspace: ") + hipGetErrorString(he);
             delete ctx;
             return PCFV_EDEVICE;
         }
@@ -478,7 +495,7 @@ pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* 
     return PCFV_OK;
 }
 
-const char* pcfv_last_error(const pcfv_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+const char* pcfv_last_error(const pcfv_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
 size_t pcfv_host_table(const pcfv_config* cfg, int which, double* out, size_t cap) {
     std::string e;

@@ -50,6 +50,14 @@ __device__ __forceinline__ double wmax(double v) {
     return v;
 }
 
+// Work groups are dispatched to the 8 XCDs of the chip round-robin.  Launchers
+// pad the grid to a multiple of 8 and kernels map their work-group index w to
+// the logical work item (w % 8) * (nwg / 8) + w / 8, so each XCD processes one
+// contiguous range of work items and neighbouring items, which share cache
+// lines of the [field][j][mode] arrays, share one L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_item(int w, int nwg) { return (w % NXCD) * (nwg / NXCD) + w / NXCD; }
+
 struct MS {
     double a, b, k2, ik2, sig, wgt;
 };
@@ -395,7 +403,8 @@ __device__ void project0(const KP& p, const double2* gx, const double2* gz, doub
 __global__ __launch_bounds__(MODE_THREADS) void k_synth(KP p, const double2* __restrict__ u,
                                                         double2* __restrict__ Y) {
     extern __shared__ double2 sm[];
-    const int m = blockIdx.x, N = p.N, nm = p.nm, t = threadIdx.x;
+    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
+    if (m >= nm) return;
     double2* V = sm;
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MODE_THREADS) V[i * N + n] = u[((size_t)i * nm + m) * N + n];
@@ -417,7 +426,9 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
     constexpr int NG1 = (MODE == PLANE_ADJ) ? 3 : 0;  // adjoint fields: single outputs
     constexpr int NXF = 3 * NG3 + NG1;
     constexpr int NZF = (MODE == PLANE_ADJ) ? 9 : 3;  // after the forward z stage
-    const int s = blockIdx.x, j = blockIdx.y;
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= p.NS * p.N) return;
+    const int j = item / p.NS, s = item - j * p.NS;   // the slabs of a plane run on one XCD
     const int N = p.N, Nx = p.Nx, Nz = p.Nz, nkx = p.nkx, nkz = p.nkz, nm = p.nm, XS = p.XS;
     const int Kx = p.Kx;
     const int x0 = s * XS, tid = threadIdx.x;
@@ -440,15 +451,18 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
             const double2* Vp = src + ((size_t)comp * N + j) * nm + kz;
             const double2* Wp = src + ((size_t)(3 + comp) * N + j) * nm + kz;
             double2 aV = c2(0, 0), aA = c2(0, 0), aW = c2(0, 0);
+            const int step = x % Nx;
+            int idx = 0;                                   // (kx * x) mod Nx, kx = 0, 1, ..
             for (int ikx = 0; ikx < nkx; ++ikx) {
+                if (ikx == Kx + 1) idx = (Nx - (Kx * x) % Nx) % Nx;   // kx = -Kx
                 const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
-                int idx = (kx * x) % Nx;
-                if (idx < 0) idx += Nx;
                 const double2 tw = twx[idx];
                 const double2 vt = cmul(Vp[(size_t)ikx * nkz], tw);
                 aV = cadd(aV, vt);
                 aA = cadd(aA, imul(p.alpha * kx, vt));
                 aW = cadd(aW, cmul(Wp[(size_t)ikx * nkz], tw));
+                idx += step;
+                if (idx >= Nx) idx -= Nx;
             }
             xb[(3 * g) * per + rem] = aV;
             xb[(3 * g + 1) * per + rem] = aA;
@@ -457,11 +471,13 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
             const int comp = g - NG3;
             const double2* Ap = Y2 + ((size_t)comp * N + j) * nm + kz;
             double2 acc = c2(0, 0);
+            const int step = x % Nx;
+            int idx = 0;
             for (int ikx = 0; ikx < nkx; ++ikx) {
-                const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
-                int idx = (kx * x) % Nx;
-                if (idx < 0) idx += Nx;
+                if (ikx == Kx + 1) idx = (Nx - (Kx * x) % Nx) % Nx;
                 acc = cadd(acc, cmul(Ap[(size_t)ikx * nkz], twx[idx]));
+                idx += step;
+                if (idx >= Nx) idx -= Nx;
             }
             xb[(3 * NG3 + comp) * per + rem] = acc;
         }
@@ -479,8 +495,10 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
             const double2* cA = xb + (3 * g + 1) * per + xl * nkz;
             const double2* cW = xb + (3 * g + 2) * per + xl * nkz;
             double sV = 0, sZ = 0, sA = 0, sW = 0;
+            int idx = 0;                                   // (kz * z) mod Nz
             for (int kz = 1; kz < nkz; ++kz) {
-                const int idx = (kz * z) % Nz;
+                idx += z;
+                if (idx >= Nz) idx -= Nz;
                 const double2 tw = twz[idx];
                 const double2 t = cmul(cV[kz], tw);
                 sV += t.x;
@@ -514,7 +532,12 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
             for (int i = 0; i < 3; ++i) {
                 const double2* cc = xb + (3 * NG3 + i) * per + xl * nkz;
                 double sr = 0;
-                for (int kz = 1; kz < nkz; ++kz) sr += cmul(cc[kz], twz[(kz * z) % Nz]).x;
+                int idx = 0;
+                for (int kz = 1; kz < nkz; ++kz) {
+                    idx += z;
+                    if (idx >= Nz) idx -= Nz;
+                    sr += cmul(cc[kz], twz[idx]).x;
+                }
                 at[i] = cc[0].x + 2.0 * sr;
             }
 #pragma unroll
@@ -536,8 +559,8 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
         if (MODE != PLANE_ADJ) {
             const double* q = pb + o * pz + xl * Nz;
             double ar = 0, ai = 0;
-            for (int z = 0; z < Nz; ++z) {
-                const double2 tw = twz[(kz * z) % Nz];
+            for (int z = 0, idx = 0; z < Nz; ++z, idx = (idx + kz >= Nz) ? idx + kz - Nz : idx + kz) {
+                const double2 tw = twz[idx];
                 ar += q[z] * tw.x;
                 ai -= q[z] * tw.y;
             }
@@ -548,8 +571,8 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
                 const double* q1 = pb + (9 + i) * pz + xl * Nz;
                 const double* q2 = pb + (3 * i + 2) * pz + xl * Nz;
                 double ar = 0, ai = 0, br = 0, bi = 0;
-                for (int z = 0; z < Nz; ++z) {
-                    const double2 tw = twz[(kz * z) % Nz];
+                for (int z = 0, idx = 0; z < Nz; ++z, idx = (idx + kz >= Nz) ? idx + kz - Nz : idx + kz) {
+                    const double2 tw = twz[idx];
                     ar += q1[z] * tw.x;
                     ai -= q1[z] * tw.y;
                     br += q2[z] * tw.x;
@@ -560,8 +583,8 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
             } else {  // P_{i,x} (kind 1) or P_{i,y} (kind 2)
                 const double* q = pb + (3 * i + (kind - 1)) * pz + xl * Nz;
                 double ar = 0, ai = 0;
-                for (int z = 0; z < Nz; ++z) {
-                    const double2 tw = twz[(kz * z) % Nz];
+                for (int z = 0, idx = 0; z < Nz; ++z, idx = (idx + kz >= Nz) ? idx + kz - Nz : idx + kz) {
+                    const double2 tw = twz[idx];
                     ar += q[z] * tw.x;
                     ai -= q[z] * tw.y;
                 }
@@ -576,12 +599,12 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
     for (int it = tid; it < NOUT * nm; it += PLANE_THREADS) {
         const int o = it / nm, mm = it - o * nm, ikx = mm / nkz, kz = mm - ikx * nkz;
         const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
+        const int kstep = ((kx % Nx) + Nx) % Nx;            // kx mod Nx
+        const int idx0 = (int)(((long long)kstep * x0) % Nx);  // (kx * x0) mod Nx
         double2 res;
         if (MODE != PLANE_ADJ) {
             double ar = 0, ai = 0;
-            for (int xl = 0; xl < XS; ++xl) {
-                int idx = (kx * (x0 + xl)) % Nx;
-                if (idx < 0) idx += Nx;
+            for (int xl = 0, idx = idx0; xl < XS; ++xl, idx = (idx + kstep >= Nx) ? idx + kstep - Nx : idx + kstep) {
                 const double2 tw = twx[idx], v = xb[o * per + xl * nkz + kz];
                 ar += v.x * tw.x + v.y * tw.y;
                 ai += v.y * tw.x - v.x * tw.y;
@@ -589,9 +612,7 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
             res = c2(ar * invNx, ai * invNx);
         } else if (o < 3) {  // X_i = F(A_i) - i a F(B_i)
             double ar = 0, ai = 0, br = 0, bi = 0;
-            for (int xl = 0; xl < XS; ++xl) {
-                int idx = (kx * (x0 + xl)) % Nx;
-                if (idx < 0) idx += Nx;
+            for (int xl = 0, idx = idx0; xl < XS; ++xl, idx = (idx + kstep >= Nx) ? idx + kstep - Nx : idx + kstep) {
                 const double2 tw = twx[idx];
                 const double2 va = xb[(3 * o) * per + xl * nkz + kz];
                 const double2 vb = xb[(3 * o + 1) * per + xl * nkz + kz];
@@ -604,9 +625,7 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
         } else {  // Y_i = F(C_i)
             const int i = o - 3;
             double ar = 0, ai = 0;
-            for (int xl = 0; xl < XS; ++xl) {
-                int idx = (kx * (x0 + xl)) % Nx;
-                if (idx < 0) idx += Nx;
+            for (int xl = 0, idx = idx0; xl < XS; ++xl, idx = (idx + kstep >= Nx) ? idx + kstep - Nx : idx + kstep) {
                 const double2 tw = twx[idx], v = xb[(3 * i + 2) * per + xl * nkz + kz];
                 ar += v.x * tw.x + v.y * tw.y;
                 ai += v.y * tw.x - v.x * tw.y;
@@ -622,7 +641,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_res(
     double2* __restrict__ r, double* __restrict__ cost_part, double2* __restrict__ a,
     double2* __restrict__ Atil) {
     extern __shared__ double2 sm[];
-    const int m = blockIdx.x, N = p.N, nm = p.nm, t = threadIdx.x;
+    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
+    if (m >= nm) return;
     auto vec = [&](int k) { return sm + (size_t)k * N; };
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
@@ -696,7 +716,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags,
                                                             double dtau, double2* __restrict__ uo,
                                                             double2* __restrict__ Y) {
     extern __shared__ double2 sm[];
-    const int m = blockIdx.x, N = p.N, nm = p.nm, t = threadIdx.x;
+    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
+    if (m >= nm) return;
     auto vec = [&](int k) { return sm + (size_t)k * N; };
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
@@ -765,7 +786,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags,
 __global__ __launch_bounds__(MODE_THREADS) void k_project(KP p, const double2* __restrict__ g,
                                                           double2* __restrict__ out) {
     extern __shared__ double2 sm[];
-    const int m = blockIdx.x, N = p.N, nm = p.nm, t = threadIdx.x;
+    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
+    if (m >= nm) return;
     auto vec = [&](int k) { return sm + (size_t)k * N; };
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = g[((size_t)i * nm + m) * N + n];
@@ -806,7 +828,8 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
 __global__ __launch_bounds__(MODE_THREADS) void k_norms(KP p, const double2* __restrict__ u,
                                                         double* __restrict__ part) {
     extern __shared__ double2 sm[];
-    const int m = blockIdx.x, N = p.N, nm = p.nm, t = threadIdx.x;
+    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
+    if (m >= nm) return;
     auto vec = [&](int k) { return sm + (size_t)k * N; };
     const MS c = mscal(p, m);
     for (int i = 0; i < 3; ++i)
@@ -855,7 +878,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_norms(KP p, const double2* __r
 __global__ __launch_bounds__(MODE_THREADS) void k_check(KP p, const double2* __restrict__ u,
                                                         double* __restrict__ part) {
     extern __shared__ double2 sm[];
-    const int m = blockIdx.x, N = p.N, nm = p.nm, t = threadIdx.x;
+    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
+    if (m >= nm) return;
     auto vec = [&](int k) { return sm + (size_t)k * N; };
     const MS c = mscal(p, m);
     for (int i = 0; i < 3; ++i)
@@ -897,7 +921,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_check(KP p, const double2* __r
 
 __global__ __launch_bounds__(MODE_THREADS) void k_pack(KP p, const double2* __restrict__ u,
                                                        double* __restrict__ psi) {
-    const int m = blockIdx.x, N = p.N, nm = p.nm, t = threadIdx.x;
+    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
+    if (m >= nm) return;
     const int idx = p.indep[m];
     if (idx < 0) return;
     if (m == 0) {
@@ -938,7 +963,8 @@ __device__ double2 par_sum(const double2* x, int lim, int par, bool sq) {
 __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __restrict__ psi,
                                                          double2* __restrict__ u) {
     extern __shared__ double2 sm[];
-    const int m = blockIdx.x, N = p.N, nm = p.nm, t = threadIdx.x;
+    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
+    if (m >= nm) return;
     const int idx = p.indep[m];
     if (idx < 0) return;
     auto vec = [&](int k) { return sm + (size_t)k * N; };
@@ -1026,14 +1052,16 @@ size_t plane_lds_bytes(const KP& p, int mode) {
 
 size_t mode_lds_bytes(const KP& p) { return (size_t)MODE_VECS * p.N * 16; }
 
+static dim3 mode_grid(const KP& p) { return dim3((unsigned)((p.nm + NXCD - 1) / NXCD * NXCD)); }
+
 hipError_t launch_synth(const KP& p, hipStream_t s, const double2* u, double2* Y) {
-    hipLaunchKernelGGL(k_synth, dim3(p.nm), dim3(MODE_THREADS), 9 * p.N * 16, s, p, u, Y);
+    hipLaunchKernelGGL(k_synth, mode_grid(p), dim3(MODE_THREADS), 9 * p.N * 16, s, p, u, Y);
     return hipGetLastError();
 }
 
 hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const double2* Y1, const double2* Y2,
                         double2* out) {
-    const dim3 grid(p.NS, p.N), block(PLANE_THREADS);
+    const dim3 grid((unsigned)((p.NS * p.N + NXCD - 1) / NXCD * NXCD)), block(PLANE_THREADS);
     const size_t lds = plane_lds_bytes(p, mode);
     if (mode == PLANE_FWD)
         hipLaunchKernelGGL(k_plane<PLANE_FWD>, grid, block, lds, s, p, Y1, Y2, out);
@@ -1047,20 +1075,20 @@ hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const double2* Y1,
 hipError_t launch_mode_res(const KP& p, hipStream_t s, int flags, const double2* P3,
                            const double2* u, double2* r, double* cost_part, double2* a,
                            double2* Atil) {
-    hipLaunchKernelGGL(k_mode_res, dim3(p.nm), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, flags,
+    hipLaunchKernelGGL(k_mode_res, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, flags,
                        P3, u, r, cost_part, a, Atil);
     return hipGetLastError();
 }
 
 hipError_t launch_mode_grad(const KP& p, hipStream_t s, int flags, const double2* P6,
                             const double2* a, double dtau, double2* u_or_out, double2* Y) {
-    hipLaunchKernelGGL(k_mode_grad, dim3(p.nm), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, flags,
+    hipLaunchKernelGGL(k_mode_grad, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, flags,
                        P6, a, dtau, u_or_out, Y);
     return hipGetLastError();
 }
 
 hipError_t launch_project(const KP& p, hipStream_t s, const double2* g, double2* out) {
-    hipLaunchKernelGGL(k_project, dim3(p.nm), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, g, out);
+    hipLaunchKernelGGL(k_project, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, g, out);
     return hipGetLastError();
 }
 
@@ -1071,22 +1099,22 @@ hipError_t launch_reduce(hipStream_t s, const double* part, int n, int stride, i
 }
 
 hipError_t launch_norms(const KP& p, hipStream_t s, const double2* u, double* part) {
-    hipLaunchKernelGGL(k_norms, dim3(p.nm), dim3(MODE_THREADS), 14 * p.N * 16, s, p, u, part);
+    hipLaunchKernelGGL(k_norms, mode_grid(p), dim3(MODE_THREADS), 14 * p.N * 16, s, p, u, part);
     return hipGetLastError();
 }
 
 hipError_t launch_check(const KP& p, hipStream_t s, const double2* u, double* part) {
-    hipLaunchKernelGGL(k_check, dim3(p.nm), dim3(MODE_THREADS), 4 * p.N * 16, s, p, u, part);
+    hipLaunchKernelGGL(k_check, mode_grid(p), dim3(MODE_THREADS), 4 * p.N * 16, s, p, u, part);
     return hipGetLastError();
 }
 
 hipError_t launch_pack(const KP& p, hipStream_t s, const double2* u, double* psi) {
-    hipLaunchKernelGGL(k_pack, dim3(p.nm), dim3(MODE_THREADS), 0, s, p, u, psi);
+    hipLaunchKernelGGL(k_pack, mode_grid(p), dim3(MODE_THREADS), 0, s, p, u, psi);
     return hipGetLastError();
 }
 
 hipError_t launch_unpack(const KP& p, hipStream_t s, const double* psi, double2* u) {
-    hipLaunchKernelGGL(k_unpack, dim3(p.nm), dim3(MODE_THREADS), 3 * p.N * 16, s, p, psi, u);
+    hipLaunchKernelGGL(k_unpack, mode_grid(p), dim3(MODE_THREADS), 3 * p.N * 16, s, p, psi, u);
     return hipGetLastError();
 }
 

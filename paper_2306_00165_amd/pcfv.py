@@ -13,6 +13,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch must be loaded first: its HIP runtime (SONAME libamdhip64.so.7) then
+# satisfies libpcfv's dependency, so both share one runtime and one device
+# context.  Loading libpcfv first would pull in a second HIP runtime.
+import torch  # noqa: F401
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libpcfv.so")
 
@@ -132,7 +136,6 @@ class Context:
 
     def __init__(self, Nx, Ny, Nz, Lx=2 * np.pi / 1.14, Lz=2 * np.pi / 2.5, Re=400.0,
                  dt_im=0.25, device="cuda:0", stream=None):
-        import torch
         self.torch = torch
         self.device = torch.device(device)
         self.cfg = make_config(Nx, Ny, Nz, Lx, Lz, Re, dt_im)
@@ -149,7 +152,7 @@ class Context:
         st = _lib.pcfv_create(ctypes.byref(self.cfg), ctypes.c_void_p(stream.cuda_stream),
                               self._ws_ptr, ctypes.byref(h))
         if st != OK:
-            raise PcfvError(st, "pcfv_create failed")
+            raise PcfvError(st, "pcfv_create failed: " + _lib.pcfv_last_error(None).decode())
         self._h = h
         lay = Layout()
         _lib.pcfv_get_layout(self._h, ctypes.byref(lay))
