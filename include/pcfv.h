@@ -16,10 +16,12 @@
  *
  * Spectral field layout (every u, r, v, w, g argument below):
  *   device memory, complex128 stored as interleaved (re, im) doubles,
- *   index [c][ikx][kz][n] with c = 0,1,2 the velocity component (x, y, z),
+ *   index [b][c][ikx][kz][n] with b = 0..batch-1 the guess (all guesses of a
+ *   context share the discretisation and are advanced together),
+ *   c = 0,1,2 the velocity component (x, y, z),
  *   ikx = 0..2Kx in FFT order (kx = 0,1,..,Kx,-Kx,..,-1), kz = 0..Kz and
  *   n = 0..Ny-1 the Chebyshev index (fastest).  Length 3*(2Kx+1)*(Kz+1)*Ny
- *   complex values.  On the kz = 0 plane both signs of kx are stored and
+ *   complex values per guess.  On the kz = 0 plane both signs of kx are stored and
  *   must be complex conjugates; the (0,0) mode is real.
  *
  * Operators (exact discrete definitions, all in FP64):
@@ -74,19 +76,22 @@ typedef enum {
 } pcfv_status;
 
 /* Problem definition (Sec. 3.1 and Sec. 5.1).  6 <= Nx, Nz <= 512 (any
- * integers), 9 <= Ny <= 128.  precision must be 0 (FP64). */
+ * integers), 9 <= Ny <= 128.  precision must be 0 (FP64).  batch: number of
+ * guesses held and advanced together (0 or 1: one guess; at most 4096). */
 typedef struct {
     double Lx, Lz, Re;
     int Nx, Ny, Nz;
     double dt_im;        /* Delta t of the Stokes step inside r(u); the paper uses 0.25 */
     int precision;       /* 0 = FP64 */
+    int batch;
 } pcfv_config;
 
 typedef struct {
     int Kx, Kz, Ny, nkx, nkz;
     long long n_modes;   /* nkx * nkz                                   */
     long long n_complex; /* 3 * n_modes * Ny: complex values per field  */
-    long long n_state;   /* length of the minimal real state vector     */
+    long long n_state;   /* length of the minimal real state vector of one guess */
+    int batch;
 } pcfv_layout;
 
 /* Bytes of device workspace pcfv_create needs for this configuration;
@@ -111,10 +116,11 @@ pcfv_status pcfv_set_stream(pcfv_ctx* ctx, void* hip_stream);
 
 /* Residual r(u) (Sec. 4 steps (1)-(2), Sec. 3.2 residual).  u admissible.
  * r may be NULL (then only the cost is formed).  cost_host, if non-NULL,
- * receives J^2 = <r,r>_W and the call synchronises. */
+ * receives J^2 = <r,r>_W of each guess (batch values) and the call
+ * synchronises. */
 pcfv_status pcfv_residual(pcfv_ctx* ctx, const double* u, double* r, double* cost_host);
 
-/* J^2 = <r(u), r(u)>_W (Sec. 2 cost function); synchronises. */
+/* J^2 = <r(u), r(u)>_W (Sec. 2 cost function) per guess; synchronises. */
 pcfv_status pcfv_cost(pcfv_ctx* ctx, const double* u, double* cost_host);
 
 /* Jv = J(u) v, the directional derivative of r at u along v (Sec. 2). */
@@ -148,19 +154,21 @@ typedef struct {
     int n_halvings;
 } pcfv_descent_report;
 
-/* Advance u in place.  Returns PCFV_OK when rel_tol was reached (or, with
- * rel_tol = 0, after max_steps), PCFV_ENOTCONV when max_steps ran out above
- * rel_tol, PCFV_ENAN on a non-finite cost, PCFV_EDIVERGED when the cost kept
- * growing after max_halvings halvings (u is then the last checked state). */
+/* Advance every guess of u in place with the same dtau.  Returns PCFV_OK when
+ * every guess reached rel_tol (or, with rel_tol = 0, after max_steps),
+ * PCFV_ENOTCONV when max_steps ran out above rel_tol, PCFV_ENAN on a
+ * non-finite cost, PCFV_EDIVERGED when some guess's cost kept growing after
+ * max_halvings halvings (u is then the last checked state).  The report gives
+ * the largest cost and relative residual over the guesses. */
 pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* opts,
                          pcfv_descent_report* report);
 
-/* Norms: out_host[0] = ||u||_W, out_host[1] = ||u_b + u||_W,
- * out_host[2] = D = <curl U, curl U>_W (so that laminar flow has D = 1,
- * Table 2), synchronises. */
-pcfv_status pcfv_norms(pcfv_ctx* ctx, const double* u, double out_host[3]);
+/* Norms per guess b: out_host[3b] = ||u||_W, out_host[3b+1] = ||u_b + u||_W,
+ * out_host[3b+2] = D = <curl U, curl U>_W (so that laminar flow has D = 1,
+ * Table 2); out_host holds 3 * batch doubles.  Synchronises. */
+pcfv_status pcfv_norms(pcfv_ctx* ctx, const double* u, double* out_host);
 
-/* Minimal real state vector psi (Sec. 6.2), length n_state doubles:
+/* Minimal real state vector psi (Sec. 6.2), n_state doubles per guess:
  * (0,0) mode: u_x and u_z coefficients n = 0..Ny-3; then for each independent
  * mode (kz > 0, or kz = 0 with kx > 0) in storage order: Re v, Im v for
  * n = 0..Ny-5, Re eta, Im eta for n = 0..Ny-3, with v the wall-normal velocity
@@ -169,9 +177,10 @@ pcfv_status pcfv_norms(pcfv_ctx* ctx, const double* u, double out_host[3]);
 pcfv_status pcfv_pack_state(pcfv_ctx* ctx, const double* u, double* psi);
 pcfv_status pcfv_unpack_state(pcfv_ctx* ctx, const double* psi, double* u);
 
-/* Admissibility defects of u: defects_host[0] = max |divergence coefficient|,
- * [1] = max |wall value|, [2] = max Hermitian defect on kz = 0; synchronises. */
-pcfv_status pcfv_check_state(pcfv_ctx* ctx, const double* u, double defects_host[3]);
+/* Admissibility defects of each guess b: defects_host[3b] = max |divergence
+ * coefficient|, [3b+1] = max |wall value|, [3b+2] = max Hermitian defect on
+ * kz = 0 (3 * batch doubles); synchronises. */
+pcfv_status pcfv_check_state(pcfv_ctx* ctx, const double* u, double* defects_host);
 
 /* Average device time per launch, in milliseconds, of each kernel of one
  * descent step, measured with HIP events on the context stream over nrep
@@ -186,8 +195,8 @@ pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* 
 const char* pcfv_last_error(const pcfv_ctx* ctx);
 
 /* Host-side copy of a constant table for cfg, computed without a device (for
- * tests of the setup arithmetic).  which: 0 fixed matrices (M_COUNT slots of
- * Ny x Ny, transposed), 1 per-mode scalars, 2 Helmholtz diagonals,
+ * tests of the setup arithmetic).  which: 0 fixed matrices (27 slots of
+ * Ny x Ny, each matrix stored transposed), 1 per-mode scalars, 2 Helmholtz diagonals,
  * 3 Poisson diagonals, 4 projection diagonals, 5 homogeneous v responses,
  * 6 their derivatives, 7 inverse influence matrices, 8 eigenvalues of the tau
  * second derivative.  Copies min(cap, size) doubles to out (if non-NULL) and

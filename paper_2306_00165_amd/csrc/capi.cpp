@@ -2,6 +2,7 @@
 // and the host-side sequencing of the kernels for each call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -40,6 +41,10 @@ bool validate(const pcfv_config* c, std::string& e) {
         e = "only precision 0 (FP64) is supported";
         return false;
     }
+    if (c->batch < 0 || c->batch > 4096) {
+        e = "batch must lie in [0, 4096] (0 means 1)";
+        return false;
+    }
     if (c->Nx < 6 || c->Nz < 6 || c->Nx > 512 || c->Nz > 512) {
         e = "Nx and Nz must lie in [6, 512]";
         return false;
@@ -66,6 +71,8 @@ KP base_kp(const pcfv_config& c) {
     p.nkx = 2 * p.Kx + 1;
     p.nkz = p.Kz + 1;
     p.nm = p.nkx * p.nkz;
+    p.B = c.batch > 0 ? c.batch : 1;
+    p.nmB = p.B * p.nm;
     // widest x slab (a divisor of Nx, at most 8) whose physical-space kernels
     // fit in 64 KiB of LDS
     p.XS = 1;
@@ -81,7 +88,7 @@ KP base_kp(const pcfv_config& c) {
 
 WsLayout layout(const pcfv_config& c) {
     const KP p = base_kp(c);
-    const size_t N = p.N, nm = p.nm, NS = p.NS;
+    const size_t N = p.N, nm = p.nm, NS = p.NS, nmB = p.nmB, B = p.B;
     size_t sz[W_COUNT];
     sz[W_MATS] = (size_t)M_COUNT * N * N * 8;
     sz[W_MINFO] = nm * MI_STRIDE * 8;
@@ -92,13 +99,13 @@ WsLayout layout(const pcfv_config& c) {
     sz[W_TWZ] = (size_t)c.Nz * 16;
     sz[W_YGL] = N * 8;
     sz[W_INDEP] = nm * 4;
-    sz[W_Y] = sz[W_YV] = 6 * N * nm * 16;
-    sz[W_ATIL] = 3 * N * nm * 16;
-    sz[W_P3] = NS * 3 * N * nm * 16;
-    sz[W_P6] = NS * 6 * N * nm * 16;
-    sz[W_A] = sz[W_R] = sz[W_CK] = sz[W_TMP] = 3 * nm * N * 16;
-    sz[W_PART] = nm * 4 * 8;
-    sz[W_SCAL] = 64 * 8;
+    sz[W_Y] = sz[W_YV] = 6 * N * nmB * 16;
+    sz[W_ATIL] = 3 * N * nmB * 16;
+    sz[W_P3] = NS * 3 * N * nmB * 16;
+    sz[W_P6] = NS * 6 * N * nmB * 16;
+    sz[W_A] = sz[W_R] = sz[W_CK] = sz[W_TMP] = 3 * nmB * N * 16;
+    sz[W_PART] = nmB * 4 * 8;
+    sz[W_SCAL] = (64 + 4 * B) * 8;
     WsLayout L;
     size_t o = 0;
     for (int i = 0; i < W_COUNT; ++i) {
@@ -124,7 +131,7 @@ struct pcfv_ctx {
 
     template <class T>
     T* at(int slot) { return reinterpret_cast<T*>(ws + L.off[slot]); }
-    long long nfield() const { return 3LL * kp.nm * kp.N; }  // complex values per field
+    long long nfield() const { return 3LL * kp.nmB * kp.N; }  // complex values, all guesses
 };
 
 namespace {
@@ -162,24 +169,32 @@ pcfv_status residual_core(pcfv_ctx* ctx, const double* u, double* r, bool cost) 
     return PCFV_OK;
 }
 
-pcfv_status read_scalars(pcfv_ctx* ctx, int n, int stride, int op, double* host) {
-    PCFV_TRY(launch_reduce(ctx->stream, ctx->part, n, stride, op, ctx->scal), "reduce");
-    PCFV_TRY(hipMemcpyAsync(host, ctx->scal, stride * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+pcfv_status read_scalars(pcfv_ctx* ctx, int stride, int op, double* host) {
+    const KP& p = ctx->kp;
+    PCFV_TRY(launch_reduce(ctx->stream, ctx->part, p.B, p.nm, stride, op, ctx->scal), "reduce");
+    PCFV_TRY(hipMemcpyAsync(host, ctx->scal, (size_t)p.B * stride * sizeof(double), hipMemcpyDeviceToHost,
+                            ctx->stream),
              "copy scalars");
     PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
     return PCFV_OK;
 }
 
-pcfv_status cost_and_norm(pcfv_ctx* ctx, const double* u, double* cost, double* ntot) {
+// Per-guess cost J^2 and ||u_b + u||_W of the current state (Y must hold its
+// y-values).
+pcfv_status cost_and_norm(pcfv_ctx* ctx, const double* u, std::vector<double>& cost,
+                          std::vector<double>& ntot) {
+    const int B = ctx->kp.B;
     pcfv_status s = residual_core(ctx, u, nullptr, true);
     if (s != PCFV_OK) return s;
-    s = read_scalars(ctx, ctx->kp.nm, 1, 0, cost);
+    cost.assign(B, 0.0);
+    s = read_scalars(ctx, 1, 0, cost.data());
     if (s != PCFV_OK) return s;
     PCFV_TRY(launch_norms(ctx->kp, ctx->stream, cd(u), ctx->part), "norms");
-    double nrm[3];
-    s = read_scalars(ctx, ctx->kp.nm, 3, 0, nrm);
+    std::vector<double> nrm(3 * B);
+    s = read_scalars(ctx, 3, 0, nrm.data());
     if (s != PCFV_OK) return s;
-    *ntot = std::sqrt(nrm[1]);
+    ntot.assign(B, 0.0);
+    for (int b = 0; b < B; ++b) ntot[b] = std::sqrt(nrm[3 * b + 1]);
     return PCFV_OK;
 }
 
@@ -254,6 +269,7 @@ pcfv_status pcfv_create(const pcfv_config* cfg, void* hip_stream, void* workspac
     p.twz = ctx->at<double2>(W_TWZ);
     p.ygl = ctx->at<double>(W_YGL);
     p.indep = ctx->at<int>(W_INDEP);
+    p.nstate = t.n_state;
     ctx->kp = p;
     ctx->Y = ctx->at<double2>(W_Y);
     ctx->Yv = ctx->at<double2>(W_YV);
@@ -305,6 +321,7 @@ pcfv_status pcfv_get_layout(const pcfv_ctx* ctx, pcfv_layout* out) {
     out->n_modes = p.nm;
     out->n_complex = 3LL * p.nm * p.N;
     out->n_state = ctx->t.n_state;
+    out->batch = p.B;
     return PCFV_OK;
 }
 
@@ -319,7 +336,7 @@ pcfv_status pcfv_residual(pcfv_ctx* ctx, const double* u, double* r, double* cos
     PCFV_TRY(launch_synth(ctx->kp, ctx->stream, cd(u), ctx->Y), "synth");
     pcfv_status s = residual_core(ctx, u, r, cost_host != nullptr);
     if (s != PCFV_OK || !cost_host) return s;
-    return read_scalars(ctx, ctx->kp.nm, 1, 0, cost_host);
+    return read_scalars(ctx, 1, 0, cost_host);
 }
 
 pcfv_status pcfv_cost(pcfv_ctx* ctx, const double* u, double* cost_host) {
@@ -364,27 +381,40 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
         !(o->rel_tol >= 0))
         return fail(ctx, PCFV_EINVAL, "invalid descent options");
     const KP& p = ctx->kp;
+    const int B = p.B;
     const size_t fbytes = (size_t)ctx->nfield() * 16;
-    double dtau = o->dtau, tau = 0, cost = 0, ntot = 0;
+    double dtau = o->dtau, tau = 0;
     long long steps = 0;
     int halvings = 0;
+    std::vector<double> cost, ntot, cost_prev;
     pcfv_descent_report local{};
     if (!rep) rep = &local;
-    auto report = [&](pcfv_status s) {
+    auto worst_rel = [&]() {
+        double w = 0;
+        for (int b = 0; b < B; ++b)
+            w = std::max(w, ntot[b] > 0 ? std::sqrt(std::max(cost[b], 0.0)) / ntot[b] : 0.0);
+        return w;
+    };
+    auto report = [&](pcfv_status st) {
         rep->steps = steps;
         rep->tau = tau;
-        rep->cost = cost;
-        rep->rel_res = (ntot > 0) ? std::sqrt(std::max(cost, 0.0)) / ntot : 0.0;
+        rep->cost = cost.empty() ? 0.0 : *std::max_element(cost.begin(), cost.end());
+        rep->rel_res = cost.empty() ? 0.0 : worst_rel();
         rep->dtau_final = dtau;
         rep->n_halvings = halvings;
-        return s;
+        return st;
+    };
+    auto finite = [&]() {
+        for (double c : cost)
+            if (!std::isfinite(c)) return false;
+        return true;
     };
     PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth");
-    pcfv_status s = cost_and_norm(ctx, u, &cost, &ntot);
+    pcfv_status s = cost_and_norm(ctx, u, cost, ntot);
     if (s != PCFV_OK) return s;
-    if (!std::isfinite(cost)) return report(fail(ctx, PCFV_ENAN, "cost is not finite"));
-    double cost_prev = cost;
-    if (o->rel_tol > 0 && std::sqrt(cost) / ntot < o->rel_tol) return report(PCFV_OK);
+    if (!finite()) return report(fail(ctx, PCFV_ENAN, "cost is not finite"));
+    cost_prev = cost;
+    if (o->rel_tol > 0 && worst_rel() < o->rel_tol) return report(PCFV_OK);
     while (steps < o->max_steps) {
         const long long k = std::min<long long>(o->check_every, o->max_steps - steps);
         if (o->grow_tol > 0)
@@ -395,40 +425,41 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
         }
         steps += k;
         tau += k * dtau;
-        s = cost_and_norm(ctx, u, &cost, &ntot);
+        s = cost_and_norm(ctx, u, cost, ntot);
         if (s != PCFV_OK) return s;
-        if (!std::isfinite(cost)) return report(fail(ctx, PCFV_ENAN, "cost is not finite"));
-        if (o->grow_tol > 0 && cost > o->grow_tol * cost_prev) {
-            if (halvings >= o->max_halvings) {
-                PCFV_TRY(hipMemcpyAsync(u, ctx->ck, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "restore");
-                PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
-                cost = cost_prev;
-                return report(fail(ctx, PCFV_EDIVERGED, "cost grew beyond grow_tol"));
-            }
+        if (!finite()) return report(fail(ctx, PCFV_ENAN, "cost is not finite"));
+        bool grew = false;
+        for (int b = 0; b < B; ++b) grew |= (o->grow_tol > 0 && cost[b] > o->grow_tol * cost_prev[b]);
+        if (grew) {
             PCFV_TRY(hipMemcpyAsync(u, ctx->ck, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "restore");
-            PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth");
             steps -= k;
             tau -= k * dtau;
+            cost = cost_prev;
+            if (halvings >= o->max_halvings) {
+                PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
+                return report(fail(ctx, PCFV_EDIVERGED, "cost grew beyond grow_tol"));
+            }
+            PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth");
             dtau *= 0.5;
             ++halvings;
-            cost = cost_prev;
             continue;
         }
         cost_prev = cost;
-        if (o->rel_tol > 0 && std::sqrt(cost) / ntot < o->rel_tol) return report(PCFV_OK);
+        if (o->rel_tol > 0 && worst_rel() < o->rel_tol) return report(PCFV_OK);
     }
     return report(o->rel_tol > 0 ? fail(ctx, PCFV_ENOTCONV, "max_steps reached above rel_tol") : PCFV_OK);
 }
 
-pcfv_status pcfv_norms(pcfv_ctx* ctx, const double* u, double out_host[3]) {
+
+pcfv_status pcfv_norms(pcfv_ctx* ctx, const double* u, double* out_host) {
     if (!ctx || !u || !out_host) return fail(ctx, PCFV_EINVAL, "NULL argument");
     PCFV_TRY(launch_norms(ctx->kp, ctx->stream, cd(u), ctx->part), "norms");
-    double v[3];
-    pcfv_status s = read_scalars(ctx, ctx->kp.nm, 3, 0, v);
+    pcfv_status s = read_scalars(ctx, 3, 0, out_host);
     if (s != PCFV_OK) return s;
-    out_host[0] = std::sqrt(std::max(v[0], 0.0));
-    out_host[1] = std::sqrt(std::max(v[1], 0.0));
-    out_host[2] = v[2];
+    for (int b = 0; b < ctx->kp.B; ++b) {
+        out_host[3 * b] = std::sqrt(std::max(out_host[3 * b], 0.0));
+        out_host[3 * b + 1] = std::sqrt(std::max(out_host[3 * b + 1], 0.0));
+    }
     return PCFV_OK;
 }
 
@@ -444,10 +475,10 @@ pcfv_status pcfv_unpack_state(pcfv_ctx* ctx, const double* psi, double* u) {
     return PCFV_OK;
 }
 
-pcfv_status pcfv_check_state(pcfv_ctx* ctx, const double* u, double defects_host[3]) {
+pcfv_status pcfv_check_state(pcfv_ctx* ctx, const double* u, double* defects_host) {
     if (!ctx || !u || !defects_host) return fail(ctx, PCFV_EINVAL, "NULL argument");
     PCFV_TRY(launch_check(ctx->kp, ctx->stream, cd(u), ctx->part), "check");
-    return read_scalars(ctx, ctx->kp.nm, 3, 1, defects_host);
+    return read_scalars(ctx, 3, 1, defects_host);
 }
 
 pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* ms_out, int* n_out) {

@@ -25,9 +25,13 @@ namespace pcfv {
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int MODE_THREADS = 64;   // one wavefront per Fourier mode
+constexpr int MODE_THREADS = 256;              // one Fourier mode per work group of 4 waves
+constexpr int MODE_WAVES = MODE_THREADS / WAVE;
+constexpr int KSPLIT = 4;                      // lanes sharing one output row of a contraction
+constexpr int ROWS_PER_WAVE = WAVE / KSPLIT;   // 16
 constexpr int PLANE_THREADS = 256;
-constexpr int MODE_VECS = 24;      // LDS vectors (length N) used by the mode kernels
+constexpr int MODE_VECS = 24;                  // LDS vectors (length N) used by the mode kernels
+constexpr int RED_SLOTS = 16;                  // doubles per wave for block reductions
 
 __device__ __forceinline__ double2 c2(double x, double y) { return make_double2(x, y); }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return c2(a.x + b.x, a.y + b.y); }
@@ -70,53 +74,127 @@ __device__ __forceinline__ const double* mat(const KP& p, int id) {
     return p.M + (size_t)id * p.N * p.N;
 }
 
-// y = A x for one complex vector; A (nout x nin) stored transposed (slot[m*N+n]).
-// x and y live in LDS and must not alias.  Caller synchronises afterwards.
+// Block reduction of NV values per thread (deterministic order): every thread
+// receives the block totals.  red: LDS scratch of MODE_WAVES * RED_SLOTS doubles.
+template <int NV>
+__device__ void bsum(double (&v)[NV], double* red) {
+    static_assert(NV <= RED_SLOTS, "too many values");
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wsum(v[i]);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[wave * RED_SLOTS + i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double t = 0;
+        for (int w = 0; w < MODE_WAVES; ++w) t += red[w * RED_SLOTS + i];
+        v[i] = t;
+    }
+    __syncthreads();
+}
+
+template <int NV>
+__device__ void bmax(double (&v)[NV], double* red) {
+    static_assert(NV <= RED_SLOTS, "too many values");
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wmax(v[i]);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[wave * RED_SLOTS + i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double t = 0;
+        for (int w = 0; w < MODE_WAVES; ++w) t = fmax(t, red[w * RED_SLOTS + i]);
+        v[i] = t;
+    }
+    __syncthreads();
+}
+
+// y = A x for one complex vector; A (nout x nin) stored transposed (slot[k*N+n]).
+// Each output row is computed by KSPLIT lanes of one wave, each summing every
+// KSPLIT-th term, then combined with cross-lane shuffles; rows are dealt out
+// in groups of 16 per wave.  x and y live in LDS and must not alias.  Caller
+// synchronises afterwards.
+template <int NP>
 __device__ void mv(const KP& p, int id, int nin, int nout, const double2* x, double2* y) {
     const double* __restrict__ A = mat(p, id);
-    const int N = p.N;
-    for (int n = threadIdx.x; n < nout; n += MODE_THREADS) {
+    const int N = p.N, lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int r = lane % ROWS_PER_WAVE, q = lane / ROWS_PER_WAVE;
+#pragma unroll
+    for (int n0 = 0; n0 < NP; n0 += MODE_WAVES * ROWS_PER_WAVE) {
+        const int n = n0 + wave * ROWS_PER_WAVE + r;
         double re = 0.0, im = 0.0;
-#pragma unroll 8
-        for (int k = 0; k < nin; ++k) {
-            const double a = A[k * N + n];
-            const double2 v = x[k];
-            re = fma(a, v.x, re);
-            im = fma(a, v.y, im);
+        if (n < nout) {
+#pragma unroll
+            for (int i = 0; i < NP / KSPLIT; ++i) {   // fully unrolled: all loads in flight
+                const int k = q + KSPLIT * i;
+                if (k < nin) {
+                    const double a = A[k * N + n];
+                    const double2 v = x[k];
+                    re = fma(a, v.x, re);
+                    im = fma(a, v.y, im);
+                }
+            }
         }
-        y[n] = c2(re, im);
+        re += __shfl_xor(re, 16, WAVE);
+        im += __shfl_xor(im, 16, WAVE);
+        re += __shfl_xor(re, 32, WAVE);
+        im += __shfl_xor(im, 32, WAVE);
+        if (q == 0 && n < nout) y[n] = c2(re, im);
     }
 }
 
 // The same matrix applied to three vectors.
+template <int NP>
 __device__ void mv3(const KP& p, int id, int nin, int nout, const double2* x0,
                     const double2* x1, const double2* x2, double2* y0, double2* y1,
                     double2* y2) {
     const double* __restrict__ A = mat(p, id);
-    const int N = p.N;
-    for (int n = threadIdx.x; n < nout; n += MODE_THREADS) {
-        double r0 = 0, i0 = 0, r1 = 0, i1 = 0, r2 = 0, i2 = 0;
-#pragma unroll 4
-        for (int k = 0; k < nin; ++k) {
-            const double a = A[k * N + n];
-            const double2 v0 = x0[k], v1 = x1[k], v2 = x2[k];
-            r0 = fma(a, v0.x, r0);
-            i0 = fma(a, v0.y, i0);
-            r1 = fma(a, v1.x, r1);
-            i1 = fma(a, v1.y, i1);
-            r2 = fma(a, v2.x, r2);
-            i2 = fma(a, v2.y, i2);
+    const int N = p.N, lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int r = lane % ROWS_PER_WAVE, q = lane / ROWS_PER_WAVE;
+#pragma unroll
+    for (int n0 = 0; n0 < NP; n0 += MODE_WAVES * ROWS_PER_WAVE) {
+        const int n = n0 + wave * ROWS_PER_WAVE + r;
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        if (n < nout) {
+#pragma unroll
+            for (int i = 0; i < NP / KSPLIT; ++i) {
+                const int k = q + KSPLIT * i;
+                if (k < nin) {
+                    const double a = A[k * N + n];
+                    const double2 v0 = x0[k], v1 = x1[k], v2 = x2[k];
+                    acc[0] = fma(a, v0.x, acc[0]);
+                    acc[1] = fma(a, v0.y, acc[1]);
+                    acc[2] = fma(a, v1.x, acc[2]);
+                    acc[3] = fma(a, v1.y, acc[3]);
+                    acc[4] = fma(a, v2.x, acc[4]);
+                    acc[5] = fma(a, v2.y, acc[5]);
+                }
+            }
         }
-        y0[n] = c2(r0, i0);
-        y1[n] = c2(r1, i1);
-        y2[n] = c2(r2, i2);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            acc[i] += __shfl_xor(acc[i], 16, WAVE);
+            acc[i] += __shfl_xor(acc[i], 32, WAVE);
+        }
+        if (q == 0 && n < nout) {
+            y0[n] = c2(acc[0], acc[1]);
+            y1[n] = c2(acc[2], acc[3]);
+            y2[n] = c2(acc[4], acc[5]);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Stokes solve S (kappa > 0) by the influence-matrix method in the fixed
 // tau eigenbasis.  Writes (ox, oy, oz) = velocity of the Chebyshev-tau
-// solution for forcing (Fx, Fy, Fz).  w: 10 scratch vectors.
+// solution for forcing (Fx, Fy, Fz).  The algorithm:
 //   h  = D Fy + i a Fx + i b Fz                  (divergence of the forcing)
 //   p0 = Poisson-tau solve (D^2 - k^2) p0 = h, p0(+-1) = 0
 //   v0 = Helmholtz-tau solve (sig - nu D^2) v0 = Fy - D p0, v0(+-1) = 0
@@ -125,13 +203,22 @@ __device__ void mv3(const KP& p, int id, int nin, int nout, const double2* x0,
 //                              and the tau correction of the Poisson equation)
 //   eta = Helmholtz-tau solve of (i b Fx - i a Fz)   (wall-normal vorticity)
 //   u_x = (i a Dv - i b eta)/k^2, u_z = (i b Dv + i a eta)/k^2
+// Each tau solve is Pl diag(d) Pr; with the precomposed fixed matrices
+// PRD = Pr R D, PRDPL = Pr R D Pl and DPL = D Pl the whole solve is three
+// contraction phases:
+//   A: s1 = Pr Fh, s2 = Pr Fe, s3 = Pr Fy, s4 = PRD Fy
+//      t1 = -dP (s4 + s1), te = dH s2
+//   B: t2 = dH (s3 - PRDPL t1)           (p0 = Pl t1 is never formed)
+//   C: v0 = Pl t2, Dv0 = DPL t2, eta = Pl te, and p0(N-1) = Pl[N-1,:] t1
+// w: 10 scratch vectors.
 // ---------------------------------------------------------------------------
+template <int NP>
 __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const double2* Fy,
-                       const double2* Fz, double2* ox, double2* oy, double2* oz, double2* w) {
+                       const double2* Fz, double2* ox, double2* oy, double2* oz, double2* w,
+                       double* red) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
-    double2 *Fh = w, *Fe = w + N, *h = w + 2 * N, *t1 = w + 3 * N, *t2 = w + 4 * N,
-            *p0 = w + 5 * N, *eta = w + 6 * N, *q = w + 7 * N, *v0 = w + 8 * N,
-            *Dv0 = w + 9 * N;
+    double2 *Fh = w, *Fe = w + N, *s1 = w + 2 * N, *s2 = w + 3 * N, *s3 = w + 4 * N,
+            *s4 = w + 5 * N, *t2 = w + 6 * N, *v0 = w + 7 * N, *Dv0 = w + 8 * N, *eta = w + 9 * N;
     const double* dH = p.dH + (size_t)m * N;
     const double* dP = p.dP + (size_t)m * N;
     for (int n = t; n < N; n += MODE_THREADS) {
@@ -140,52 +227,47 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
         Fe[n] = csub(imul(c.b, fx), imul(c.a, fz));
     }
     __syncthreads();
-    mv(p, M_D, N, N, Fy, h);
-    __syncthreads();
-    for (int n = t; n < M; n += MODE_THREADS) h[n] = cscl(-1.0, cadd(h[n], Fh[n]));
-    __syncthreads();
-    mv(p, M_PR, M, M, h, t1);
-    mv(p, M_PR, M, M, Fe, t2);
+    mv3<NP>(p, M_PR, M, M, Fh, Fe, Fy, s1, s2, s3);
+    mv<NP>(p, M_PRD, N, M, Fy, s4);
     __syncthreads();
     for (int n = t; n < M; n += MODE_THREADS) {
-        t1[n] = cscl(dP[n], t1[n]);
-        t2[n] = cscl(dH[n], t2[n]);
+        s1[n] = cscl(-dP[n], cadd(s4[n], s1[n]));   // t1
+        s2[n] = cscl(dH[n], s2[n]);                 // te
     }
     __syncthreads();
-    mv(p, M_PL, M, N, t1, p0);
-    mv(p, M_PL, M, N, t2, eta);
+    mv<NP>(p, M_PRDPL, M, M, s1, t2);
     __syncthreads();
-    mv(p, M_D, N, N, p0, q);
+    for (int n = t; n < M; n += MODE_THREADS) t2[n] = cscl(dH[n], csub(s3[n], t2[n]));
     __syncthreads();
-    for (int n = t; n < N; n += MODE_THREADS) q[n] = csub(Fy[n], q[n]);
+    mv<NP>(p, M_PL, M, N, t2, v0);
+    mv<NP>(p, M_DPL, M, N, t2, Dv0);
+    mv<NP>(p, M_PL, M, N, s2, eta);
     __syncthreads();
-    mv(p, M_PR, M, M, q, t1);
-    __syncthreads();
-    for (int n = t; n < M; n += MODE_THREADS) t1[n] = cscl(dH[n], t1[n]);
-    __syncthreads();
-    mv(p, M_PL, M, N, t1, v0);
-    __syncthreads();
-    mv(p, M_D, N, N, v0, Dv0);
-    __syncthreads();
-    double spr = 0, spi = 0, smr = 0, smi = 0;
+    const double* PLlast = mat(p, M_PL) + (N - 1);      // row N-1 of Pl: PLlast[k * N]
+    double sums[6] = {0, 0, 0, 0, 0, 0};
     for (int n = t; n < N; n += MODE_THREADS) {
         const double2 d = Dv0[n];
-        spr += d.x;
-        spi += d.y;
-        smr += (n & 1) ? -d.x : d.x;
-        smi += (n & 1) ? -d.y : d.y;
+        sums[0] += d.x;
+        sums[1] += d.y;
+        sums[2] += (n & 1) ? -d.x : d.x;
+        sums[3] += (n & 1) ? -d.y : d.y;
+        if (n < M) {
+            sums[4] += PLlast[(size_t)n * N] * s1[n].x;
+            sums[5] += PLlast[(size_t)n * N] * s1[n].y;
+        }
     }
-    const double2 e0 = c2(wsum(spr), wsum(spi)), e1 = c2(wsum(smr), wsum(smi));
+    bsum(sums, red);
+    const double2 e0 = c2(sums[0], sums[1]), e1 = c2(sums[2], sums[3]), p0last = c2(sums[4], sums[5]);
     const double tn = 2.0 * (N - 1);
-    const double2 e2 = csub(cadd(cscl(c.sig, v0[N - 2]), cscl(tn, p0[N - 1])), Fy[N - 2]);
+    const double2 e2 = csub(cadd(cscl(c.sig, v0[N - 2]), cscl(tn, p0last)), Fy[N - 2]);
     const double2 e3 = csub(cscl(c.sig, v0[N - 1]), Fy[N - 1]);
     const double* Ai = p.Ainv + (size_t)m * 16;
     double2 cc[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double2 s = cadd(cadd(cscl(Ai[4 * k], e0), cscl(Ai[4 * k + 1], e1)),
-                         cadd(cscl(Ai[4 * k + 2], e2), cscl(Ai[4 * k + 3], e3)));
-        cc[k] = cscl(-1.0, s);
+        double2 sk = cadd(cadd(cscl(Ai[4 * k], e0), cscl(Ai[4 * k + 1], e1)),
+                          cadd(cscl(Ai[4 * k + 2], e2), cscl(Ai[4 * k + 3], e3)));
+        cc[k] = cscl(-1.0, sk);
     }
     const double* Vk = p.Vk + (size_t)m * 4 * N;
     const double* DVk = p.DVk + (size_t)m * 4 * N;
@@ -204,137 +286,120 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
     __syncthreads();
 }
 
-// Conjugate transpose of stokes(): (yx, yy, yz) = S^H (xu, xv, xw), obtained by
-// running the steps above backwards with every matrix transposed.  w: 12 vectors.
+// Conjugate transpose of stokes(): (yx, yy, yz) = S^H (xu, xv, xw), the steps
+// above run backwards with every matrix transposed (three contraction phases).
+// w: 11 scratch vectors.
+template <int NP>
 __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, const double2* xv,
                          const double2* xw, double2* yx, double2* yy, double2* yz,
-                         double2* w) {
+                         double2* w, double* red) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
-    double2 *bDv = w, *beta = w + N, *bv = w + 2 * N, *bDv0 = w + 3 * N, *bv0 = w + 4 * N,
-            *bp0 = w + 5 * N, *bFy = w + 6 * N, *bq = w + 7 * N, *bh = w + 8 * N,
-            *tt = w + 9 * N, *tu = w + 10 * N, *bFe = w + 11 * N;
+    double2 *bDv = w, *beta = w + N, *bv0 = w + 2 * N, *bDv0 = w + 3 * N, *bt2 = w + 4 * N,
+            *tmp = w + 5 * N, *bte = w + 6 * N, *bFh = w + 7 * N, *bFe = w + 8 * N,
+            *bFy = w + 9 * N, *bFy2 = w + 10 * N;
     const double* dH = p.dH + (size_t)m * N;
     const double* dP = p.dP + (size_t)m * N;
-    for (int n = t; n < N; n += MODE_THREADS) {
-        const double2 a0 = xu[n], a2 = xw[n];
-        bDv[n] = cscl(c.ik2, cadd(imul(-c.a, a0), imul(-c.b, a2)));
-        beta[n] = cscl(c.ik2, csub(imul(c.b, a0), imul(c.a, a2)));
-    }
-    __syncthreads();
-    mv(p, M_DT, N, N, bDv, tt);
-    __syncthreads();
-    for (int n = t; n < N; n += MODE_THREADS) bv[n] = cadd(xv[n], tt[n]);
-    __syncthreads();
     const double* Vk = p.Vk + (size_t)m * 4 * N;
-    double2 bc[4];
+    const double* DVk = p.DVk + (size_t)m * 4 * N;
+    double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int n = t; n < N; n += MODE_THREADS) {
+        const double2 a0 = xu[n], a2 = xw[n], bv = xv[n];
+        const double2 bd = cscl(c.ik2, cadd(imul(-c.a, a0), imul(-c.b, a2)));
+        bDv[n] = bd;
+        beta[n] = cscl(c.ik2, csub(imul(c.b, a0), imul(c.a, a2)));
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double sr = 0, si = 0;
-        for (int n = t; n < N; n += MODE_THREADS) {
-            sr += Vk[k * N + n] * bv[n].x;
-            si += Vk[k * N + n] * bv[n].y;
+        for (int k = 0; k < 4; ++k) {   // v = v0 + Vk^T c and Dv = Dv0 + DVk^T c
+            dots[2 * k] += Vk[k * N + n] * bv.x + DVk[k * N + n] * bd.x;
+            dots[2 * k + 1] += Vk[k * N + n] * bv.y + DVk[k * N + n] * bd.y;
         }
-        bc[k] = c2(wsum(sr), wsum(si));
     }
+    bsum(dots, red);
     const double* Ai = p.Ainv + (size_t)m * 16;
     double2 be[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        double2 s = cadd(cadd(cscl(Ai[j], bc[0]), cscl(Ai[4 + j], bc[1])),
-                         cadd(cscl(Ai[8 + j], bc[2]), cscl(Ai[12 + j], bc[3])));
-        be[j] = cscl(-1.0, s);
+        double2 sj = c2(0, 0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sj = cadd(sj, cscl(Ai[4 * k + j], c2(dots[2 * k], dots[2 * k + 1])));
+        be[j] = cscl(-1.0, sj);
     }
-    for (int n = t; n < N; n += MODE_THREADS) bDv0[n] = (n & 1) ? csub(be[0], be[1]) : cadd(be[0], be[1]);
-    __syncthreads();
-    mv(p, M_DT, N, N, bDv0, tt);
-    __syncthreads();
-    const double tn = 2.0 * (N - 1);
     for (int n = t; n < N; n += MODE_THREADS) {
-        double2 x = cadd(bv[n], tt[n]);
+        double2 x = xv[n];
         if (n == N - 2) x = cadd(x, cscl(c.sig, be[2]));
         if (n == N - 1) x = cadd(x, cscl(c.sig, be[3]));
         bv0[n] = x;
-        bp0[n] = (n == N - 1) ? cscl(tn, be[2]) : c2(0, 0);
-        bFy[n] = (n == N - 2) ? cscl(-1.0, be[2]) : ((n == N - 1) ? cscl(-1.0, be[3]) : c2(0, 0));
+        bDv0[n] = cadd(bDv[n], (n & 1) ? csub(be[0], be[1]) : cadd(be[0], be[1]));
     }
     __syncthreads();
-    mv(p, M_PLT, N, M, bv0, tt);
-    mv(p, M_PLT, N, M, beta, tu);
+    mv<NP>(p, M_PLT, N, M, bv0, bt2);
+    mv<NP>(p, M_DPLT, N, M, bDv0, tmp);
+    mv<NP>(p, M_PLT, N, M, beta, bte);
     __syncthreads();
     for (int n = t; n < M; n += MODE_THREADS) {
-        tt[n] = cscl(dH[n], tt[n]);
-        tu[n] = cscl(dH[n], tu[n]);
+        bt2[n] = cscl(dH[n], cadd(bt2[n], tmp[n]));   // u2 = dH (PL^T bv0 + DPL^T bDv0)
+        bte[n] = cscl(dH[n], bte[n]);                 // bs2
     }
     __syncthreads();
-    mv(p, M_PRT, M, M, tt, bq);
-    mv(p, M_PRT, M, M, tu, bFe);
-    for (int n = M + t; n < N; n += MODE_THREADS) {
-        bq[n] = c2(0, 0);
-        bFe[n] = c2(0, 0);
-    }
+    mv<NP>(p, M_PRDPLT, M, M, bt2, tmp);
     __syncthreads();
-    mv(p, M_DT, N, N, bq, tt);
+    const double2 bp0last = cscl(2.0 * (N - 1), be[2]);
+    const double* PLlast = mat(p, M_PL) + (N - 1);
+    for (int n = t; n < M; n += MODE_THREADS)   // bs1 = -dP (Pl[N-1,:] bp0last - PRDPL^T u2)
+        tmp[n] = cscl(-dP[n], csub(cscl(PLlast[(size_t)n * N], bp0last), tmp[n]));
+    __syncthreads();
+    mv<NP>(p, M_PRT, M, M, tmp, bFh);
+    mv<NP>(p, M_PRT, M, M, bte, bFe);
+    mv<NP>(p, M_PRT, M, M, bt2, bFy);
+    mv<NP>(p, M_PRDT, M, N, tmp, bFy2);
     __syncthreads();
     for (int n = t; n < N; n += MODE_THREADS) {
-        bFy[n] = cadd(bFy[n], bq[n]);
-        bp0[n] = csub(bp0[n], tt[n]);
-    }
-    __syncthreads();
-    mv(p, M_PLT, N, M, bp0, tu);
-    __syncthreads();
-    for (int n = t; n < M; n += MODE_THREADS) tu[n] = cscl(dP[n], tu[n]);
-    __syncthreads();
-    mv(p, M_PRT, M, M, tu, bh);
-    __syncthreads();
-    for (int n = t; n < N; n += MODE_THREADS) bh[n] = (n < M) ? cscl(-1.0, bh[n]) : c2(0, 0);
-    __syncthreads();
-    mv(p, M_DT, N, N, bh, tt);
-    __syncthreads();
-    for (int n = t; n < N; n += MODE_THREADS) {
-        const double2 h = bh[n], e = bFe[n];
+        const double2 h = (n < M) ? bFh[n] : c2(0, 0), e = (n < M) ? bFe[n] : c2(0, 0);
+        double2 y = cadd((n < M) ? bFy[n] : c2(0, 0), bFy2[n]);
+        if (n == N - 2) y = csub(y, be[2]);
+        if (n == N - 1) y = csub(y, be[3]);
         yx[n] = cadd(imul(-c.a, h), imul(-c.b, e));
-        yy[n] = cadd(bFy[n], tt[n]);
+        yy[n] = y;
         yz[n] = cadd(imul(-c.b, h), imul(c.a, e));
     }
     __syncthreads();
 }
 
-// (0,0) mode: u_x and u_z solve the Dirichlet tau Helmholtz problem with
-// sigma = lam, u_y = 0.  w: 2 scratch vectors.
+template <int NP>
 __device__ void stokes0(const KP& p, const double2* Fx, const double2* Fz, double2* ox,
                         double2* oy, double2* oz, double2* w) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
     double2 *t1 = w, *t2 = w + N;
     const double* dH = p.dH;
-    mv(p, M_PR, M, M, Fx, t1);
-    mv(p, M_PR, M, M, Fz, t2);
+    mv<NP>(p, M_PR, M, M, Fx, t1);
+    mv<NP>(p, M_PR, M, M, Fz, t2);
     __syncthreads();
     for (int n = t; n < M; n += MODE_THREADS) {
         t1[n] = cscl(dH[n], t1[n]);
         t2[n] = cscl(dH[n], t2[n]);
     }
     __syncthreads();
-    mv(p, M_PL, M, N, t1, ox);
-    mv(p, M_PL, M, N, t2, oz);
+    mv<NP>(p, M_PL, M, N, t1, ox);
+    mv<NP>(p, M_PL, M, N, t2, oz);
     for (int n = t; n < N; n += MODE_THREADS) oy[n] = c2(0, 0);
     __syncthreads();
 }
 
+template <int NP>
 __device__ void stokes0_h(const KP& p, const double2* xu, const double2* xw, double2* yx,
                           double2* yy, double2* yz, double2* w) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
     double2 *t1 = w, *t2 = w + N;
     const double* dH = p.dH;
-    mv(p, M_PLT, N, M, xu, t1);
-    mv(p, M_PLT, N, M, xw, t2);
+    mv<NP>(p, M_PLT, N, M, xu, t1);
+    mv<NP>(p, M_PLT, N, M, xw, t2);
     __syncthreads();
     for (int n = t; n < M; n += MODE_THREADS) {
         t1[n] = cscl(dH[n], t1[n]);
         t2[n] = cscl(dH[n], t2[n]);
     }
     __syncthreads();
-    mv(p, M_PRT, M, M, t1, yx);
-    mv(p, M_PRT, M, M, t2, yz);
+    mv<NP>(p, M_PRT, M, M, t1, yx);
+    mv<NP>(p, M_PRT, M, M, t2, yz);
     for (int n = t; n < N; n += MODE_THREADS) {
         yy[n] = c2(0, 0);
         if (n >= M) {
@@ -349,12 +414,13 @@ __device__ void stokes0_h(const KP& p, const double2* xu, const double2* xw, dou
 // the (v, eta) parametrisation: the W-Gram matrix is block diagonal there,
 // the eta block is the fixed G-orthogonal Dirichlet projector and the v block
 // is diagonalised by fixed vectors X with diagonal 1/(1 + Lambda/kappa^2).
-// w: 9 scratch vectors.
+// Three contraction phases.  w: 8 scratch vectors.
+template <int NP>
 __device__ void project(const KP& p, int m, const MS& c, const double2* gx, const double2* gy,
                         const double2* gz, double2* ox, double2* oy, double2* oz, double2* w) {
     const int N = p.N, t = threadIdx.x;
-    double2 *gh = w, *ge = w + N, *t1 = w + 2 * N, *t2 = w + 3 * N, *bv = w + 4 * N,
-            *t4 = w + 5 * N, *v = w + 6 * N, *eta = w + 7 * N, *Dv = w + 8 * N;
+    double2 *gh = w, *ge = w + N, *t1 = w + 2 * N, *t2 = w + 3 * N, *t4 = w + 4 * N,
+            *v = w + 5 * N, *eta = w + 6 * N, *Dv = w + 7 * N;
     const double* dq = p.dproj + (size_t)m * N;
     for (int n = t; n < N; n += MODE_THREADS) {
         const double2 x = gx[n], z = gz[n];
@@ -362,19 +428,18 @@ __device__ void project(const KP& p, int m, const MS& c, const double2* gx, cons
         ge[n] = csub(imul(c.b, x), imul(c.a, z));
     }
     __syncthreads();
-    mv(p, M_DTG, N, N, gh, t1);
-    mv(p, M_G, N, N, gy, t2);
-    mv(p, M_PID, N, N, ge, eta);
+    mv<NP>(p, M_DTG, N, N, gh, t1);
+    mv<NP>(p, M_G, N, N, gy, t2);
+    mv<NP>(p, M_PID, N, N, ge, eta);
     __syncthreads();
-    for (int n = t; n < N; n += MODE_THREADS) bv[n] = csub(t2[n], cscl(c.ik2, t1[n]));
+    for (int n = t; n < N; n += MODE_THREADS) t2[n] = csub(t2[n], cscl(c.ik2, t1[n]));
     __syncthreads();
-    mv(p, M_PVLT, N, N - 4, bv, t4);
+    mv<NP>(p, M_PVLT, N, N - 4, t2, t4);
     __syncthreads();
     for (int n = t; n < N - 4; n += MODE_THREADS) t4[n] = cscl(dq[n], t4[n]);
     __syncthreads();
-    mv(p, M_PVL, N - 4, N, t4, v);
-    __syncthreads();
-    mv(p, M_D, N, N, v, Dv);
+    mv<NP>(p, M_PVL, N - 4, N, t4, v);
+    mv<NP>(p, M_DPVL, N - 4, N, t4, Dv);
     __syncthreads();
     for (int n = t; n < N; n += MODE_THREADS) {
         const double2 d = Dv[n], e = eta[n];
@@ -385,11 +450,12 @@ __device__ void project(const KP& p, int m, const MS& c, const double2* gx, cons
     __syncthreads();
 }
 
+template <int NP>
 __device__ void project0(const KP& p, const double2* gx, const double2* gz, double2* ox,
                          double2* oy, double2* oz) {
     const int N = p.N;
-    mv(p, M_PID, N, N, gx, ox);
-    mv(p, M_PID, N, N, gz, oz);
+    mv<NP>(p, M_PID, N, N, gx, ox);
+    mv<NP>(p, M_PID, N, N, gz, oz);
     for (int n = threadIdx.x; n < N; n += MODE_THREADS) oy[n] = c2(0, 0);
     __syncthreads();
 }
@@ -400,21 +466,24 @@ __device__ void project0(const KP& p, const double2* gx, const double2* gz, doub
 
 // y-values of u and of du/dy for the three components: Y[c] = C u_c,
 // Y[3+c] = C D u_c (Gauss-Lobatto synthesis).
+template <int NP>
 __global__ __launch_bounds__(MODE_THREADS) void k_synth(KP p, const double2* __restrict__ u,
                                                         double2* __restrict__ Y) {
     extern __shared__ double2 sm[];
-    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
-    if (m >= nm) return;
+    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    if (mB >= nmB) return;
+    const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
+    const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     double2* V = sm;
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) V[i * N + n] = u[((size_t)i * nm + m) * N + n];
+        for (int n = t; n < N; n += MODE_THREADS) V[i * N + n] = u[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
-    mv3(p, M_C, N, N, V, V + N, V + 2 * N, V + 3 * N, V + 4 * N, V + 5 * N);
-    mv3(p, M_CD, N, N, V, V + N, V + 2 * N, V + 6 * N, V + 7 * N, V + 8 * N);
+    mv3<NP>(p, M_C, N, N, V, V + N, V + 2 * N, V + 3 * N, V + 4 * N, V + 5 * N);
+    mv3<NP>(p, M_CD, N, N, V, V + N, V + 2 * N, V + 6 * N, V + 7 * N, V + 8 * N);
     __syncthreads();
     for (int f = 0; f < 6; ++f)
         for (int j = t; j < N; j += MODE_THREADS)
-            Y[((size_t)f * N + j) * nm + m] = V[(3 + f) * N + j];
+            Y[((size_t)f * N + j) * nmB + mB] = V[(3 + f) * N + j];
 }
 
 template <int MODE>
@@ -427,9 +496,11 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
     constexpr int NXF = 3 * NG3 + NG1;
     constexpr int NZF = (MODE == PLANE_ADJ) ? 9 : 3;  // after the forward z stage
     const int item = xcd_item(blockIdx.x, gridDim.x);
-    if (item >= p.NS * p.N) return;
-    const int j = item / p.NS, s = item - j * p.NS;   // the slabs of a plane run on one XCD
+    if (item >= p.B * p.NS * p.N) return;
+    const int jb = item / p.NS, s = item - jb * p.NS;   // the slabs of a plane run on one XCD
+    const int b = jb / p.N, j = jb - b * p.N;          // guess, Gauss-Lobatto plane
     const int N = p.N, Nx = p.Nx, Nz = p.Nz, nkx = p.nkx, nkz = p.nkz, nm = p.nm, XS = p.XS;
+    const int nmB = p.nmB, mo = b * nm;                // y-value arrays are [f][j][b * nm + m]
     const int Kx = p.Kx;
     const int x0 = s * XS, tid = threadIdx.x;
     const int per = XS * nkz, pz = XS * Nz;
@@ -448,8 +519,8 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
         if (g < NG3) {
             const double2* src = (g < 3) ? Y1 : Y2;
             const int comp = g % 3;
-            const double2* Vp = src + ((size_t)comp * N + j) * nm + kz;
-            const double2* Wp = src + ((size_t)(3 + comp) * N + j) * nm + kz;
+            const double2* Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
+            const double2* Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
             double2 aV = c2(0, 0), aA = c2(0, 0), aW = c2(0, 0);
             const int step = x % Nx;
             int idx = 0;                                   // (kx * x) mod Nx, kx = 0, 1, ..
@@ -469,7 +540,7 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
             xb[(3 * g + 2) * per + rem] = aW;
         } else {
             const int comp = g - NG3;
-            const double2* Ap = Y2 + ((size_t)comp * N + j) * nm + kz;
+            const double2* Ap = Y2 + ((size_t)comp * N + j) * nmB + mo + kz;
             double2 acc = c2(0, 0);
             const int step = x % Nx;
             int idx = 0;
@@ -632,58 +703,61 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
             }
             res = c2(ar * invNx, ai * invNx);
         }
-        out[(((size_t)s * NOUT + o) * N + j) * nm + mm] = res;
+        out[(((size_t)s * NOUT + o) * N + j) * nmB + mo + mm] = res;
     }
 }
 
+template <int NP>
 __global__ __launch_bounds__(MODE_THREADS) void k_mode_res(
     KP p, int flags, const double2* __restrict__ P3, const double2* __restrict__ u,
     double2* __restrict__ r, double* __restrict__ cost_part, double2* __restrict__ a,
     double2* __restrict__ Atil) {
     extern __shared__ double2 sm[];
-    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
-    if (m >= nm) return;
+    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    if (mB >= nmB) return;
+    const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
+    const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     auto vec = [&](int k) { return sm + (size_t)k * N; };
+    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
     double2 *R0 = vec(9), *R1 = vec(10), *R2 = vec(11);
     if (flags & RES_INPUT_W) {
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) vec(9 + i)[n] = u[((size_t)i * nm + m) * N + n];
+            for (int n = t; n < N; n += MODE_THREADS) vec(9 + i)[n] = u[so + ((size_t)i * nm + m) * N + n];
         __syncthreads();
     } else {
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MODE_THREADS) {
                 double2 acc = c2(0, 0);
-                for (int s = 0; s < p.NS; ++s) acc = cadd(acc, P3[(((size_t)s * 3 + i) * N + n) * nm + m]);
+                for (int s = 0; s < p.NS; ++s) acc = cadd(acc, P3[(((size_t)s * 3 + i) * N + n) * nmB + mB]);
                 vec(i)[n] = acc;
-                vec(3 + i)[n] = u[((size_t)i * nm + m) * N + n];
+                vec(3 + i)[n] = u[so + ((size_t)i * nm + m) * N + n];
             }
         __syncthreads();
-        mv3(p, M_CINV, N, N, vec(0), vec(1), vec(2), vec(6), vec(7), vec(8));
-        __syncthreads();
-        mv3(p, M_D2, N, N, vec(3), vec(4), vec(5), vec(0), vec(1), vec(2));
+        mv3<NP>(p, M_CINV, N, N, vec(0), vec(1), vec(2), vec(6), vec(7), vec(8));
+        mv3<NP>(p, M_D2, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
         __syncthreads();
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MODE_THREADS) {
-                const double2 L = csub(vec(i)[n], cscl(c.k2, vec(3 + i)[n]));
+                const double2 L = csub(vec(12 + i)[n], cscl(c.k2, vec(3 + i)[n]));
                 vec(6 + i)[n] = cadd(cscl(-1.0, vec(6 + i)[n]), cscl(p.nu, L));
             }
         __syncthreads();
         if (zero)
-            stokes0(p, vec(6), vec(8), R0, R1, R2, vec(12));
+            stokes0<NP>(p, vec(6), vec(8), R0, R1, R2, vec(12));
         else
-            stokes(p, m, c, vec(6), vec(7), vec(8), R0, R1, R2, vec(12));
+            stokes<NP>(p, m, c, vec(6), vec(7), vec(8), R0, R1, R2, vec(12), red);
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MODE_THREADS) {
                 const double2 v = cscl(p.lam, vec(9 + i)[n]);
                 vec(9 + i)[n] = v;
-                if (flags & RES_WRITE_R) r[((size_t)i * nm + m) * N + n] = v;
+                if (flags & RES_WRITE_R) r[so + ((size_t)i * nm + m) * N + n] = v;
             }
         __syncthreads();
     }
     if (!(flags & (RES_COST | RES_ADJ))) return;
-    mv3(p, M_G, N, N, R0, R1, R2, vec(3), vec(4), vec(5));
+    mv3<NP>(p, M_G, N, N, R0, R1, R2, vec(3), vec(4), vec(5));
     __syncthreads();
     if (flags & RES_COST) {
         double s = 0;
@@ -692,66 +766,69 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_res(
                 const double2 x = vec(9 + i)[n], y = vec(3 + i)[n];
                 s += x.x * y.x + x.y * y.y;
             }
-        s = wsum(s);
-        if (t == 0) cost_part[m] = c.wgt * s;
+        double tot[1] = {s};
+        bsum(tot, red);
+        if (t == 0) cost_part[mB] = c.wgt * tot[0];
     }
     if (!(flags & RES_ADJ)) return;
     if (zero)
-        stokes0_h(p, vec(3), vec(5), vec(6), vec(7), vec(8), vec(12));
+        stokes0_h<NP>(p, vec(3), vec(5), vec(6), vec(7), vec(8), vec(12));
     else
-        stokes_h(p, m, c, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8), vec(12));
-    mv3(p, M_GINV, N, N, vec(6), vec(7), vec(8), vec(0), vec(1), vec(2));
-    mv3(p, M_CINVT, N, N, vec(6), vec(7), vec(8), vec(12), vec(13), vec(14));
+        stokes_h<NP>(p, m, c, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8), vec(12), red);
+    mv3<NP>(p, M_GINV, N, N, vec(6), vec(7), vec(8), vec(0), vec(1), vec(2));
+    mv3<NP>(p, M_CINVT, N, N, vec(6), vec(7), vec(8), vec(12), vec(13), vec(14));
     __syncthreads();
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MODE_THREADS) {
-            a[((size_t)i * nm + m) * N + n] = vec(i)[n];
-            Atil[((size_t)i * N + n) * nm + m] = vec(12 + i)[n];
+            a[so + ((size_t)i * nm + m) * N + n] = vec(i)[n];
+            Atil[((size_t)i * N + n) * nmB + mB] = vec(12 + i)[n];
         }
 }
 
+template <int NP>
 __global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags,
                                                             const double2* __restrict__ P6,
                                                             const double2* __restrict__ a,
                                                             double dtau, double2* __restrict__ uo,
                                                             double2* __restrict__ Y) {
     extern __shared__ double2 sm[];
-    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
-    if (m >= nm) return;
+    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    if (mB >= nmB) return;
+    const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
+    const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     auto vec = [&](int k) { return sm + (size_t)k * N; };
+    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MODE_THREADS) {
             double2 sx = c2(0, 0), sy = c2(0, 0);
             for (int s = 0; s < p.NS; ++s) {
-                sx = cadd(sx, P6[(((size_t)s * 6 + i) * N + n) * nm + m]);
-                sy = cadd(sy, P6[(((size_t)s * 6 + 3 + i) * N + n) * nm + m]);
+                sx = cadd(sx, P6[(((size_t)s * 6 + i) * N + n) * nmB + mB]);
+                sy = cadd(sy, P6[(((size_t)s * 6 + 3 + i) * N + n) * nmB + mB]);
             }
             vec(i)[n] = sx;
             vec(3 + i)[n] = sy;
-            vec(6 + i)[n] = a[((size_t)i * nm + m) * N + n];
+            vec(6 + i)[n] = a[so + ((size_t)i * nm + m) * N + n];
         }
     __syncthreads();
-    mv3(p, M_MA, N, N, vec(0), vec(1), vec(2), vec(9), vec(10), vec(11));
-    __syncthreads();
-    mv3(p, M_MB, N, N, vec(3), vec(4), vec(5), vec(0), vec(1), vec(2));
-    __syncthreads();
-    mv3(p, M_ML, N, N, vec(6), vec(7), vec(8), vec(3), vec(4), vec(5));
+    mv3<NP>(p, M_MA, N, N, vec(0), vec(1), vec(2), vec(9), vec(10), vec(11));
+    mv3<NP>(p, M_MB, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
+    mv3<NP>(p, M_ML, N, N, vec(6), vec(7), vec(8), vec(15), vec(16), vec(17));
     __syncthreads();
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MODE_THREADS) {
-            const double2 adv = cadd(vec(9 + i)[n], vec(i)[n]);
-            const double2 lap = csub(vec(3 + i)[n], cscl(c.k2, vec(6 + i)[n]));
+            const double2 adv = cadd(vec(9 + i)[n], vec(12 + i)[n]);
+            const double2 lap = csub(vec(15 + i)[n], cscl(c.k2, vec(6 + i)[n]));
             vec(9 + i)[n] = cscl(p.lam, csub(cscl(p.nu, lap), adv));
         }
     __syncthreads();
     double2 *F0 = vec(9), *F1 = vec(10), *F2 = vec(11);
     if (flags & GRAD_PROJECT) {
         if (zero)
-            project0(p, vec(9), vec(11), vec(0), vec(1), vec(2));
+            project0<NP>(p, vec(9), vec(11), vec(0), vec(1), vec(2));
         else
-            project(p, m, c, vec(9), vec(10), vec(11), vec(0), vec(1), vec(2), vec(12));
+            project<NP>(p, m, c, vec(9), vec(10), vec(11), vec(0), vec(1), vec(2), vec(12));
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = cscl(-1.0, vec(i)[n]);
         __syncthreads();
@@ -763,48 +840,55 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags,
     if (flags & GRAD_UPDATE) {
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MODE_THREADS) {
-                const size_t gi = ((size_t)i * nm + m) * N + n;
+                const size_t gi = so + ((size_t)i * nm + m) * N + n;
                 const double2 un = cadd(uo[gi], cscl(dtau, Fs[i][n]));
                 uo[gi] = un;
                 vec(3 + i)[n] = un;
             }
         __syncthreads();
-        mv3(p, M_C, N, N, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8));
-        mv3(p, M_CD, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
+        mv3<NP>(p, M_C, N, N, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8));
+        mv3<NP>(p, M_CD, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
         __syncthreads();
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MODE_THREADS) {
-                Y[((size_t)i * N + n) * nm + m] = vec(6 + i)[n];
-                Y[((size_t)(3 + i) * N + n) * nm + m] = vec(12 + i)[n];
+                Y[((size_t)i * N + n) * nmB + mB] = vec(6 + i)[n];
+                Y[((size_t)(3 + i) * N + n) * nmB + mB] = vec(12 + i)[n];
             }
     } else {
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) uo[((size_t)i * nm + m) * N + n] = Fs[i][n];
+            for (int n = t; n < N; n += MODE_THREADS) uo[so + ((size_t)i * nm + m) * N + n] = Fs[i][n];
     }
 }
 
+template <int NP>
 __global__ __launch_bounds__(MODE_THREADS) void k_project(KP p, const double2* __restrict__ g,
                                                           double2* __restrict__ out) {
     extern __shared__ double2 sm[];
-    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
-    if (m >= nm) return;
+    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    if (mB >= nmB) return;
+    const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
+    const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     auto vec = [&](int k) { return sm + (size_t)k * N; };
+    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = g[((size_t)i * nm + m) * N + n];
+        for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = g[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
     if (m == 0)
-        project0(p, vec(0), vec(2), vec(3), vec(4), vec(5));
+        project0<NP>(p, vec(0), vec(2), vec(3), vec(4), vec(5));
     else
-        project(p, m, mscal(p, m), vec(0), vec(1), vec(2), vec(3), vec(4), vec(5), vec(12));
+        project<NP>(p, m, mscal(p, m), vec(0), vec(1), vec(2), vec(3), vec(4), vec(5), vec(12));
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) out[((size_t)i * nm + m) * N + n] = vec(3 + i)[n];
+        for (int n = t; n < N; n += MODE_THREADS) out[so + ((size_t)i * nm + m) * N + n] = vec(3 + i)[n];
 }
 
-// Deterministic column reductions of per-mode partials: out[c] = sum (op 0) or
-// max (op 1) over rows of part[row * stride + c].
+// Deterministic per-guess reductions of per-mode partials: out[g * stride + c]
+// = sum (op 0) or max (op 1) over rows i < n of part[(g * n + i) * stride + c].
+// One work group per guess g.
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part, int n, int stride,
                                                 int op, double* __restrict__ out) {
     __shared__ double red[256];
+    const int g = blockIdx.x;
+    part += (size_t)g * n * stride;
     for (int c = 0; c < stride; ++c) {
         double acc = 0.0;
         for (int i = threadIdx.x; i < n; i += 256) {
@@ -819,39 +903,50 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
                                       : red[threadIdx.x] + red[threadIdx.x + w];
             __syncthreads();
         }
-        if (threadIdx.x == 0) out[c] = red[0];
+        if (threadIdx.x == 0) out[(size_t)g * stride + c] = red[0];
         __syncthreads();
     }
 }
 
 // Per-mode partials of ||u||^2, ||u_b + u||^2 and <curl U, curl U> (U = u_b + u).
+template <int NP>
 __global__ __launch_bounds__(MODE_THREADS) void k_norms(KP p, const double2* __restrict__ u,
                                                         double* __restrict__ part) {
     extern __shared__ double2 sm[];
-    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
-    if (m >= nm) return;
+    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    if (mB >= nmB) return;
+    const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
+    const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     auto vec = [&](int k) { return sm + (size_t)k * N; };
+    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
     const MS c = mscal(p, m);
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = u[((size_t)i * nm + m) * N + n];
+        for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = u[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
-    mv3(p, M_G, N, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
+    mv3<NP>(p, M_G, N, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
     __syncthreads();
     double s0 = 0;
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MODE_THREADS) s0 += vec(i)[n].x * vec(3 + i)[n].x + vec(i)[n].y * vec(3 + i)[n].y;
-    s0 = wsum(s0);
-    __syncthreads();
+    {
+        double tot[1] = {s0};
+        bsum(tot, red);
+        s0 = tot[0];
+    }
     if (m == 0 && t == 0) vec(0)[1] = cadd(vec(0)[1], c2(1.0, 0.0));  // + u_b = T_1(y) e_x
     __syncthreads();
-    mv3(p, M_G, N, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
-    mv(p, M_D, N, N, vec(0), vec(6));
-    mv(p, M_D, N, N, vec(2), vec(7));
+    mv3<NP>(p, M_G, N, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
+    mv<NP>(p, M_D, N, N, vec(0), vec(6));
+    mv<NP>(p, M_D, N, N, vec(2), vec(7));
     __syncthreads();
     double s1 = 0;
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MODE_THREADS) s1 += vec(i)[n].x * vec(3 + i)[n].x + vec(i)[n].y * vec(3 + i)[n].y;
-    s1 = wsum(s1);
+    {
+        double tot[1] = {s1};
+        bsum(tot, red);
+        s1 = tot[0];
+    }
     // vorticity: (D U_z - i b U_y, i b U_x - i a U_z, i a U_y - D U_x)
     for (int n = t; n < N; n += MODE_THREADS) {
         const double2 ux = vec(0)[n], uy = vec(1)[n], uz = vec(2)[n];
@@ -860,32 +955,40 @@ __global__ __launch_bounds__(MODE_THREADS) void k_norms(KP p, const double2* __r
         vec(10)[n] = csub(imul(c.a, uy), vec(6)[n]);
     }
     __syncthreads();
-    mv3(p, M_G, N, N, vec(8), vec(9), vec(10), vec(11), vec(12), vec(13));
+    mv3<NP>(p, M_G, N, N, vec(8), vec(9), vec(10), vec(11), vec(12), vec(13));
     __syncthreads();
     double s2 = 0;
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MODE_THREADS)
             s2 += vec(8 + i)[n].x * vec(11 + i)[n].x + vec(8 + i)[n].y * vec(11 + i)[n].y;
-    s2 = wsum(s2);
+    {
+        double tot[1] = {s2};
+        bsum(tot, red);
+        s2 = tot[0];
+    }
     if (t == 0) {
-        part[(size_t)m * 3 + 0] = c.wgt * s0;
-        part[(size_t)m * 3 + 1] = c.wgt * s1;
-        part[(size_t)m * 3 + 2] = c.wgt * s2;
+        part[(size_t)mB * 3 + 0] = c.wgt * s0;
+        part[(size_t)mB * 3 + 1] = c.wgt * s1;
+        part[(size_t)mB * 3 + 2] = c.wgt * s2;
     }
 }
 
 // Per-mode admissibility defects: max |div|, max |wall value|, Hermitian defect.
+template <int NP>
 __global__ __launch_bounds__(MODE_THREADS) void k_check(KP p, const double2* __restrict__ u,
                                                         double* __restrict__ part) {
     extern __shared__ double2 sm[];
-    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
-    if (m >= nm) return;
+    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    if (mB >= nmB) return;
+    const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
+    const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     auto vec = [&](int k) { return sm + (size_t)k * N; };
+    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
     const MS c = mscal(p, m);
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = u[((size_t)i * nm + m) * N + n];
+        for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = u[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
-    mv(p, M_D, N, N, vec(1), vec(3));
+    mv<NP>(p, M_D, N, N, vec(1), vec(3));
     __syncthreads();
     double dv = 0, herm = 0;
     double wr[6] = {0, 0, 0, 0, 0, 0}, wi[6] = {0, 0, 0, 0, 0, 0};
@@ -903,40 +1006,50 @@ __global__ __launch_bounds__(MODE_THREADS) void k_check(KP p, const double2* __r
             wi[2 * i + 1] += (n & 1) ? -v.y : v.y;
             if (m == 0) herm = fmax(herm, fabs(v.y));
             if (kz == 0 && kx > 0) {
-                const double2 w = u[((size_t)i * nm + mp) * N + n];
+                const double2 w = u[so + ((size_t)i * nm + mp) * N + n];
                 herm = fmax(herm, hypot(w.x - v.x, w.y + v.y));
             }
         }
     }
+    double sums[12];
+    for (int q = 0; q < 6; ++q) {
+        sums[2 * q] = wr[q];
+        sums[2 * q + 1] = wi[q];
+    }
+    bsum(sums, red);
     double wall = 0;
-    for (int q = 0; q < 6; ++q) wall = fmax(wall, hypot(wsum(wr[q]), wsum(wi[q])));
-    dv = wmax(dv);
-    herm = wmax(herm);
+    for (int q = 0; q < 6; ++q) wall = fmax(wall, hypot(sums[2 * q], sums[2 * q + 1]));
+    double mx[2] = {dv, herm};
+    bmax(mx, red);
+    dv = mx[0];
+    herm = mx[1];
     if (t == 0) {
-        part[(size_t)m * 3 + 0] = dv;
-        part[(size_t)m * 3 + 1] = wall;
-        part[(size_t)m * 3 + 2] = herm;
+        part[(size_t)mB * 3 + 0] = dv;
+        part[(size_t)mB * 3 + 1] = wall;
+        part[(size_t)mB * 3 + 2] = herm;
     }
 }
 
 __global__ __launch_bounds__(MODE_THREADS) void k_pack(KP p, const double2* __restrict__ u,
                                                        double* __restrict__ psi) {
-    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
-    if (m >= nm) return;
+    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    if (mB >= nmB) return;
+    const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
+    const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     const int idx = p.indep[m];
     if (idx < 0) return;
     if (m == 0) {
         for (int n = t; n < N - 2; n += MODE_THREADS) {
-            psi[n] = u[(size_t)m * N + n].x;
-            psi[(N - 2) + n] = u[((size_t)2 * nm + m) * N + n].x;
+            psi[(size_t)b * p.nstate + n] = u[so + (size_t)m * N + n].x;
+            psi[(size_t)b * p.nstate + (N - 2) + n] = u[so + ((size_t)2 * nm + m) * N + n].x;
         }
         return;
     }
     const MS c = mscal(p, m);
-    double* o = psi + 2 * (N - 2) + (size_t)idx * (4 * N - 12);
+    double* o = psi + (size_t)b * p.nstate + 2 * (N - 2) + (size_t)idx * (4 * N - 12);
     for (int n = t; n < N; n += MODE_THREADS) {
-        const double2 v = u[((size_t)nm + m) * N + n];
-        const double2 e = csub(imul(c.b, u[(size_t)m * N + n]), imul(c.a, u[((size_t)2 * nm + m) * N + n]));
+        const double2 v = u[so + ((size_t)nm + m) * N + n];
+        const double2 e = csub(imul(c.b, u[so + (size_t)m * N + n]), imul(c.a, u[so + ((size_t)2 * nm + m) * N + n]));
         if (n < N - 4) {
             o[n] = v.x;
             o[(N - 4) + n] = v.y;
@@ -949,34 +1062,39 @@ __global__ __launch_bounds__(MODE_THREADS) void k_pack(KP p, const double2* __re
 }
 
 // Sum over lanes of x[n] (n < lim, n = par mod 2), optionally weighted by n^2.
-__device__ double2 par_sum(const double2* x, int lim, int par, bool sq) {
-    double sr = 0, si = 0;
+__device__ double2 par_sum(const double2* x, int lim, int par, bool sq, double* red) {
+    double v[2] = {0, 0};
     for (int n = threadIdx.x; n < lim; n += MODE_THREADS)
         if ((n & 1) == par) {
             const double w = sq ? (double)n * n : 1.0;
-            sr += w * x[n].x;
-            si += w * x[n].y;
+            v[0] += w * x[n].x;
+            v[1] += w * x[n].y;
         }
-    return c2(wsum(sr), wsum(si));
+    bsum(v, red);
+    return c2(v[0], v[1]);
 }
 
+template <int NP>
 __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __restrict__ psi,
                                                          double2* __restrict__ u) {
     extern __shared__ double2 sm[];
-    const int m = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, t = threadIdx.x;
-    if (m >= nm) return;
+    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    if (mB >= nmB) return;
+    const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
+    const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     const int idx = p.indep[m];
     if (idx < 0) return;
     auto vec = [&](int k) { return sm + (size_t)k * N; };
+    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
     if (m == 0) {
         for (int n = t; n < N; n += MODE_THREADS) {
-            vec(0)[n] = c2(n < N - 2 ? psi[n] : 0.0, 0);
-            vec(1)[n] = c2(n < N - 2 ? psi[(N - 2) + n] : 0.0, 0);
+            vec(0)[n] = c2(n < N - 2 ? psi[(size_t)b * p.nstate + n] : 0.0, 0);
+            vec(1)[n] = c2(n < N - 2 ? psi[(size_t)b * p.nstate + (N - 2) + n] : 0.0, 0);
         }
         __syncthreads();
         for (int f = 0; f < 2; ++f) {  // Dirichlet: each parity class sums to zero
-            const double2 s0 = par_sum(vec(f), N - 2, (N - 2) & 1, false);
-            const double2 s1 = par_sum(vec(f), N - 2, (N - 1) & 1, false);
+            const double2 s0 = par_sum(vec(f), N - 2, (N - 2) & 1, false, red);
+            const double2 s1 = par_sum(vec(f), N - 2, (N - 1) & 1, false, red);
             __syncthreads();
             if (t == 0) {
                 vec(f)[N - 2] = cscl(-1.0, s0);
@@ -985,14 +1103,14 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
             __syncthreads();
         }
         for (int n = t; n < N; n += MODE_THREADS) {
-            u[(size_t)m * N + n] = vec(0)[n];
-            u[((size_t)nm + m) * N + n] = c2(0, 0);
-            u[((size_t)2 * nm + m) * N + n] = vec(1)[n];
+            u[so + (size_t)m * N + n] = vec(0)[n];
+            u[so + ((size_t)nm + m) * N + n] = c2(0, 0);
+            u[so + ((size_t)2 * nm + m) * N + n] = vec(1)[n];
         }
         return;
     }
     const MS c = mscal(p, m);
-    const double* o = psi + 2 * (N - 2) + (size_t)idx * (4 * N - 12);
+    const double* o = psi + (size_t)b * p.nstate + 2 * (N - 2) + (size_t)idx * (4 * N - 12);
     double2 *v = vec(0), *e = vec(1), *Dv = vec(2);
     for (int n = t; n < N; n += MODE_THREADS) {
         v[n] = (n < N - 4) ? c2(o[n], o[(N - 4) + n]) : c2(0, 0);
@@ -1002,7 +1120,7 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
     // clamped v: within each parity class sum v_n = 0 and sum n^2 v_n = 0
     for (int q = N - 2; q < N; ++q) {
         const int pp = q - 2, par = q & 1;
-        const double2 s0 = par_sum(v, pp, par, false), s2 = par_sum(v, pp, par, true);
+        const double2 s0 = par_sum(v, pp, par, false, red), s2 = par_sum(v, pp, par, true, red);
         const double2 vq = cscl(1.0 / ((double)q * q - (double)pp * pp), csub(cscl((double)pp * pp, s0), s2));
         __syncthreads();
         if (t == 0) {
@@ -1012,8 +1130,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
         __syncthreads();
     }
     {
-        const double2 s0 = par_sum(e, N - 2, (N - 2) & 1, false);
-        const double2 s1 = par_sum(e, N - 2, (N - 1) & 1, false);
+        const double2 s0 = par_sum(e, N - 2, (N - 2) & 1, false, red);
+        const double2 s1 = par_sum(e, N - 2, (N - 1) & 1, false, red);
         __syncthreads();
         if (t == 0) {
             e[N - 2] = cscl(-1.0, s0);
@@ -1021,7 +1139,7 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
         }
         __syncthreads();
     }
-    mv(p, M_D, N, N, v, Dv);
+    mv<NP>(p, M_D, N, N, v, Dv);
     __syncthreads();
     const int ikx = m / p.nkz, kz = m - ikx * p.nkz;
     const int mp = ((p.nkx - ikx) % p.nkx) * p.nkz;
@@ -1030,8 +1148,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
         const double2 uz = cscl(c.ik2, cadd(imul(c.b, Dv[n]), imul(c.a, e[n])));
         const double2 vals[3] = {ux, v[n], uz};
         for (int i = 0; i < 3; ++i) {
-            u[((size_t)i * nm + m) * N + n] = vals[i];
-            if (kz == 0) u[((size_t)i * nm + mp) * N + n] = c2(vals[i].x, -vals[i].y);
+            u[so + ((size_t)i * nm + m) * N + n] = vals[i];
+            if (kz == 0) u[so + ((size_t)i * nm + mp) * N + n] = c2(vals[i].x, -vals[i].y);
         }
     }
 }
@@ -1050,18 +1168,37 @@ size_t plane_lds_bytes(const KP& p, int mode) {
     return (size_t)(p.Nx + p.Nz) * 16 + nxf * p.XS * p.nkz * 16 + (size_t)npf * p.XS * p.Nz * 8;
 }
 
-size_t mode_lds_bytes(const KP& p) { return (size_t)MODE_VECS * p.N * 16; }
+size_t mode_lds_bytes(const KP& p) {
+    return (size_t)MODE_VECS * p.N * 16 + (size_t)MODE_WAVES * RED_SLOTS * 8;
+}
 
-static dim3 mode_grid(const KP& p) { return dim3((unsigned)((p.nm + NXCD - 1) / NXCD * NXCD)); }
+static dim3 mode_grid(const KP& p) { return dim3((unsigned)((p.nmB + NXCD - 1) / NXCD * NXCD)); }
+
+// The per-mode kernels are compiled for Ny padded to a multiple of 16 so that
+// every contraction loop is fully unrolled.
+static int padded_ny(const KP& p) { return (p.N + 15) / 16 * 16; }
+
+#define PCFV_DISPATCH_NP(np, ...)                                 \
+    switch (np) {                                                 \
+        case 16: { constexpr int NP = 16; __VA_ARGS__; } break;   \
+        case 32: { constexpr int NP = 32; __VA_ARGS__; } break;   \
+        case 48: { constexpr int NP = 48; __VA_ARGS__; } break;   \
+        case 64: { constexpr int NP = 64; __VA_ARGS__; } break;   \
+        case 80: { constexpr int NP = 80; __VA_ARGS__; } break;   \
+        case 96: { constexpr int NP = 96; __VA_ARGS__; } break;   \
+        case 112: { constexpr int NP = 112; __VA_ARGS__; } break; \
+        case 128: { constexpr int NP = 128; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;                     \
+    }
 
 hipError_t launch_synth(const KP& p, hipStream_t s, const double2* u, double2* Y) {
-    hipLaunchKernelGGL(k_synth, mode_grid(p), dim3(MODE_THREADS), 9 * p.N * 16, s, p, u, Y);
+    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_synth<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, u, Y));
     return hipGetLastError();
 }
 
 hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const double2* Y1, const double2* Y2,
                         double2* out) {
-    const dim3 grid((unsigned)((p.NS * p.N + NXCD - 1) / NXCD * NXCD)), block(PLANE_THREADS);
+    const dim3 grid((unsigned)((p.B * p.NS * p.N + NXCD - 1) / NXCD * NXCD)), block(PLANE_THREADS);
     const size_t lds = plane_lds_bytes(p, mode);
     if (mode == PLANE_FWD)
         hipLaunchKernelGGL(k_plane<PLANE_FWD>, grid, block, lds, s, p, Y1, Y2, out);
@@ -1075,36 +1212,36 @@ hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const double2* Y1,
 hipError_t launch_mode_res(const KP& p, hipStream_t s, int flags, const double2* P3,
                            const double2* u, double2* r, double* cost_part, double2* a,
                            double2* Atil) {
-    hipLaunchKernelGGL(k_mode_res, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, flags,
-                       P3, u, r, cost_part, a, Atil);
+    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_mode_res<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, flags,
+                       P3, u, r, cost_part, a, Atil));
     return hipGetLastError();
 }
 
 hipError_t launch_mode_grad(const KP& p, hipStream_t s, int flags, const double2* P6,
                             const double2* a, double dtau, double2* u_or_out, double2* Y) {
-    hipLaunchKernelGGL(k_mode_grad, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, flags,
-                       P6, a, dtau, u_or_out, Y);
+    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_mode_grad<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, flags,
+                       P6, a, dtau, u_or_out, Y));
     return hipGetLastError();
 }
 
 hipError_t launch_project(const KP& p, hipStream_t s, const double2* g, double2* out) {
-    hipLaunchKernelGGL(k_project, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, g, out);
+    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_project<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, g, out));
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(hipStream_t s, const double* part, int n, int stride, int op,
+hipError_t launch_reduce(hipStream_t s, const double* part, int ngroups, int n, int stride, int op,
                          double* out) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, part, n, stride, op, out);
+    hipLaunchKernelGGL(k_reduce, dim3(ngroups), dim3(256), 0, s, part, n, stride, op, out);
     return hipGetLastError();
 }
 
 hipError_t launch_norms(const KP& p, hipStream_t s, const double2* u, double* part) {
-    hipLaunchKernelGGL(k_norms, mode_grid(p), dim3(MODE_THREADS), 14 * p.N * 16, s, p, u, part);
+    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_norms<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, u, part));
     return hipGetLastError();
 }
 
 hipError_t launch_check(const KP& p, hipStream_t s, const double2* u, double* part) {
-    hipLaunchKernelGGL(k_check, mode_grid(p), dim3(MODE_THREADS), 4 * p.N * 16, s, p, u, part);
+    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_check<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, u, part));
     return hipGetLastError();
 }
 
@@ -1114,7 +1251,7 @@ hipError_t launch_pack(const KP& p, hipStream_t s, const double2* u, double* psi
 }
 
 hipError_t launch_unpack(const KP& p, hipStream_t s, const double* psi, double2* u) {
-    hipLaunchKernelGGL(k_unpack, mode_grid(p), dim3(MODE_THREADS), 3 * p.N * 16, s, p, psi, u);
+    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_unpack<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, psi, u));
     return hipGetLastError();
 }
 

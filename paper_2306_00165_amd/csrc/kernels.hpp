@@ -9,6 +9,8 @@ namespace pcfv {
 // Everything a kernel needs about the discretisation; passed by value.
 struct KP {
     int N, Nx, Nz, nkx, nkz, nm, Kx, Kz;
+    int B, nmB;              // guesses per launch, B * nm
+    long long nstate;        // state-vector length of one guess
     int XS, NS;              // x-slab width of the physical-space kernels, number of slabs
     double lam, nu, alpha, beta;
     const double* M;         // M_COUNT fixed matrices, N x N slots, transposed
@@ -55,7 +57,9 @@ hipError_t launch_mode_res(const KP& p, hipStream_t s, int flags, const double2*
 hipError_t launch_mode_grad(const KP& p, hipStream_t s, int flags, const double2* P6,
                             const double2* a, double dtau, double2* u_or_out, double2* Y);
 hipError_t launch_project(const KP& p, hipStream_t s, const double2* g, double2* out);
-hipError_t launch_reduce(hipStream_t s, const double* part, int n, int stride, int op,
+// Per-guess reductions: out[g * stride + c] = sum (op 0) or max (op 1) over
+// rows i < n of part[(g * n + i) * stride + c], for groups g < ngroups.
+hipError_t launch_reduce(hipStream_t s, const double* part, int ngroups, int n, int stride, int op,
                          double* out);
 hipError_t launch_norms(const KP& p, hipStream_t s, const double2* u, double* part);
 hipError_t launch_check(const KP& p, hipStream_t s, const double2* u, double* part);

@@ -456,6 +456,18 @@ bool build_tables(double Lx, double Lz, double Re, int Nx, int Ny, int Nz, doubl
     store(t.mats, N, M_PVL, PvL);
     store(t.mats, N, M_PVLT, tr(PvL));
     store(t.mats, N, M_PID, PiD);
+    // compositions used by the fused contraction phases of the kernels
+    Mat RD(M, N);
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < N; ++j) RD(i, j) = D(i, j);
+    Mat PRD = mul(Pr, RD), PRDPL = mul(PRD, Pl), DPL = mul(D, Pl);
+    store(t.mats, N, M_PRD, PRD);
+    store(t.mats, N, M_PRDT, tr(PRD));
+    store(t.mats, N, M_PRDPL, PRDPL);
+    store(t.mats, N, M_PRDPLT, tr(PRDPL));
+    store(t.mats, N, M_DPL, DPL);
+    store(t.mats, N, M_DPLT, tr(DPL));
+    store(t.mats, N, M_DPVL, mul(D, PvL));
 
     // -- per-mode tables -------------------------------------------------------------
     const int nm = t.nmodes;

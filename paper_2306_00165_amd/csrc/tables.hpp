@@ -40,6 +40,13 @@ enum FixedMat {
     M_PVL,     // Ny x (Ny-4): clamped basis times the simultaneous eigenvectors X
     M_PVLT,    // (Ny-4) x Ny
     M_PID,     // G-orthogonal projector onto Dirichlet polynomials
+    M_PRD,     // (Ny-2) x Ny: Pr R D
+    M_PRDT,    // Ny x (Ny-2)
+    M_PRDPL,   // (Ny-2) x (Ny-2): Pr R D Pl
+    M_PRDPLT,  // (Ny-2) x (Ny-2)
+    M_DPL,     // Ny x (Ny-2): D Pl
+    M_DPLT,    // (Ny-2) x Ny
+    M_DPVL,    // Ny x (Ny-4): D PvL
     M_COUNT
 };
 

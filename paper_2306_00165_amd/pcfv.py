@@ -35,13 +35,14 @@ EXPORTS = [
 class Config(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_double), ("Lz", ctypes.c_double), ("Re", ctypes.c_double),
                 ("Nx", ctypes.c_int), ("Ny", ctypes.c_int), ("Nz", ctypes.c_int),
-                ("dt_im", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("dt_im", ctypes.c_double), ("precision", ctypes.c_int), ("batch", ctypes.c_int)]
 
 
 class Layout(ctypes.Structure):
     _fields_ = [("Kx", ctypes.c_int), ("Kz", ctypes.c_int), ("Ny", ctypes.c_int),
                 ("nkx", ctypes.c_int), ("nkz", ctypes.c_int), ("n_modes", ctypes.c_longlong),
-                ("n_complex", ctypes.c_longlong), ("n_state", ctypes.c_longlong)]
+                ("n_complex", ctypes.c_longlong), ("n_state", ctypes.c_longlong),
+                ("batch", ctypes.c_int)]
 
 
 class DescentOpts(ctypes.Structure):
@@ -108,8 +109,10 @@ class PcfvError(RuntimeError):
         self.status = status
 
 
-def make_config(Nx, Ny, Nz, Lx=2 * np.pi / 1.14, Lz=2 * np.pi / 2.5, Re=400.0, dt_im=0.25):
-    return Config(float(Lx), float(Lz), float(Re), int(Nx), int(Ny), int(Nz), float(dt_im), 0)
+def make_config(Nx, Ny, Nz, Lx=2 * np.pi / 1.14, Lz=2 * np.pi / 2.5, Re=400.0, dt_im=0.25,
+                batch=1):
+    return Config(float(Lx), float(Lz), float(Re), int(Nx), int(Ny), int(Nz), float(dt_im), 0,
+                  int(batch))
 
 
 def workspace_bytes(cfg):
@@ -132,13 +135,16 @@ def _ptr(t):
 
 
 class Context:
-    """One discretisation (box, Re, grid) on one GPU.  Owns its workspace tensor."""
+    """One discretisation (box, Re, grid) on one GPU, holding `batch` guesses.
+    Owns its workspace tensor.  Fields have shape (3, 2Kx+1, Kz+1, Ny) for
+    batch = 1 and (batch, 3, 2Kx+1, Kz+1, Ny) otherwise."""
 
     def __init__(self, Nx, Ny, Nz, Lx=2 * np.pi / 1.14, Lz=2 * np.pi / 2.5, Re=400.0,
-                 dt_im=0.25, device="cuda:0", stream=None):
+                 dt_im=0.25, device="cuda:0", stream=None, batch=1):
         self.torch = torch
         self.device = torch.device(device)
-        self.cfg = make_config(Nx, Ny, Nz, Lx, Lz, Re, dt_im)
+        self.batch = int(batch)
+        self.cfg = make_config(Nx, Ny, Nz, Lx, Lz, Re, dt_im, self.batch)
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:
             raise PcfvError(EINVAL, "invalid configuration")
@@ -157,7 +163,8 @@ class Context:
         lay = Layout()
         _lib.pcfv_get_layout(self._h, ctypes.byref(lay))
         self.layout = lay
-        self.shape = (3, lay.nkx, lay.nkz, lay.Ny)
+        one = (3, lay.nkx, lay.nkz, lay.Ny)
+        self.shape = one if self.batch == 1 else (self.batch,) + one
         self.n_state = lay.n_state
 
     def __del__(self):
@@ -185,18 +192,26 @@ class Context:
         return self.torch.empty(self.shape, dtype=self.torch.complex128, device=self.device)
 
     # -- the C ABI -----------------------------------------------------------
+    def _scalars(self, n):
+        return (ctypes.c_double * (n * self.batch))()
+
+    def _unbatch(self, vals, n):
+        vals = list(vals)
+        rows = [tuple(vals[i * n:(i + 1) * n]) if n > 1 else vals[i] for i in range(self.batch)]
+        return rows[0] if self.batch == 1 else rows
+
     def residual(self, u, want_cost=False):
         u = self._field(u)
         r = self.empty()
-        c = ctypes.c_double(0.0)
-        self._check(_lib.pcfv_residual(self._h, _ptr(u), _ptr(r), ctypes.byref(c) if want_cost else None))
-        return (r, c.value) if want_cost else r
+        c = self._scalars(1)
+        self._check(_lib.pcfv_residual(self._h, _ptr(u), _ptr(r), c if want_cost else None))
+        return (r, self._unbatch(c, 1)) if want_cost else r
 
     def cost(self, u):
         u = self._field(u)
-        c = ctypes.c_double(0.0)
-        self._check(_lib.pcfv_cost(self._h, _ptr(u), ctypes.byref(c)))
-        return c.value
+        c = self._scalars(1)
+        self._check(_lib.pcfv_cost(self._h, _ptr(u), c))
+        return self._unbatch(c, 1)
 
     def jvp(self, u, v):
         u, v = self._field(u), self._field(v)
@@ -232,26 +247,27 @@ class Context:
 
     def norms(self, u):
         u = self._field(u)
-        out = (ctypes.c_double * 3)()
+        out = self._scalars(3)
         self._check(_lib.pcfv_norms(self._h, _ptr(u), out))
-        return tuple(out)
+        return self._unbatch(out, 3)
 
     def check_state(self, u):
         u = self._field(u)
-        out = (ctypes.c_double * 3)()
+        out = self._scalars(3)
         self._check(_lib.pcfv_check_state(self._h, _ptr(u), out))
-        return tuple(out)
+        return self._unbatch(out, 3)
 
     def pack(self, u):
         u = self._field(u)
-        psi = self.torch.empty(self.n_state, dtype=self.torch.float64, device=self.device)
+        shape = (self.n_state,) if self.batch == 1 else (self.batch, self.n_state)
+        psi = self.torch.empty(shape, dtype=self.torch.float64, device=self.device)
         self._check(_lib.pcfv_pack_state(self._h, _ptr(u), _ptr(psi)))
         return psi
 
     def unpack(self, psi):
         t = self.torch
         psi = t.as_tensor(psi).to(self.device, t.float64).contiguous()
-        if psi.numel() != self.n_state:
+        if psi.numel() != self.n_state * self.batch:
             raise ValueError("psi has the wrong length")
         u = self.empty()
         self._check(_lib.pcfv_unpack_state(self._h, _ptr(psi), _ptr(u)))

@@ -239,3 +239,36 @@ def test_metric_descent_step_matches_oracle_direction(metric):
     e = rel(to_np(u) - u0, want - u0)
     print(f"[gpu] 48x49x48 descent step rel err {e:.3e}")
     assert e < TOL_ADJ49
+
+
+# -- several guesses in one context ---------------------------------------------------
+
+def test_batched_guesses_match_single_guess_oracle():
+    """Three different guesses advanced together: each matches the oracle run
+    on that guess alone (residual, costs, norms, 5 descent steps, state vector)."""
+    import torch
+    from paper_2306_00165_amd.pcfv import Context
+    g = Grid(16, 25, 16)
+    m = Method(g)
+    us = [inputs.random_field(16, 25, 16, energy=e, seed=s) for s, e in [(21, 1e-3), (22, 3e-3), (23, 2e-3)]]
+    c = Context(16, 25, 16, batch=3)
+    U = torch.as_tensor(np.stack(us)).to("cuda:0").contiguous()
+    r, costs = c.residual(U, want_cost=True)
+    r = to_np(r)
+    for b in range(3):
+        rr = m.residual(us[b])
+        assert rel(r[b], rr) < TOL
+        assert abs(costs[b] - m.inner(rr, rr)) < TOL * costs[b]
+        n0, n1, d = c.norms(U)[b]
+        assert abs(n1 - m.total_norm(us[b])) < 1e-13 * n1
+    psi = to_np(c.pack(U))
+    for b in range(3):
+        np.testing.assert_allclose(psi[b], state.pack(g, us[b]), rtol=0, atol=1e-15 * np.abs(psi).max())
+    st, rep = c.descend(U, max_steps=5, dtau=0.02, check_every=2)
+    assert st == 0 and rep["steps"] == 5
+    for b in range(3):
+        ub = us[b]
+        for _ in range(5):
+            ub, _ = m.descent_step(ub, 0.02)
+        assert rel(to_np(U[b]), ub) < TOL
+    assert max(max(d) for d in c.check_state(U)) < 1e-15

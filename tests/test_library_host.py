@@ -39,7 +39,8 @@ def test_invalid_configs_are_rejected(bad):
 def _tables(dims, **kw):
     cfg = pcfv.make_config(*dims, **kw)
     N = dims[1]
-    t = {"mats": pcfv.host_table(cfg, 0).reshape(20, N, N)}
+    mats = pcfv.host_table(cfg, 0)
+    t = {"mats": mats.reshape(len(mats) // (N * N), N, N)}
     for name, idx, shape in [("minfo", 1, (-1, 8)), ("dH", 2, (-1, N)), ("dP", 3, (-1, N)),
                              ("dproj", 4, (-1, N)), ("Vk", 5, (-1, 4, N)), ("DVk", 6, (-1, 4, N)),
                              ("Ainv", 7, (-1, 4, 4)), ("mu", 8, (-1,))]:
@@ -85,42 +86,84 @@ def test_tau_helmholtz_eigenbasis_solves_the_tau_system(dims):
         np.testing.assert_allclose(x, want, rtol=0, atol=1e-13 * np.abs(want).max())
 
 
+SLOT = dict(C=0, CD=1, CINV=2, CINVT=3, D=4, D2=5, DT=6, G=7, GINV=8, PL=9, PR=10, PLT=11,
+            PRT=12, MA=13, MB=14, ML=15, DTG=16, PVL=17, PVLT=18, PID=19, PRD=20, PRDT=21,
+            PRDPL=22, PRDPLT=23, DPL=24, DPLT=25, DPVL=26)
+
+
+def _replay_stokes(t, N, mm, Fx, Fy, Fz):
+    """The kernel's fused influence-matrix Stokes solve, replayed in numpy."""
+    M = N - 2
+    A = lambda k, o, i: _mat(t, SLOT[k], o, i)  # noqa: E731
+    a, b, k2, ik2, sig = t["minfo"][mm][:5]
+    dH, dP = t["dH"][mm][:M], t["dP"][mm][:M]
+    Fh, Fe = 1j * a * Fx + 1j * b * Fz, 1j * b * Fx - 1j * a * Fz
+    PR = A("PR", M, M)
+    s1, s2, s3 = PR @ Fh[:M], PR @ Fe[:M], PR @ Fy[:M]
+    s4 = A("PRD", M, N) @ Fy
+    t1 = -dP * (s4 + s1)
+    te = dH * s2
+    t2 = dH * (s3 - A("PRDPL", M, M) @ t1)
+    PL = A("PL", N, M)
+    v0, Dv0, eta = PL @ t2, A("DPL", N, M) @ t2, PL @ te
+    p0last = PL[N - 1] @ t1
+    e = np.array([Dv0.sum(), (Dv0 * (-1.0) ** np.arange(N)).sum(),
+                  sig * v0[N - 2] + 2 * (N - 1) * p0last - Fy[N - 2], sig * v0[N - 1] - Fy[N - 1]])
+    c = -t["Ainv"][mm] @ e
+    v = v0 + t["Vk"][mm].T @ c
+    Dv = Dv0 + t["DVk"][mm].T @ c
+    return np.array([ik2 * (1j * a * Dv - 1j * b * eta), v, ik2 * (1j * b * Dv + 1j * a * eta)])
+
+
+def _replay_stokes_h(t, N, mm, xu, xv, xw):
+    """The kernel's conjugate-transposed Stokes solve, replayed in numpy."""
+    M = N - 2
+    A = lambda k, o, i: _mat(t, SLOT[k], o, i)  # noqa: E731
+    a, b, k2, ik2, sig = t["minfo"][mm][:5]
+    dH, dP = t["dH"][mm][:M], t["dP"][mm][:M]
+    bDv = ik2 * (-1j * a * xu - 1j * b * xw)
+    beta = ik2 * (1j * b * xu - 1j * a * xw)
+    bc = t["Vk"][mm] @ xv + t["DVk"][mm] @ bDv
+    be = -t["Ainv"][mm].T @ bc
+    bv0 = xv.copy()
+    bv0[N - 2] += sig * be[2]
+    bv0[N - 1] += sig * be[3]
+    bDv0 = bDv + be[0] + (-1.0) ** np.arange(N) * be[1]
+    u2 = dH * (A("PLT", M, N) @ bv0 + A("DPLT", M, N) @ bDv0)
+    bs2 = dH * (A("PLT", M, N) @ beta)
+    bt1 = A("PL", N, M)[N - 1] * (2 * (N - 1) * be[2]) - A("PRDPLT", M, M) @ u2
+    bs1 = -dP * bt1
+    PRT = A("PRT", M, M)
+    pad = lambda x: np.concatenate([x, np.zeros(2)])  # noqa: E731
+    bFh, bFe = pad(PRT @ bs1), pad(PRT @ bs2)
+    bFy = pad(PRT @ u2) + A("PRDT", N, M) @ bs1
+    bFy[N - 2] -= be[2]
+    bFy[N - 1] -= be[3]
+    return np.array([-1j * a * bFh - 1j * b * bFe, bFy, -1j * b * bFh + 1j * a * bFe])
+
+
 @pytest.mark.parametrize("dims", [(16, 25, 16), (32, 33, 32)])
 def test_influence_matrix_replay_matches_dense_tau_solve(dims):
-    """Replaying the kernel's influence-matrix algorithm on the library tables
-    reproduces the oracle's dense Chebyshev-tau Stokes solve, and its
-    transpose reproduces the oracle's transposed solve."""
+    """Replaying the kernel's influence-matrix algorithm (the same fused
+    contraction phases, on the library tables) reproduces the oracle's dense
+    Chebyshev-tau Stokes solve, and its transpose reproduces the oracle's
+    conjugate-transposed solve."""
     g = Grid(*dims)
     m = Method(g)
     t = _tables(dims)
-    N, M = g.N, g.N - 2
-    D = _mat(t, 4, N, N)
-    Pl, Pr = _mat(t, 9, N, M), _mat(t, 10, M, M)
+    N = g.N
     F = inputs.random_field(*dims, energy=1.0, seed=5)
     F = F + 0.3 * np.roll(F, 1, axis=0)
-    ref = m.S.solve(F)
+    X = inputs.random_field(*dims, energy=1.0, seed=7) @ m.G.T
+    ref, refh = m.S.solve(F), m.S.solve_h(X)
     for (ikx, kz) in g.modes():
         mm = ikx * g.nkz + kz
         if mm == 0:
             continue
-        a, b, k2, ik2, sig = t["minfo"][mm][:5]
-        Fx, Fy, Fz = F[:, ikx, kz]
-
-        def hs(f, d):
-            return Pl @ (d[:M] * (Pr @ f[:M]))
-
-        Fh, Fe = 1j * a * Fx + 1j * b * Fz, 1j * b * Fx - 1j * a * Fz
-        p0 = hs(-(D @ Fy + Fh), t["dP"][mm])
-        v0 = hs(Fy - D @ p0, t["dH"][mm])
-        Dv0 = D @ v0
-        e = np.array([Dv0.sum(), (Dv0 * (-1.0) ** np.arange(N)).sum(),
-                      sig * v0[N - 2] + 2 * (N - 1) * p0[N - 1] - Fy[N - 2], sig * v0[N - 1] - Fy[N - 1]])
-        c = -t["Ainv"][mm] @ e
-        v = v0 + t["Vk"][mm].T @ c
-        Dv = Dv0 + t["DVk"][mm].T @ c
-        eta = hs(Fe, t["dH"][mm])
-        out = np.array([ik2 * (1j * a * Dv - 1j * b * eta), v, ik2 * (1j * b * Dv + 1j * a * eta)])
+        out = _replay_stokes(t, N, mm, *F[:, ikx, kz])
         np.testing.assert_allclose(out, ref[:, ikx, kz], rtol=0, atol=1e-14 * np.abs(ref).max())
+        outh = _replay_stokes_h(t, N, mm, *X[:, ikx, kz])
+        np.testing.assert_allclose(outh, refh[:, ikx, kz], rtol=0, atol=1e-12 * np.abs(refh).max())
 
 
 @pytest.mark.parametrize("dims", [(16, 25, 16), (12, 17, 9)])
@@ -142,9 +185,10 @@ def test_projection_tables_replay_matches_oracle_projection(dims):
         else:
             a, b, k2, ik2 = t["minfo"][mm][:4]
             gh, ge = 1j * a * gx + 1j * b * gz, 1j * b * gx - 1j * a * gz
-            bv = G @ gy - ik2 * (D.T @ (G @ gh))
-            v = PvL @ (t["dproj"][mm][:N - 4] * (PvL.T @ bv))
+            bv = G @ gy - ik2 * (_mat(t, 16, N, N) @ gh)
+            t4 = t["dproj"][mm][:N - 4] * (_mat(t, 18, N - 4, N) @ bv)
+            v = PvL @ t4
             eta = PiD @ ge
-            Dv = D @ v
+            Dv = _mat(t, 26, N, N - 4) @ t4
             out = np.array([ik2 * (1j * a * Dv - 1j * b * eta), v, ik2 * (1j * b * Dv + 1j * a * eta)])
         np.testing.assert_allclose(out, ref[:, ikx, kz], rtol=0, atol=1e-13 * np.abs(X).max())
