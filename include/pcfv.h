@@ -134,7 +134,8 @@ pcfv_status pcfv_adjoint(pcfv_ctx* ctx, const double* u, const double* w, double
  * (Sec. 3.4). g any Hermitian-consistent field.  Pg may equal g (in place). */
 pcfv_status pcfv_project(pcfv_ctx* ctx, const double* g, double* Pg);
 
-/* One or more descent steps (Sec. 4 step (5)). */
+/* One or more descent steps (Sec. 4 step (5)), optionally accelerated by DMD
+ * extrapolation (Sec. 6.2). */
 typedef struct {
     long long max_steps;  /* steps to take at most                                  */
     double dtau;          /* forward-Euler step (the paper: 0.03 at 32x31x32)         */
@@ -143,6 +144,19 @@ typedef struct {
     double grow_tol;      /* cost growth factor between checks that counts as
                              divergence (<= 0: disabled)                             */
     int max_halvings;     /* dtau halvings allowed on divergence                      */
+    /* DMD (Sec. 6.2): snapshots every dmd_stride steps; after dmd_window of them
+     * the window is extrapolated (pcfv_dmd_extrapolate) and each guess whose
+     * extrapolated cost is below dmd_accept times its current cost restarts
+     * from it; the next window starts dmd_gap steps later.  Windows start only
+     * once every guess has J = sqrt(J^2) < dmd_start (<= 0: at once).
+     * dmd_window = 0 disables DMD.  dmd_buffer: device memory for
+     * dmd_window * batch * n_state doubles, caller-owned. */
+    int dmd_window;
+    int dmd_stride;
+    int dmd_gap;
+    double dmd_start;
+    double dmd_accept;
+    double* dmd_buffer;
 } pcfv_descent_opts;
 
 typedef struct {
@@ -152,6 +166,8 @@ typedef struct {
     double rel_res;       /* ||r||_W / ||u_b + u||_W at the last check               */
     double dtau_final;
     int n_halvings;
+    int n_dmd;            /* DMD extrapolations performed                            */
+    int n_dmd_accepted;   /* guesses restarted from an extrapolated state             */
 } pcfv_descent_report;
 
 /* Advance every guess of u in place with the same dtau.  Returns PCFV_OK when
@@ -162,6 +178,18 @@ typedef struct {
  * the largest cost and relative residual over the guesses. */
 pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* opts,
                          pcfv_descent_report* report);
+
+/* DMD extrapolation (Sec. 6) of each guess.  snaps: device, [M][batch][n_state]
+ * minimal state vectors (pcfv_pack_state), oldest first, consecutive ones
+ * dtau_snap apart, 3 <= M <= 256.  For r = 1..r* (r* = numerical rank of the
+ * window, singular values above 1e-7 of the largest) the steady state
+ * Re(b_1 phi_1) of the rank-r exact DMD (mode with the smallest |omega|,
+ * amplitudes fitted at the last snapshot) is formed and its cost evaluated;
+ * the cheapest is written to u_out (batch fields), its cost to cost_host[b]
+ * and r to rank_host[b] (either may be NULL).  A guess whose window has rank 0
+ * gets its last snapshot and rank 0.  Synchronises. */
+pcfv_status pcfv_dmd_extrapolate(pcfv_ctx* ctx, const double* snaps, int M, double dtau_snap,
+                                 double* u_out, double* cost_host, int* rank_host);
 
 /* Norms per guess b: out_host[3b] = ||u||_W, out_host[3b+1] = ||u_b + u||_W,
  * out_host[3b+2] = D = <curl U, curl U>_W (so that laminar flow has D = 1,
@@ -202,6 +230,16 @@ const char* pcfv_last_error(const pcfv_ctx* ctx);
  * second derivative.  Copies min(cap, size) doubles to out (if non-NULL) and
  * returns the table size in doubles, or 0 if cfg or which is invalid. */
 size_t pcfv_host_table(const pcfv_config* cfg, int which, double* out, size_t cap);
+
+/* Host-side DMD algebra of Sec. 6.1-6.2 (for tests, no device): given the
+ * M x M Gram matrix Ge = Ge_hi + Ge_lo (row-major, an unevaluated sum of two
+ * doubles per entry; Ge_lo may be NULL) of E = [psi_1, psi_2 - psi_1, ..,
+ * psi_M - psi_{M-1}], writes for r = 1..r* the M-1 coefficients c with steady
+ * state psi_s(r) = sum_k c_k psi_{k+2} into coef[(r-1)(M-1) + k] (at most cap
+ * doubles) and returns r* (singular values of [psi_1..psi_{M-1}] above 1e-7
+ * times the largest), or -1 on invalid input.  3 <= M <= 256. */
+int pcfv_host_dmd(const double* Ge_hi, const double* Ge_lo, int M, double dtau, double* coef,
+                  size_t cap);
 
 #ifdef __cplusplus
 }

@@ -31,4 +31,4 @@ library routines, brute force on tiny grids and invariants of the method.
 """
 
 from .grid import Grid  # noqa: F401
-from . import cheb, flow, stokes, method  # noqa: F401
+from . import cheb, flow, stokes, method, state, dmd  # noqa: F401

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libpcfv.so")
-SOURCES = ["csrc/tables.cpp", "csrc/kernels.hip", "csrc/capi.cpp"]
+SOURCES = ["csrc/tables.cpp", "csrc/dmd.cpp", "csrc/kernels.hip", "csrc/capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -6,10 +6,12 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
 #include "../../include/pcfv.h"
+#include "dmd.hpp"
 #include "kernels.hpp"
 #include "tables.hpp"
 
@@ -19,7 +21,8 @@ namespace {
 
 enum WsSlot {
     W_MATS, W_MINFO, W_DH, W_DP, W_DPROJ, W_VK, W_DVK, W_AINV, W_TWX, W_TWZ, W_YGL, W_INDEP,
-    W_Y, W_YV, W_ATIL, W_P3, W_P6, W_A, W_R, W_CK, W_TMP, W_PART, W_SCAL, W_COUNT
+    W_Y, W_YV, W_ATIL, W_P3, W_P6, W_A, W_R, W_CK, W_TMP, W_PART, W_SCAL, W_DMDG, W_DMDC, W_DMDPSI,
+    W_COUNT
 };
 
 struct WsLayout {
@@ -29,6 +32,7 @@ struct WsLayout {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxPlaneLds = 64 * 1024;
+constexpr int kMaxDmd = 256;   // largest DMD window
 
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -106,6 +110,10 @@ WsLayout layout(const pcfv_config& c) {
     sz[W_A] = sz[W_R] = sz[W_CK] = sz[W_TMP] = 3 * nmB * N * 16;
     sz[W_PART] = nmB * 4 * 8;
     sz[W_SCAL] = (64 + 4 * B) * 8;
+    const long long nstate = 4LL * (p.Kx + 2LL * p.Kx * p.Kz + p.Kz) * (p.N - 3) + 2LL * (p.N - 2);
+    sz[W_DMDG] = B * kMaxDmd * kMaxDmd * 16;
+    sz[W_DMDC] = B * kMaxDmd * 8;
+    sz[W_DMDPSI] = B * (size_t)nstate * 8;
     WsLayout L;
     size_t o = 0;
     for (int i = 0; i < W_COUNT; ++i) {
@@ -126,7 +134,7 @@ struct pcfv_ctx {
     WsLayout L;
     KP kp;
     double2 *Y, *Yv, *Atil, *P3, *P6, *a, *r, *ck, *tmp;
-    double *part, *scal;
+    double *part, *scal, *dmdG, *dmdC, *dmdPsi;
     std::string err;
 
     template <class T>
@@ -211,6 +219,68 @@ pcfv_status descent_step(pcfv_ctx* ctx, double* u, double dtau) {
     return PCFV_OK;
 }
 
+
+// DMD extrapolation of the window snaps ([M][B][n_state]); writes the best
+// candidate of each guess to u_out (last snapshot if none), its cost and rank.
+pcfv_status dmd_core(pcfv_ctx* ctx, const double* snaps, int M, double dtau, double* u_out,
+                     std::vector<double>& best_cost, std::vector<int>& best_rank) {
+    const KP& p = ctx->kp;
+    const int B = p.B;
+    const long long n = p.nstate;
+    const size_t gbytes = (size_t)M * M * 2 * sizeof(double);
+    const size_t fbytes1 = (size_t)3 * p.nm * p.N * 16;   // one guess's field
+    if (M < 3 || M > kMaxDmd) return fail(ctx, PCFV_EINVAL, "DMD window must hold 3..256 snapshots");
+    PCFV_TRY(launch_dmd_gram(ctx->stream, snaps, M, B, n, ctx->dmdG), "dmd gram");
+    std::vector<double> G((size_t)B * M * M * 2);
+    PCFV_TRY(hipMemcpyAsync(G.data(), ctx->dmdG, (size_t)B * gbytes, hipMemcpyDeviceToHost, ctx->stream),
+             "copy gram");
+    PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
+    std::vector<std::vector<std::vector<double>>> coef(B);
+    std::vector<int> rstar(B, 0);
+    int rmax = 0;
+    for (int b = 0; b < B; ++b) {
+        std::vector<long double> Gb((size_t)M * M);
+        for (size_t k = 0; k < Gb.size(); ++k)
+            Gb[k] = (long double)G[((size_t)b * M * M + k) * 2] + (long double)G[((size_t)b * M * M + k) * 2 + 1];
+        std::vector<double> om;
+        std::string err;
+        const int r = dmd_candidates(Gb, M, dtau, coef[b], om, err);
+        if (r < 0) return fail(ctx, PCFV_EINVAL, err);
+        rstar[b] = r;
+        rmax = std::max(rmax, r);
+    }
+    best_cost.assign(B, std::numeric_limits<double>::infinity());
+    best_rank.assign(B, 0);
+    // fallback: the last snapshot
+    PCFV_TRY(launch_unpack(p, ctx->stream, snaps + (size_t)(M - 1) * B * n, dd(u_out)), "unpack");
+    std::vector<double> cvec((size_t)B * (M - 1));
+    std::vector<double> costs(B);
+    for (int r = 1; r <= rmax; ++r) {
+        for (int b = 0; b < B; ++b)
+            for (int k = 0; k < M - 1; ++k)
+                cvec[(size_t)b * (M - 1) + k] = (r <= rstar[b]) ? coef[b][r - 1][k] : 0.0;
+        PCFV_TRY(hipMemcpyAsync(ctx->dmdC, cvec.data(), cvec.size() * sizeof(double), hipMemcpyHostToDevice,
+                                ctx->stream),
+                 "copy coefficients");
+        PCFV_TRY(launch_dmd_combine(ctx->stream, snaps, M, B, n, ctx->dmdC, ctx->dmdPsi), "dmd combine");
+        PCFV_TRY(launch_unpack(p, ctx->stream, ctx->dmdPsi, ctx->tmp), "unpack");
+        PCFV_TRY(launch_synth(p, ctx->stream, ctx->tmp, ctx->Y), "synth");
+        pcfv_status st = residual_core(ctx, reinterpret_cast<const double*>(ctx->tmp), nullptr, true);
+        if (st != PCFV_OK) return st;
+        st = read_scalars(ctx, 1, 0, costs.data());
+        if (st != PCFV_OK) return st;
+        for (int b = 0; b < B; ++b)
+            if (r <= rstar[b] && std::isfinite(costs[b]) && costs[b] < best_cost[b]) {
+                best_cost[b] = costs[b];
+                best_rank[b] = r;
+                PCFV_TRY(hipMemcpyAsync(u_out + (size_t)b * 3 * p.nm * p.N * 2,
+                                        reinterpret_cast<const char*>(ctx->tmp) + b * fbytes1, fbytes1,
+                                        hipMemcpyDeviceToDevice, ctx->stream),
+                         "copy candidate");
+            }
+    }
+    return PCFV_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -282,6 +352,9 @@ pcfv_status pcfv_create(const pcfv_config* cfg, void* hip_stream, void* workspac
     ctx->tmp = ctx->at<double2>(W_TMP);
     ctx->part = ctx->at<double>(W_PART);
     ctx->scal = ctx->at<double>(W_SCAL);
+    ctx->dmdG = ctx->at<double>(W_DMDG);
+    ctx->dmdC = ctx->at<double>(W_DMDC);
+    ctx->dmdPsi = ctx->at<double>(W_DMDPSI);
     struct Up {
         int slot;
         const void* src;
@@ -380,12 +453,17 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
     if (o->max_steps < 0 || !(o->dtau > 0) || o->check_every < 1 || o->max_halvings < 0 ||
         !(o->rel_tol >= 0))
         return fail(ctx, PCFV_EINVAL, "invalid descent options");
+    const bool use_dmd = o->dmd_window > 0;
+    if (use_dmd && (o->dmd_window < 3 || o->dmd_window > kMaxDmd || o->dmd_stride < 1 || o->dmd_gap < 0 ||
+                    !o->dmd_buffer || !(o->dmd_accept > 0)))
+        return fail(ctx, PCFV_EINVAL, "invalid DMD options");
     const KP& p = ctx->kp;
     const int B = p.B;
     const size_t fbytes = (size_t)ctx->nfield() * 16;
+    const size_t fbytes1 = (size_t)3 * p.nm * p.N * 16;
     double dtau = o->dtau, tau = 0;
     long long steps = 0;
-    int halvings = 0;
+    int halvings = 0, n_dmd = 0, n_acc = 0;
     std::vector<double> cost, ntot, cost_prev;
     pcfv_descent_report local{};
     if (!rep) rep = &local;
@@ -395,13 +473,16 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
             w = std::max(w, ntot[b] > 0 ? std::sqrt(std::max(cost[b], 0.0)) / ntot[b] : 0.0);
         return w;
     };
+    auto max_cost = [&]() { return cost.empty() ? 0.0 : *std::max_element(cost.begin(), cost.end()); };
     auto report = [&](pcfv_status st) {
         rep->steps = steps;
         rep->tau = tau;
-        rep->cost = cost.empty() ? 0.0 : *std::max_element(cost.begin(), cost.end());
+        rep->cost = max_cost();
         rep->rel_res = cost.empty() ? 0.0 : worst_rel();
         rep->dtau_final = dtau;
         rep->n_halvings = halvings;
+        rep->n_dmd = n_dmd;
+        rep->n_dmd_accepted = n_acc;
         return st;
     };
     auto finite = [&]() {
@@ -415,16 +496,64 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
     if (!finite()) return report(fail(ctx, PCFV_ENAN, "cost is not finite"));
     cost_prev = cost;
     if (o->rel_tol > 0 && worst_rel() < o->rel_tol) return report(PCFV_OK);
+    bool window = false;
+    int nsnap = 0;
+    long long next_snap = 0, window_start = 0, since_check = 0;
+    if (o->grow_tol > 0)
+        PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
     while (steps < o->max_steps) {
-        const long long k = std::min<long long>(o->check_every, o->max_steps - steps);
-        if (o->grow_tol > 0)
-            PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
+        if (use_dmd && !window && steps >= window_start &&
+            (o->dmd_start <= 0 || std::sqrt(std::max(max_cost(), 0.0)) < o->dmd_start)) {
+            window = true;
+            nsnap = 0;
+            next_snap = steps;
+        }
+        if (window && steps == next_snap) {
+            PCFV_TRY(launch_pack(p, ctx->stream, cd(u), o->dmd_buffer + (size_t)nsnap * B * p.nstate), "pack");
+            ++nsnap;
+            next_snap += o->dmd_stride;
+            if (nsnap == o->dmd_window) {
+                std::vector<double> cnow, nnow, dcost;
+                std::vector<int> drank;
+                s = cost_and_norm(ctx, u, cnow, nnow);
+                if (s != PCFV_OK) return s;
+                double2* cand = ctx->a;   // scratch: recomputed by every step
+                s = dmd_core(ctx, o->dmd_buffer, o->dmd_window, o->dmd_stride * dtau,
+                             reinterpret_cast<double*>(cand), dcost, drank);
+                if (s != PCFV_OK) return s;
+                ++n_dmd;
+                for (int b = 0; b < B; ++b)
+                    if (drank[b] > 0 && dcost[b] < o->dmd_accept * cnow[b]) {
+                        PCFV_TRY(hipMemcpyAsync(reinterpret_cast<char*>(u) + b * fbytes1,
+                                                reinterpret_cast<const char*>(cand) + b * fbytes1, fbytes1,
+                                                hipMemcpyDeviceToDevice, ctx->stream),
+                                 "accept");
+                        ++n_acc;
+                    }
+                PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth");
+                s = cost_and_norm(ctx, u, cost, ntot);
+                if (s != PCFV_OK) return s;
+                cost_prev = cost;
+                if (o->grow_tol > 0)
+                    PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
+                window = false;
+                window_start = steps + o->dmd_gap;
+                since_check = 0;
+                if (o->rel_tol > 0 && worst_rel() < o->rel_tol) return report(PCFV_OK);
+                continue;
+            }
+        }
+        long long k = std::min<long long>(o->check_every - since_check, o->max_steps - steps);
+        if (window) k = std::min<long long>(k, next_snap - steps);
         for (long long i = 0; i < k; ++i) {
             s = descent_step(ctx, u, dtau);
             if (s != PCFV_OK) return s;
         }
         steps += k;
         tau += k * dtau;
+        since_check += k;
+        if (since_check < o->check_every && steps < o->max_steps) continue;
+        since_check = 0;
         s = cost_and_norm(ctx, u, cost, ntot);
         if (s != PCFV_OK) return s;
         if (!finite()) return report(fail(ctx, PCFV_ENAN, "cost is not finite"));
@@ -432,9 +561,8 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
         for (int b = 0; b < B; ++b) grew |= (o->grow_tol > 0 && cost[b] > o->grow_tol * cost_prev[b]);
         if (grew) {
             PCFV_TRY(hipMemcpyAsync(u, ctx->ck, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "restore");
-            steps -= k;
-            tau -= k * dtau;
             cost = cost_prev;
+            window = false;
             if (halvings >= o->max_halvings) {
                 PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
                 return report(fail(ctx, PCFV_EDIVERGED, "cost grew beyond grow_tol"));
@@ -445,11 +573,27 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
             continue;
         }
         cost_prev = cost;
+        if (o->grow_tol > 0)
+            PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
         if (o->rel_tol > 0 && worst_rel() < o->rel_tol) return report(PCFV_OK);
     }
     return report(o->rel_tol > 0 ? fail(ctx, PCFV_ENOTCONV, "max_steps reached above rel_tol") : PCFV_OK);
 }
 
+pcfv_status pcfv_dmd_extrapolate(pcfv_ctx* ctx, const double* snaps, int M, double dtau_snap,
+                                 double* u_out, double* cost_host, int* rank_host) {
+    if (!ctx || !snaps || !u_out) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    std::vector<double> cost;
+    std::vector<int> rank;
+    pcfv_status s = dmd_core(ctx, snaps, M, dtau_snap, u_out, cost, rank);
+    if (s != PCFV_OK) return s;
+    for (int b = 0; b < ctx->kp.B; ++b) {
+        if (cost_host) cost_host[b] = cost[b];
+        if (rank_host) rank_host[b] = rank[b];
+    }
+    PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
+    return PCFV_OK;
+}
 
 pcfv_status pcfv_norms(pcfv_ctx* ctx, const double* u, double* out_host) {
     if (!ctx || !u || !out_host) return fail(ctx, PCFV_EINVAL, "NULL argument");
@@ -527,6 +671,24 @@ pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* 
 }
 
 const char* pcfv_last_error(const pcfv_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+int pcfv_host_dmd(const double* Ge_hi, const double* Ge_lo, int M, double dtau, double* coef,
+                  size_t cap) {
+    if (!Ge_hi || M < 3 || M > kMaxDmd) return -1;
+    std::vector<long double> G((size_t)M * M);
+    for (size_t k = 0; k < G.size(); ++k)
+        G[k] = (long double)Ge_hi[k] + (Ge_lo ? (long double)Ge_lo[k] : 0.0L);
+    std::vector<std::vector<double>> c;
+    std::vector<double> om;
+    std::string err;
+    const int r = dmd_candidates(G, M, dtau, c, om, err);
+    if (r < 0) return -1;
+    size_t k = 0;
+    for (const auto& row : c)
+        for (double v : row)
+            if (coef && k < cap) coef[k++] = v;
+    return r;
+}
 
 size_t pcfv_host_table(const pcfv_config* cfg, int which, double* out, size_t cap) {
     std::string e;

@@ -1154,6 +1154,87 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
     }
 }
 
+// Double-double accumulation (Dekker/Knuth error-free transforms): the DMD
+// algebra factors the Gram matrix, whose error the factor inherits times
+// cond(E)^2, so the Gram is summed to about 2^-100 relative accuracy.
+struct dd {
+    double hi, lo;
+};
+
+__device__ inline dd dd_add(dd a, dd b) {
+    const double s = a.hi + b.hi;
+    const double v = s - a.hi;
+    double e = (a.hi - (s - v)) + (b.hi - v);
+    e += a.lo + b.lo;
+    const double h = s + e;
+    return dd{h, e - (h - s)};
+}
+
+__device__ inline dd dd_fma(double x, double y, dd acc) {
+    const double p = x * y;
+    return dd_add(acc, dd{p, fma(x, y, -p)});
+}
+
+// Gram matrix of the snapshot differences of each guess: with S[k][b][:] the
+// minimal state vectors (k < M), e_0 = S[0], e_k = S[k] - S[k-1];
+// G[b][i][j] = e_i . e_j as a (hi, lo) pair of doubles.  One work group per
+// (b, i <= j), deterministic reduction order.
+__global__ __launch_bounds__(256) void k_dmd_gram(const double* __restrict__ S, int M, int B,
+                                                  long long n, double* __restrict__ G) {
+    __shared__ double rhi[256], rlo[256];
+    int w = blockIdx.x;
+    const int npair = M * (M + 1) / 2;
+    const int b = w / npair;
+    w -= b * npair;
+    int i = 0;
+    while (w >= M - i) {
+        w -= M - i;
+        ++i;
+    }
+    const int j = i + w;
+    const size_t stride = (size_t)B * n;
+    const double* si = S + (size_t)i * stride + (size_t)b * n;
+    const double* sj = S + (size_t)j * stride + (size_t)b * n;
+    dd acc{0.0, 0.0};
+    for (long long t = threadIdx.x; t < n; t += 256) {
+        const double ei = (i > 0) ? si[t] - si[t - stride] : si[t];
+        const double ej = (j > 0) ? sj[t] - sj[t - stride] : sj[t];
+        acc = dd_fma(ei, ej, acc);
+    }
+    rhi[threadIdx.x] = acc.hi;
+    rlo[threadIdx.x] = acc.lo;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const dd r = dd_add(dd{rhi[threadIdx.x], rlo[threadIdx.x]},
+                                dd{rhi[threadIdx.x + h], rlo[threadIdx.x + h]});
+            rhi[threadIdx.x] = r.hi;
+            rlo[threadIdx.x] = r.lo;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* g = G + (size_t)b * M * M * 2;
+        g[((size_t)i * M + j) * 2] = rhi[0];
+        g[((size_t)i * M + j) * 2 + 1] = rlo[0];
+        g[((size_t)j * M + i) * 2] = rhi[0];
+        g[((size_t)j * M + i) * 2 + 1] = rlo[0];
+    }
+}
+
+// psi[b][t] = sum_k coef[b][k] S[k + 1][b][t], k < M - 1.
+__global__ __launch_bounds__(256) void k_dmd_combine(const double* __restrict__ S, int M, int B,
+                                                     long long n, const double* __restrict__ coef,
+                                                     double* __restrict__ psi) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int b = blockIdx.y;
+    if (t >= n) return;
+    const size_t stride = (size_t)B * n;
+    double acc = 0.0;
+    for (int k = 0; k < M - 1; ++k) acc = fma(coef[(size_t)b * (M - 1) + k], S[(size_t)(k + 1) * stride + (size_t)b * n + t], acc);
+    psi[(size_t)b * n + t] = acc;
+}
+
 __global__ void k_axpy(long long n, double a, const double* __restrict__ x, double* __restrict__ y) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = fma(a, x[i], y[i]);
@@ -1252,6 +1333,18 @@ hipError_t launch_pack(const KP& p, hipStream_t s, const double2* u, double* psi
 
 hipError_t launch_unpack(const KP& p, hipStream_t s, const double* psi, double2* u) {
     PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_unpack<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, psi, u));
+    return hipGetLastError();
+}
+
+hipError_t launch_dmd_gram(hipStream_t s, const double* S, int M, int B, long long n, double* G) {
+    hipLaunchKernelGGL(k_dmd_gram, dim3((unsigned)(B * M * (M + 1) / 2)), dim3(256), 0, s, S, M, B, n, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_dmd_combine(hipStream_t s, const double* S, int M, int B, long long n,
+                              const double* coef, double* psi) {
+    hipLaunchKernelGGL(k_dmd_combine, dim3((unsigned)((n + 255) / 256), (unsigned)B), dim3(256), 0, s, S, M, B,
+                       n, coef, psi);
     return hipGetLastError();
 }
 

@@ -66,5 +66,10 @@ hipError_t launch_check(const KP& p, hipStream_t s, const double2* u, double* pa
 hipError_t launch_pack(const KP& p, hipStream_t s, const double2* u, double* psi);
 hipError_t launch_unpack(const KP& p, hipStream_t s, const double* psi, double2* u);
 hipError_t launch_axpy(hipStream_t s, long long n, double a, const double* x, double* y);
+// DMD: Gram matrix of snapshot differences ([B][M][M]) and linear combination
+// of snapshots 2..M with per-guess coefficients ([B][M-1]).  S is [M][B][n].
+hipError_t launch_dmd_gram(hipStream_t s, const double* S, int M, int B, long long n, double* G);
+hipError_t launch_dmd_combine(hipStream_t s, const double* S, int M, int B, long long n,
+                              const double* coef, double* psi);
 
 }  // namespace pcfv

@@ -28,7 +28,8 @@ EXPORTS = [
     "pcfv_workspace_bytes", "pcfv_create", "pcfv_destroy", "pcfv_get_layout", "pcfv_set_stream",
     "pcfv_residual", "pcfv_cost", "pcfv_jvp", "pcfv_adjoint", "pcfv_project", "pcfv_descend",
     "pcfv_norms", "pcfv_pack_state", "pcfv_unpack_state", "pcfv_check_state",
-    "pcfv_time_kernels", "pcfv_last_error", "pcfv_host_table",
+    "pcfv_time_kernels", "pcfv_last_error", "pcfv_host_table", "pcfv_dmd_extrapolate",
+    "pcfv_host_dmd",
 ]
 
 
@@ -48,13 +49,16 @@ class Layout(ctypes.Structure):
 class DescentOpts(ctypes.Structure):
     _fields_ = [("max_steps", ctypes.c_longlong), ("dtau", ctypes.c_double),
                 ("rel_tol", ctypes.c_double), ("check_every", ctypes.c_int),
-                ("grow_tol", ctypes.c_double), ("max_halvings", ctypes.c_int)]
+                ("grow_tol", ctypes.c_double), ("max_halvings", ctypes.c_int),
+                ("dmd_window", ctypes.c_int), ("dmd_stride", ctypes.c_int), ("dmd_gap", ctypes.c_int),
+                ("dmd_start", ctypes.c_double), ("dmd_accept", ctypes.c_double),
+                ("dmd_buffer", ctypes.c_void_p)]
 
 
 class DescentReport(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_longlong), ("tau", ctypes.c_double), ("cost", ctypes.c_double),
                 ("rel_res", ctypes.c_double), ("dtau_final", ctypes.c_double),
-                ("n_halvings", ctypes.c_int)]
+                ("n_halvings", ctypes.c_int), ("n_dmd", ctypes.c_int), ("n_dmd_accepted", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -97,6 +101,10 @@ def load_library(path=_LIB_PATH):
     lib.pcfv_last_error.argtypes = [vp]
     lib.pcfv_host_table.restype = ctypes.c_size_t
     lib.pcfv_host_table.argtypes = [cfgp, i, dp, ctypes.c_size_t]
+    lib.pcfv_dmd_extrapolate.restype = i
+    lib.pcfv_dmd_extrapolate.argtypes = [vp, vp, i, d, vp, dp, ctypes.POINTER(i)]
+    lib.pcfv_host_dmd.restype = i
+    lib.pcfv_host_dmd.argtypes = [dp, dp, i, d, dp, ctypes.c_size_t]
     return lib
 
 
@@ -128,6 +136,25 @@ def host_table(cfg, which):
     _lib.pcfv_host_table(ctypes.byref(cfg), int(which),
                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n)
     return out
+
+
+def host_dmd(Ge_hi, dtau, Ge_lo=None):
+    """Host DMD algebra on the Gram matrix Ge_hi + Ge_lo of snapshot
+    differences: returns a list (one entry per rank r = 1..r*) of coefficient
+    vectors c (length M-1) with steady state sum_k c_k psi_{k+2}."""
+    dptr = ctypes.POINTER(ctypes.c_double)
+    hi = np.ascontiguousarray(Ge_hi, dtype=np.float64)
+    M = hi.shape[0]
+    lo = None if Ge_lo is None else np.ascontiguousarray(Ge_lo, dtype=np.float64)
+    if hi.shape != (M, M) or (lo is not None and lo.shape != (M, M)):
+        raise ValueError("Gram matrix must be square")
+    cap = M * (M - 1)
+    out = np.zeros(cap)
+    r = _lib.pcfv_host_dmd(hi.ctypes.data_as(dptr), None if lo is None else lo.ctypes.data_as(dptr),
+                           M, float(dtau), out.ctypes.data_as(dptr), cap)
+    if r < 0:
+        raise ValueError("invalid DMD input")
+    return [out[k * (M - 1):(k + 1) * (M - 1)] for k in range(r)]
 
 
 def _ptr(t):
@@ -232,18 +259,40 @@ class Context:
         return out
 
     def descend(self, u, max_steps, dtau, rel_tol=0.0, check_every=None, grow_tol=0.0,
-                max_halvings=0):
+                max_halvings=0, dmd_window=0, dmd_stride=1, dmd_gap=0, dmd_start=0.0,
+                dmd_accept=10.0):
         """Advance u (a contiguous complex128 device tensor) in place; returns
-        (status, report dict)."""
+        (status, report dict).  dmd_window > 0 enables DMD extrapolation."""
         if not (u.is_contiguous() and u.dtype == self.torch.complex128 and tuple(u.shape) == self.shape):
             raise ValueError("u must be a contiguous complex128 device tensor of the context shape")
+        buf = None
+        if dmd_window > 0:
+            buf = self.torch.empty(int(dmd_window) * self.batch * self.n_state, dtype=self.torch.float64,
+                                   device=self.device)
         o = DescentOpts(int(max_steps), float(dtau), float(rel_tol),
-                        int(check_every or max(1, max_steps)), float(grow_tol), int(max_halvings))
+                        int(check_every or max(1, max_steps)), float(grow_tol), int(max_halvings),
+                        int(dmd_window), int(dmd_stride), int(dmd_gap), float(dmd_start), float(dmd_accept),
+                        ctypes.c_void_p(buf.data_ptr()) if buf is not None else None)
         rep = DescentReport()
         st = _lib.pcfv_descend(self._h, _ptr(u), ctypes.byref(o), ctypes.byref(rep))
         if st not in (OK, ENOTCONV, ENAN, EDIVERGED):
             self._check(st)
         return st, rep.as_dict()
+
+    def dmd_extrapolate(self, snaps, dtau_snap):
+        """snaps: device float64 tensor [M][batch][n_state] (M state vectors per
+        guess, oldest first).  Returns (u_s, cost(s), rank(s))."""
+        t = self.torch
+        snaps = t.as_tensor(snaps).to(self.device, t.float64).contiguous()
+        M = snaps.shape[0]
+        if snaps.numel() != M * self.batch * self.n_state:
+            raise ValueError("snapshots have the wrong size")
+        out = self.empty()
+        cost = self._scalars(1)
+        rank = (ctypes.c_int * self.batch)()
+        self._check(_lib.pcfv_dmd_extrapolate(self._h, _ptr(snaps), int(M), float(dtau_snap), _ptr(out),
+                                              cost, rank))
+        return out, self._unbatch(cost, 1), self._unbatch(rank, 1)
 
     def norms(self, u):
         u = self._field(u)

@@ -272,3 +272,108 @@ def test_batched_guesses_match_single_guess_oracle():
             ub, _ = m.descent_step(ub, 0.02)
         assert rel(to_np(U[b]), ub) < TOL
     assert max(max(d) for d in c.check_state(U)) < 1e-15
+
+
+# -- DMD extrapolation (Sec. 6) ---------------------------------------------------
+
+def _oracle_window(m, u, steps_before, nsnap, stride, dtau):
+    """Oracle descent: steps_before steps, then nsnap snapshots stride steps
+    apart (the last one taken without stepping past it)."""
+    for _ in range(steps_before):
+        u, _ = m.descent_step(u, dtau)
+    win = []
+    for k in range((nsnap - 1) * stride + 1):
+        if k % stride == 0:
+            win.append(u.copy())
+        if k < (nsnap - 1) * stride:
+            u, _ = m.descent_step(u, dtau)
+    return win
+
+
+def _dmd_tol(psis, r):
+    """1e3 * eps * s_1 / (s_r - s_{r+1}): the perturbation bound of the rank-r
+    DMD subspace for round-off at the snapshot scale."""
+    s = np.linalg.svd(np.asarray(psis)[:-1].T, compute_uv=False)
+    gap = s[r - 1] - (s[r] if r < len(s) else 0.0)
+    return 1e3 * np.finfo(float).eps * s[0] / gap
+
+
+def test_dmd_extrapolate_matches_oracle(ctxs):
+    """Same oracle snapshots into both: the GPU picks the oracle's rank, its
+    state matches the oracle's steady state within the subspace bound, and the
+    cost it reports is the cost of the state it returns."""
+    from oracle import dmd
+    g, m, c = ctxs("cfg1")
+    win = _oracle_window(m, inputs.config1_guess(), 40, 10, 4, 0.02)
+    psis = np.stack([state.pack(g, w) for w in win])
+    u_ref, c_ref, r_ref = dmd.extrapolate(m, win, 0.08)
+    u_s, cost, r = c.dmd_extrapolate(psis[:, None, :], 0.08)
+    u_s = to_np(u_s)
+    print(f"[gpu] dmd rank {r} (oracle {r_ref}) cost {cost:.6e} (oracle {c_ref:.6e}) "
+          f"state rel err {rel(u_s, u_ref):.3e} tol {_dmd_tol(psis, r_ref):.1e}", flush=True)
+    assert r == r_ref
+    assert rel(u_s, u_ref) < _dmd_tol(psis, r_ref)
+    assert abs(cost - m.cost(u_s)) < TOL * cost
+    assert cost < m.cost(win[-1])
+    assert max(c.check_state(u_s)) < 1e-15
+
+
+def test_dmd_extrapolate_batched_matches_single():
+    """Two guesses' windows extrapolated in one batched call equal the
+    single-guess calls."""
+    import torch
+    from paper_2306_00165_amd.pcfv import Context
+    g = Grid(16, 25, 16)
+    m = Method(g)
+    wins = [_oracle_window(m, inputs.random_field(16, 25, 16, energy=e, seed=s), 30, 8, 3, 0.02)
+            for s, e in [(31, 1e-3), (32, 2e-3)]]
+    psis = np.stack([np.stack([state.pack(g, w) for w in win]) for win in wins], axis=1)  # [M][B][n]
+    cb = Context(16, 25, 16, batch=2)
+    ub, costb, rb = cb.dmd_extrapolate(psis, 0.06)
+    c1 = Context(16, 25, 16)
+    for b in range(2):
+        u1, cost1, r1 = c1.dmd_extrapolate(psis[:, b:b + 1, :], 0.06)
+        assert rb[b] == r1
+        assert rel(to_np(ub[b]), to_np(u1)) < 1e-14
+        assert abs(costb[b] - cost1) < 1e-14 * cost1
+
+
+def test_descend_with_dmd_equals_composed_entry_points(ctxs):
+    """descend with a DMD window performs exactly: steps with snapshots every
+    `stride`, the extrapolation, acceptance, further steps; composing the same
+    entry points by hand gives the same state, and the extrapolated state
+    matches the oracle's replay of that schedule within the subspace bound
+    amplified by the snapshots' distance from the oracle's."""
+    import torch
+    from oracle import dmd
+    g, m, c = ctxs("cfg1")
+    u0 = inputs.config1_guess()
+    W, stride, dtau, after = 10, 4, 0.02, 6
+    u = torch.as_tensor(u0).to("cuda:0").contiguous()
+    c.descend(u, max_steps=40, dtau=dtau)
+    start = u.clone()
+    st, rep = c.descend(u, max_steps=(W - 1) * stride + after, dtau=dtau, dmd_window=W, dmd_stride=stride,
+                        dmd_gap=1000, dmd_accept=10.0)
+    assert st == 0 and rep["n_dmd"] == 1 and rep["n_dmd_accepted"] == 1
+    # the same schedule from entry points
+    v = start.clone()
+    snaps = []
+    for k in range(W):
+        snaps.append(to_np(c.pack(v)))
+        if k < W - 1:
+            c.descend(v, max_steps=stride, dtau=dtau)
+    u_s, cost_s, r_s = c.dmd_extrapolate(np.stack(snaps)[:, None, :], stride * dtau)
+    c.descend(u_s, max_steps=after, dtau=dtau)
+    assert rel(to_np(u), to_np(u_s)) < 1e-15
+    # oracle replay of the schedule
+    win = _oracle_window(m, u0, 40, W, stride, dtau)
+    psis = np.stack([state.pack(g, w) for w in win])
+    snap_err = max(rel(a, b) for a, b in zip(snaps, psis))
+    u_ref, c_ref, r_ref = dmd.extrapolate(m, win, stride * dtau)
+    for _ in range(after):
+        u_ref, _ = m.descent_step(u_ref, dtau)
+    tol = _dmd_tol(psis, r_ref) * max(1.0, snap_err / np.finfo(float).eps)
+    print(f"[gpu] descend+dmd rank {r_s} (oracle {r_ref}) snapshot err {snap_err:.2e} "
+          f"state rel err {rel(to_np(u), u_ref):.3e} tol {tol:.1e}", flush=True)
+    assert r_s == r_ref
+    assert rel(to_np(u), u_ref) < tol

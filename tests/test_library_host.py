@@ -192,3 +192,65 @@ def test_projection_tables_replay_matches_oracle_projection(dims):
             Dv = _mat(t, 26, N, N - 4) @ t4
             out = np.array([ik2 * (1j * a * Dv - 1j * b * eta), v, ik2 * (1j * b * Dv + 1j * a * eta)])
         np.testing.assert_allclose(out, ref[:, ikx, kz], rtol=0, atol=1e-13 * np.abs(X).max())
+
+
+# -- DMD host algebra (Sec. 6.1-6.2) ---------------------------------------------------
+
+def _exact_gram(E):
+    """Gram matrix of the rows of E summed exactly (rational arithmetic), split
+    into a (hi, lo) pair of doubles."""
+    from fractions import Fraction
+    M = E.shape[0]
+    F = [[Fraction(float(x)) for x in row] for row in E]
+    hi = np.zeros((M, M))
+    lo = np.zeros((M, M))
+    for i in range(M):
+        for j in range(i, M):
+            s = sum(a * b for a, b in zip(F[i], F[j]))
+            h = float(s)
+            hi[i, j] = hi[j, i] = h
+            lo[i, j] = lo[j, i] = float(s - Fraction(h))
+    return hi, lo
+
+
+@pytest.mark.parametrize("nmodes,M", [(1, 4), (3, 8), (6, 20)])
+def test_host_dmd_matches_oracle_on_affine_windows(nmodes, M):
+    """Affine dynamics with a known fixed point psi*: the library's Gram-based
+    DMD algebra returns the numerical rank of the oracle's SVD, recovers psi*
+    at full rank like the oracle does, and at every truncated rank agrees with
+    the oracle's steady state within 1e3 * eps * s_1 / (s_r - s_{r+1}) (the
+    first-order perturbation bound of the rank-r singular subspace that both
+    sides compute, relative to the snapshot scale)."""
+    from test_oracle_dmd import affine_window
+    from oracle import dmd
+    snaps, psi_star, _ = affine_window(200, nmodes, M, seed=nmodes)
+    E = np.vstack([snaps[0], np.diff(snaps, axis=0)])
+    hi, lo = _exact_gram(E)
+    coefs = pcfv.host_dmd(hi, 1.0, lo)
+    rstar = dmd.numerical_rank(snaps)
+    assert len(coefs) == rstar == nmodes + 1
+    s = np.linalg.svd(snaps[:-1].T, compute_uv=False)
+    for r, c in enumerate(coefs, start=1):
+        psi = c @ snaps[1:]
+        ref, _ = dmd.steady_state(snaps, 1.0, r)
+        gap = s[r - 1] - (s[r] if r < len(s) else 0.0)
+        tol = 1e3 * np.finfo(float).eps * s[0] / gap
+        assert np.abs(psi - ref).max() <= tol * np.abs(ref).max(), (r, tol)
+    psi = coefs[-1] @ snaps[1:]
+    assert np.abs(psi - psi_star).max() < 1e-9 * np.abs(psi_star).max()
+
+
+def test_host_dmd_rank_one_window_and_invalid_input():
+    """A window that has already converged (all snapshots equal) has rank 1
+    and the steady state is that snapshot (lambda = 1, omega = 0); windows of
+    fewer than 3 snapshots are rejected."""
+    psi = np.random.default_rng(4).standard_normal(50)
+    snaps = np.array([psi] * 5)
+    E = np.vstack([snaps[0], np.diff(snaps, axis=0)])
+    coefs = pcfv.host_dmd(E @ E.T, 0.5)
+    assert len(coefs) == 1
+    np.testing.assert_allclose(coefs[0] @ snaps[1:], psi, rtol=1e-14, atol=0)
+    with pytest.raises(ValueError):
+        pcfv.host_dmd(np.eye(2), 1.0)
+    with pytest.raises(ValueError):
+        pcfv.host_dmd(np.eye(3), 0.0)

@@ -1,0 +1,63 @@
+"""Pins for the oracle's DMD extrapolation.
+
+Affine-linear dynamics psi_{k+1} = psi* + A (psi_k - psi*) with a known stable
+A have the exact fixed point psi*: DMD of a window whose span contains the
+dynamics (rank >= number of excited modes + 1) must return psi* to round-off
+(Sec. 6: the omega ~ 0 mode of the best-fit linear model is the steady state).
+Also pinned: omega_1 = 0 exactly there, the numerical rank, and that the
+extrapolation of an actual descent window lowers the cost."""
+
+import numpy as np
+import pytest
+
+from oracle import Grid, dmd, state
+from oracle.method import Method
+from paper_2306_00165_amd import inputs
+
+
+def affine_window(n, nmodes, M, seed, dtau=1.0):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, nmodes)))
+    rates = np.linspace(0.05, 0.4, nmodes)          # decay rates: A = exp(-rate dtau) on span(Q)
+    psi_star = rng.standard_normal(n)
+    c0 = rng.standard_normal(nmodes)
+    snaps = [psi_star + Q @ (c0 * np.exp(-rates * k * dtau)) for k in range(M)]
+    return np.array(snaps), psi_star, rates
+
+
+@pytest.mark.parametrize("nmodes,M", [(1, 4), (3, 8), (6, 20)])
+def test_affine_dynamics_fixed_point_is_exact(nmodes, M):
+    snaps, psi_star, rates = affine_window(200, nmodes, M, seed=nmodes)
+    r = dmd.numerical_rank(snaps)
+    assert r == nmodes + 1
+    psi_s, om = dmd.steady_state(snaps, 1.0, r)
+    assert abs(om) < 1e-9
+    np.testing.assert_allclose(psi_s, psi_star, rtol=0, atol=1e-9 * np.abs(psi_star).max())
+    lam, omega, Phi, b = dmd.dmd(snaps, 1.0, r)
+    got = np.sort(-np.real(omega))[1:]
+    np.testing.assert_allclose(got, np.sort(rates), rtol=1e-8)
+
+
+def test_truncated_rank_is_worse_than_full_rank():
+    snaps, psi_star, _ = affine_window(100, 4, 12, seed=9)
+    err_full = np.abs(dmd.steady_state(snaps, 1.0, 5)[0] - psi_star).max()
+    err_low = np.abs(dmd.steady_state(snaps, 1.0, 2)[0] - psi_star).max()
+    assert err_full < 1e-9 < err_low
+
+
+def test_extrapolation_of_a_descent_window_lowers_the_cost():
+    g = Grid(16, 25, 16)
+    m = Method(g)
+    u = inputs.config1_guess()
+    for _ in range(40):
+        u, _ = m.descent_step(u, 0.02)
+    window = []
+    for k in range(40):
+        if k % 4 == 0:
+            window.append(u.copy())
+        u, _ = m.descent_step(u, 0.02)
+    c_now = m.cost(window[-1])
+    u_s, c_s, r = dmd.extrapolate(m, window, 4 * 0.02)
+    assert r >= 1 and u_s is not None
+    assert max(m.defects(u_s)) < 1e-12
+    assert c_s < c_now
