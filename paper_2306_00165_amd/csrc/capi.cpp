@@ -664,8 +664,8 @@ pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* 
         PCFV_TRY(hipEventElapsedTime(&ms, e0, e1), "elapsed");
         ms_out[k] = ms / nrep;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (n_out) *n_out = 5;
     return PCFV_OK;
 }
