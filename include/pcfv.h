@@ -76,13 +76,18 @@ typedef enum {
 } pcfv_status;
 
 /* Problem definition (Sec. 3.1 and Sec. 5.1).  6 <= Nx, Nz <= 512 (any
- * integers), 9 <= Ny <= 128.  precision must be 0 (FP64).  batch: number of
- * guesses held and advanced together (0 or 1: one guess; at most 4096). */
+ * integers), 9 <= Ny <= 128.  batch: number of guesses held and advanced
+ * together (0 or 1: one guess; at most 4096).
+ * precision: PCFV_FP64 (0), everything in FP64; or PCFV_MIXED (1), the
+ * transforms in x and z and the nonlinear products in FP32 while the Stokes
+ * solves, the influence matrix, projection, cost and update stay FP64.  The
+ * state u and every argument stay FP64 in both. */
+enum { PCFV_FP64 = 0, PCFV_MIXED = 1 };
 typedef struct {
     double Lx, Lz, Re;
     int Nx, Ny, Nz;
     double dt_im;        /* Delta t of the Stokes step inside r(u); the paper uses 0.25 */
-    int precision;       /* 0 = FP64 */
+    int precision;       /* PCFV_FP64 or PCFV_MIXED */
     int batch;
 } pcfv_config;
 
@@ -113,6 +118,10 @@ void pcfv_destroy(pcfv_ctx* ctx);
 
 pcfv_status pcfv_get_layout(const pcfv_ctx* ctx, pcfv_layout* out);
 pcfv_status pcfv_set_stream(pcfv_ctx* ctx, void* hip_stream);
+
+/* Switch the context between PCFV_FP64 and PCFV_MIXED for later calls (the
+ * workspace of either precision serves both).  PCFV_EINVAL otherwise. */
+pcfv_status pcfv_set_precision(pcfv_ctx* ctx, int precision);
 
 /* Residual r(u) (Sec. 4 steps (1)-(2), Sec. 3.2 residual).  u admissible.
  * r may be NULL (then only the cost is formed).  cost_host, if non-NULL,
@@ -157,6 +166,10 @@ typedef struct {
     double dmd_start;
     double dmd_accept;
     double* dmd_buffer;
+    /* Mixed precision: on a PCFV_MIXED context, once every guess has
+     * ||r||/||u_b+u|| < fp64_below at a check, the rest of the call runs in
+     * FP64 (the refinement phase); <= 0 keeps the context's precision. */
+    double fp64_below;
 } pcfv_descent_opts;
 
 typedef struct {
@@ -168,6 +181,7 @@ typedef struct {
     int n_halvings;
     int n_dmd;            /* DMD extrapolations performed                            */
     int n_dmd_accepted;   /* guesses restarted from an extrapolated state             */
+    long long steps_fp32; /* steps taken with the FP32 physical-space stage           */
 } pcfv_descent_report;
 
 /* Advance every guess of u in place with the same dtau.  Returns PCFV_OK when

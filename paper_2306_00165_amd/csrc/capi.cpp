@@ -41,8 +41,8 @@ bool validate(const pcfv_config* c, std::string& e) {
         e = "config is NULL";
         return false;
     }
-    if (c->precision != 0) {
-        e = "only precision 0 (FP64) is supported";
+    if (c->precision != PCFV_FP64 && c->precision != PCFV_MIXED) {
+        e = "precision must be PCFV_FP64 (0) or PCFV_MIXED (1)";
         return false;
     }
     if (c->batch < 0 || c->batch > 4096) {
@@ -87,6 +87,7 @@ KP base_kp(const pcfv_config& c) {
             break;
     }
     p.NS = c.Nx / p.XS;
+    p.prec = c.precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
     return p;
 }
 
@@ -404,6 +405,14 @@ pcfv_status pcfv_set_stream(pcfv_ctx* ctx, void* hip_stream) {
     return PCFV_OK;
 }
 
+pcfv_status pcfv_set_precision(pcfv_ctx* ctx, int precision) {
+    if (!ctx) return PCFV_EINVAL;
+    if (precision != PCFV_FP64 && precision != PCFV_MIXED)
+        return fail(ctx, PCFV_EINVAL, "precision must be PCFV_FP64 (0) or PCFV_MIXED (1)");
+    ctx->kp.prec = precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
+    return PCFV_OK;
+}
+
 pcfv_status pcfv_residual(pcfv_ctx* ctx, const double* u, double* r, double* cost_host) {
     if (!ctx || !u) return fail(ctx, PCFV_EINVAL, "NULL argument");
     PCFV_TRY(launch_synth(ctx->kp, ctx->stream, cd(u), ctx->Y), "synth");
@@ -458,11 +467,17 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
                     !o->dmd_buffer || !(o->dmd_accept > 0)))
         return fail(ctx, PCFV_EINVAL, "invalid DMD options");
     const KP& p = ctx->kp;
+    // the refinement phase switches ctx->kp.prec; every exit restores it
+    struct PrecGuard {
+        KP& kp;
+        int saved;
+        ~PrecGuard() { kp.prec = saved; }
+    } guard{ctx->kp, ctx->kp.prec};
     const int B = p.B;
     const size_t fbytes = (size_t)ctx->nfield() * 16;
     const size_t fbytes1 = (size_t)3 * p.nm * p.N * 16;
     double dtau = o->dtau, tau = 0;
-    long long steps = 0;
+    long long steps = 0, steps32 = 0;
     int halvings = 0, n_dmd = 0, n_acc = 0;
     std::vector<double> cost, ntot, cost_prev;
     pcfv_descent_report local{};
@@ -483,7 +498,23 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
         rep->n_halvings = halvings;
         rep->n_dmd = n_dmd;
         rep->n_dmd_accepted = n_acc;
+        rep->steps_fp32 = steps32;
         return st;
+    };
+    // FP32 -> FP64 once every guess is below fp64_below: new y-values and cost
+    auto maybe_refine = [&]() -> pcfv_status {
+        if (!(o->fp64_below > 0) || ctx->kp.prec != PREC_FP32 || worst_rel() >= o->fp64_below) return PCFV_OK;
+        ctx->kp.prec = PREC_FP64;
+        PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth");
+        pcfv_status st = cost_and_norm(ctx, u, cost, ntot);
+        if (st != PCFV_OK) return st;
+        cost_prev = cost;
+        return PCFV_OK;
+    };
+    // converged: below rel_tol, and past the FP32 phase if a refinement is asked for
+    auto converged = [&]() {
+        return o->rel_tol > 0 && worst_rel() < o->rel_tol &&
+               (ctx->kp.prec == PREC_FP64 || !(o->fp64_below > 0));
     };
     auto finite = [&]() {
         for (double c : cost)
@@ -495,7 +526,9 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
     if (s != PCFV_OK) return s;
     if (!finite()) return report(fail(ctx, PCFV_ENAN, "cost is not finite"));
     cost_prev = cost;
-    if (o->rel_tol > 0 && worst_rel() < o->rel_tol) return report(PCFV_OK);
+    s = maybe_refine();
+    if (s != PCFV_OK) return s;
+    if (converged()) return report(PCFV_OK);
     bool window = false;
     int nsnap = 0;
     long long next_snap = 0, window_start = 0, since_check = 0;
@@ -534,12 +567,14 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
                 s = cost_and_norm(ctx, u, cost, ntot);
                 if (s != PCFV_OK) return s;
                 cost_prev = cost;
+                s = maybe_refine();
+                if (s != PCFV_OK) return s;
                 if (o->grow_tol > 0)
                     PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
                 window = false;
                 window_start = steps + o->dmd_gap;
                 since_check = 0;
-                if (o->rel_tol > 0 && worst_rel() < o->rel_tol) return report(PCFV_OK);
+                if (converged()) return report(PCFV_OK);
                 continue;
             }
         }
@@ -549,6 +584,7 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
             s = descent_step(ctx, u, dtau);
             if (s != PCFV_OK) return s;
         }
+        if (ctx->kp.prec == PREC_FP32) steps32 += k;
         steps += k;
         tau += k * dtau;
         since_check += k;
@@ -573,9 +609,11 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
             continue;
         }
         cost_prev = cost;
+        s = maybe_refine();
+        if (s != PCFV_OK) return s;
         if (o->grow_tol > 0)
             PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
-        if (o->rel_tol > 0 && worst_rel() < o->rel_tol) return report(PCFV_OK);
+        if (converged()) return report(PCFV_OK);
     }
     return report(o->rel_tol > 0 ? fail(ctx, PCFV_ENOTCONV, "max_steps reached above rel_tol") : PCFV_OK);
 }

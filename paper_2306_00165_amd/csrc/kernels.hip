@@ -29,7 +29,7 @@ constexpr int MODE_THREADS = 256;              // one Fourier mode per work grou
 constexpr int MODE_WAVES = MODE_THREADS / WAVE;
 constexpr int KSPLIT = 4;                      // lanes sharing one output row of a contraction
 constexpr int ROWS_PER_WAVE = WAVE / KSPLIT;   // 16
-constexpr int PLANE_THREADS = 256;
+constexpr int PLANE_THREADS = 512;
 constexpr int MODE_VECS = 24;                  // LDS vectors (length N) used by the mode kernels
 constexpr int RED_SLOTS = 16;                  // doubles per wave for block reductions
 
@@ -42,6 +42,34 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 // (i s) z for real s
 __device__ __forceinline__ double2 imul(double s, double2 z) { return c2(-s * z.y, s * z.x); }
+
+// The physical-space kernels are instantiated for R = double (FP64 path) and
+// R = float (FP32 transforms and products); C<R> is the matching complex type.
+// The per-mode kernels always compute in FP64 and read/write the y-value and
+// partial arrays in the storage type of the physical-space precision.
+template <class R> struct CT;
+template <> struct CT<double> { typedef double2 T; };
+template <> struct CT<float> { typedef float2 T; };
+template <class R> using C = typename CT<R>::T;
+
+// mkc: complex from two reals of either precision (overloads, no int literals).
+__device__ __forceinline__ double2 mkc(double x, double y) { return make_double2(x, y); }
+__device__ __forceinline__ float2 mkc(float x, float y) { return make_float2(x, y); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return mkc(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return mkc(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscl(float s, float2 a) { return mkc(s * a.x, s * a.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return mkc(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 imul(float s, float2 z) { return mkc(-s * z.y, s * z.x); }
+
+__device__ __forceinline__ double2 widen(double2 v) { return v; }
+__device__ __forceinline__ double2 widen(float2 v) { return make_double2(v.x, v.y); }
+template <class T> __device__ __forceinline__ T narrow(double2 v);
+template <> __device__ __forceinline__ double2 narrow<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 narrow<float2>(double2 v) {
+    return make_float2((float)v.x, (float)v.y);
+}
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -466,9 +494,9 @@ __device__ void project0(const KP& p, const double2* gx, const double2* gz, doub
 
 // y-values of u and of du/dy for the three components: Y[c] = C u_c,
 // Y[3+c] = C D u_c (Gauss-Lobatto synthesis).
-template <int NP>
+template <int NP, class YT>
 __global__ __launch_bounds__(MODE_THREADS) void k_synth(KP p, const double2* __restrict__ u,
-                                                        double2* __restrict__ Y) {
+                                                        YT* __restrict__ Y) {
     extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
@@ -483,14 +511,17 @@ __global__ __launch_bounds__(MODE_THREADS) void k_synth(KP p, const double2* __r
     __syncthreads();
     for (int f = 0; f < 6; ++f)
         for (int j = t; j < N; j += MODE_THREADS)
-            Y[((size_t)f * N + j) * nmB + mB] = V[(3 + f) * N + j];
+            Y[((size_t)f * N + j) * nmB + mB] = narrow<YT>(V[(3 + f) * N + j]);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __restrict__ Y1,
-                                                         const double2* __restrict__ Y2,
-                                                         double2* __restrict__ out) {
-    extern __shared__ double2 sm[];
+template <int MODE, class R>
+__global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const C<R>* __restrict__ Y1,
+                                                         const C<R>* __restrict__ Y2,
+                                                         C<R>* __restrict__ out) {
+    typedef C<R> CR;
+    extern __shared__ __align__(16) unsigned char smraw[];
+    CR* sm = reinterpret_cast<CR*>(smraw);
+    const R zero = 0, two = 2, alpha = (R)p.alpha, beta = (R)p.beta;
     constexpr int NG3 = (MODE == PLANE_JVP) ? 6 : 3;  // velocity fields: (V, i a V, W) groups
     constexpr int NG1 = (MODE == PLANE_ADJ) ? 3 : 0;  // adjoint fields: single outputs
     constexpr int NXF = 3 * NG3 + NG1;
@@ -504,12 +535,12 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
     const int Kx = p.Kx;
     const int x0 = s * XS, tid = threadIdx.x;
     const int per = XS * nkz, pz = XS * Nz;
-    double2* twx = sm;
-    double2* twz = twx + Nx;
-    double2* xb = twz + Nz;
-    double* pb = reinterpret_cast<double*>(xb + NXF * per);
-    for (int i = tid; i < Nx; i += PLANE_THREADS) twx[i] = p.twx[i];
-    for (int i = tid; i < Nz; i += PLANE_THREADS) twz[i] = p.twz[i];
+    CR* twx = sm;
+    CR* twz = twx + Nx;
+    CR* xb = twz + Nz;
+    R* pb = reinterpret_cast<R*>(xb + NXF * per);
+    for (int i = tid; i < Nx; i += PLANE_THREADS) twx[i] = narrow<CR>(p.twx[i]);
+    for (int i = tid; i < Nz; i += PLANE_THREADS) twz[i] = narrow<CR>(p.twz[i]);
     __syncthreads();
 
     // inverse transform in x for the slab's x positions, all retained kz
@@ -517,20 +548,20 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
         const int g = it / per, rem = it - g * per, xl = rem / nkz, kz = rem - xl * nkz;
         const int x = x0 + xl;
         if (g < NG3) {
-            const double2* src = (g < 3) ? Y1 : Y2;
+            const CR* src = (g < 3) ? Y1 : Y2;
             const int comp = g % 3;
-            const double2* Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
-            const double2* Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
-            double2 aV = c2(0, 0), aA = c2(0, 0), aW = c2(0, 0);
+            const CR* Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
+            const CR* Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
+            CR aV = mkc(zero, zero), aA = mkc(zero, zero), aW = mkc(zero, zero);
             const int step = x % Nx;
             int idx = 0;                                   // (kx * x) mod Nx, kx = 0, 1, ..
             for (int ikx = 0; ikx < nkx; ++ikx) {
                 if (ikx == Kx + 1) idx = (Nx - (Kx * x) % Nx) % Nx;   // kx = -Kx
                 const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
-                const double2 tw = twx[idx];
-                const double2 vt = cmul(Vp[(size_t)ikx * nkz], tw);
+                const CR tw = twx[idx];
+                const CR vt = cmul(Vp[(size_t)ikx * nkz], tw);
                 aV = cadd(aV, vt);
-                aA = cadd(aA, imul(p.alpha * kx, vt));
+                aA = cadd(aA, imul(alpha * (R)kx, vt));
                 aW = cadd(aW, cmul(Wp[(size_t)ikx * nkz], tw));
                 idx += step;
                 if (idx >= Nx) idx -= Nx;
@@ -540,8 +571,8 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
             xb[(3 * g + 2) * per + rem] = aW;
         } else {
             const int comp = g - NG3;
-            const double2* Ap = Y2 + ((size_t)comp * N + j) * nmB + mo + kz;
-            double2 acc = c2(0, 0);
+            const CR* Ap = Y2 + ((size_t)comp * N + j) * nmB + mo + kz;
+            CR acc = mkc(zero, zero);
             const int step = x % Nx;
             int idx = 0;
             for (int ikx = 0; ikx < nkx; ++ikx) {
@@ -556,34 +587,34 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
     __syncthreads();
 
     // inverse (complex-to-real) transform in z at each point, then the products
-    const double yj = p.ygl[j];
+    const R yj = (R)p.ygl[j];
     for (int pt = tid; pt < pz; pt += PLANE_THREADS) {
         const int xl = pt / Nz, z = pt - xl * Nz;
-        double val[NG3][4];  // U, dU/dx, dU/dy, dU/dz of each velocity field
+        R val[NG3][4];  // U, dU/dx, dU/dy, dU/dz of each velocity field
 #pragma unroll
         for (int g = 0; g < NG3; ++g) {
-            const double2* cV = xb + (3 * g) * per + xl * nkz;
-            const double2* cA = xb + (3 * g + 1) * per + xl * nkz;
-            const double2* cW = xb + (3 * g + 2) * per + xl * nkz;
-            double sV = 0, sZ = 0, sA = 0, sW = 0;
+            const CR* cV = xb + (3 * g) * per + xl * nkz;
+            const CR* cA = xb + (3 * g + 1) * per + xl * nkz;
+            const CR* cW = xb + (3 * g + 2) * per + xl * nkz;
+            R sV = 0, sZ = 0, sA = 0, sW = 0;
             int idx = 0;                                   // (kz * z) mod Nz
             for (int kz = 1; kz < nkz; ++kz) {
                 idx += z;
                 if (idx >= Nz) idx -= Nz;
-                const double2 tw = twz[idx];
-                const double2 t = cmul(cV[kz], tw);
+                const CR tw = twz[idx];
+                const CR t = cmul(cV[kz], tw);
                 sV += t.x;
-                sZ += p.beta * kz * t.y;
+                sZ += beta * (R)kz * t.y;
                 sA += cmul(cA[kz], tw).x;
                 sW += cmul(cW[kz], tw).x;
             }
-            val[g][0] = cV[0].x + 2.0 * sV;
-            val[g][1] = cA[0].x + 2.0 * sA;
-            val[g][2] = cW[0].x + 2.0 * sW;
-            val[g][3] = -2.0 * sZ;
+            val[g][0] = cV[0].x + two * sV;
+            val[g][1] = cA[0].x + two * sA;
+            val[g][2] = cW[0].x + two * sW;
+            val[g][3] = -two * sZ;
         }
         val[0][0] += yj;   // base flow u_b = y e_x
-        val[0][2] += 1.0;  // d(u_b)_x / dy = 1
+        val[0][2] += (R)1; // d(u_b)_x / dy = 1
         if (MODE == PLANE_FWD) {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -591,25 +622,25 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
         } else if (MODE == PLANE_JVP) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                double q = 0;
+                R q = 0;
 #pragma unroll
                 for (int jj = 0; jj < 3; ++jj)
                     q += val[jj][0] * val[3 + i][1 + jj] + val[3 + jj][0] * val[i][1 + jj];
                 pb[i * pz + pt] = q;
             }
         } else {
-            double at[3];
+            R at[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const double2* cc = xb + (3 * NG3 + i) * per + xl * nkz;
-                double sr = 0;
+                const CR* cc = xb + (3 * NG3 + i) * per + xl * nkz;
+                R sr = 0;
                 int idx = 0;
                 for (int kz = 1; kz < nkz; ++kz) {
                     idx += z;
                     if (idx >= Nz) idx -= Nz;
                     sr += cmul(cc[kz], twz[idx]).x;
                 }
-                at[i] = cc[0].x + 2.0 * sr;
+                at[i] = cc[0].x + two * sr;
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -624,42 +655,42 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
     __syncthreads();
 
     // forward transform in z (normalised), into xb
-    const double invNz = 1.0 / Nz, invNx = 1.0 / Nx;
+    const R invNz = (R)1 / (R)Nz, invNx = (R)1 / (R)Nx;
     for (int it = tid; it < NZF * per; it += PLANE_THREADS) {
         const int o = it / per, rem = it - o * per, xl = rem / nkz, kz = rem - xl * nkz;
         if (MODE != PLANE_ADJ) {
-            const double* q = pb + o * pz + xl * Nz;
-            double ar = 0, ai = 0;
+            const R* q = pb + o * pz + xl * Nz;
+            R ar = 0, ai = 0;
             for (int z = 0, idx = 0; z < Nz; ++z, idx = (idx + kz >= Nz) ? idx + kz - Nz : idx + kz) {
-                const double2 tw = twz[idx];
+                const CR tw = twz[idx];
                 ar += q[z] * tw.x;
                 ai -= q[z] * tw.y;
             }
-            xb[o * per + rem] = c2(ar * invNz, ai * invNz);
+            xb[o * per + rem] = mkc(ar * invNz, ai * invNz);
         } else {
             const int i = o / 3, kind = o - 3 * i;
             if (kind == 0) {  // Q_i - i b P_{i,z}
-                const double* q1 = pb + (9 + i) * pz + xl * Nz;
-                const double* q2 = pb + (3 * i + 2) * pz + xl * Nz;
-                double ar = 0, ai = 0, br = 0, bi = 0;
+                const R* q1 = pb + (9 + i) * pz + xl * Nz;
+                const R* q2 = pb + (3 * i + 2) * pz + xl * Nz;
+                R ar = 0, ai = 0, br = 0, bi = 0;
                 for (int z = 0, idx = 0; z < Nz; ++z, idx = (idx + kz >= Nz) ? idx + kz - Nz : idx + kz) {
-                    const double2 tw = twz[idx];
+                    const CR tw = twz[idx];
                     ar += q1[z] * tw.x;
                     ai -= q1[z] * tw.y;
                     br += q2[z] * tw.x;
                     bi -= q2[z] * tw.y;
                 }
-                const double2 r = csub(c2(ar, ai), imul(p.beta * kz, c2(br, bi)));
+                const CR r = csub(mkc(ar, ai), imul(beta * (R)kz, mkc(br, bi)));
                 xb[o * per + rem] = cscl(invNz, r);
             } else {  // P_{i,x} (kind 1) or P_{i,y} (kind 2)
-                const double* q = pb + (3 * i + (kind - 1)) * pz + xl * Nz;
-                double ar = 0, ai = 0;
+                const R* q = pb + (3 * i + (kind - 1)) * pz + xl * Nz;
+                R ar = 0, ai = 0;
                 for (int z = 0, idx = 0; z < Nz; ++z, idx = (idx + kz >= Nz) ? idx + kz - Nz : idx + kz) {
-                    const double2 tw = twz[idx];
+                    const CR tw = twz[idx];
                     ar += q[z] * tw.x;
                     ai -= q[z] * tw.y;
                 }
-                xb[o * per + rem] = c2(ar * invNz, ai * invNz);
+                xb[o * per + rem] = mkc(ar * invNz, ai * invNz);
             }
         }
     }
@@ -672,46 +703,46 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const double2* __
         const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
         const int kstep = ((kx % Nx) + Nx) % Nx;            // kx mod Nx
         const int idx0 = (int)(((long long)kstep * x0) % Nx);  // (kx * x0) mod Nx
-        double2 res;
+        CR res;
         if (MODE != PLANE_ADJ) {
-            double ar = 0, ai = 0;
+            R ar = 0, ai = 0;
             for (int xl = 0, idx = idx0; xl < XS; ++xl, idx = (idx + kstep >= Nx) ? idx + kstep - Nx : idx + kstep) {
-                const double2 tw = twx[idx], v = xb[o * per + xl * nkz + kz];
+                const CR tw = twx[idx], v = xb[o * per + xl * nkz + kz];
                 ar += v.x * tw.x + v.y * tw.y;
                 ai += v.y * tw.x - v.x * tw.y;
             }
-            res = c2(ar * invNx, ai * invNx);
+            res = mkc(ar * invNx, ai * invNx);
         } else if (o < 3) {  // X_i = F(A_i) - i a F(B_i)
-            double ar = 0, ai = 0, br = 0, bi = 0;
+            R ar = 0, ai = 0, br = 0, bi = 0;
             for (int xl = 0, idx = idx0; xl < XS; ++xl, idx = (idx + kstep >= Nx) ? idx + kstep - Nx : idx + kstep) {
-                const double2 tw = twx[idx];
-                const double2 va = xb[(3 * o) * per + xl * nkz + kz];
-                const double2 vb = xb[(3 * o + 1) * per + xl * nkz + kz];
+                const CR tw = twx[idx];
+                const CR va = xb[(3 * o) * per + xl * nkz + kz];
+                const CR vb = xb[(3 * o + 1) * per + xl * nkz + kz];
                 ar += va.x * tw.x + va.y * tw.y;
                 ai += va.y * tw.x - va.x * tw.y;
                 br += vb.x * tw.x + vb.y * tw.y;
                 bi += vb.y * tw.x - vb.x * tw.y;
             }
-            res = cscl(invNx, csub(c2(ar, ai), imul(p.alpha * kx, c2(br, bi))));
+            res = cscl(invNx, csub(mkc(ar, ai), imul(alpha * (R)kx, mkc(br, bi))));
         } else {  // Y_i = F(C_i)
             const int i = o - 3;
-            double ar = 0, ai = 0;
+            R ar = 0, ai = 0;
             for (int xl = 0, idx = idx0; xl < XS; ++xl, idx = (idx + kstep >= Nx) ? idx + kstep - Nx : idx + kstep) {
-                const double2 tw = twx[idx], v = xb[(3 * i + 2) * per + xl * nkz + kz];
+                const CR tw = twx[idx], v = xb[(3 * i + 2) * per + xl * nkz + kz];
                 ar += v.x * tw.x + v.y * tw.y;
                 ai += v.y * tw.x - v.x * tw.y;
             }
-            res = c2(ar * invNx, ai * invNx);
+            res = mkc(ar * invNx, ai * invNx);
         }
         out[(((size_t)s * NOUT + o) * N + j) * nmB + mo + mm] = res;
     }
 }
 
-template <int NP>
+template <int NP, class YT>
 __global__ __launch_bounds__(MODE_THREADS) void k_mode_res(
-    KP p, int flags, const double2* __restrict__ P3, const double2* __restrict__ u,
+    KP p, int flags, const YT* __restrict__ P3, const double2* __restrict__ u,
     double2* __restrict__ r, double* __restrict__ cost_part, double2* __restrict__ a,
-    double2* __restrict__ Atil) {
+    YT* __restrict__ Atil) {
     extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
@@ -730,7 +761,7 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_res(
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MODE_THREADS) {
                 double2 acc = c2(0, 0);
-                for (int s = 0; s < p.NS; ++s) acc = cadd(acc, P3[(((size_t)s * 3 + i) * N + n) * nmB + mB]);
+                for (int s = 0; s < p.NS; ++s) acc = cadd(acc, widen(P3[(((size_t)s * 3 + i) * N + n) * nmB + mB]));
                 vec(i)[n] = acc;
                 vec(3 + i)[n] = u[so + ((size_t)i * nm + m) * N + n];
             }
@@ -781,16 +812,16 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_res(
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MODE_THREADS) {
             a[so + ((size_t)i * nm + m) * N + n] = vec(i)[n];
-            Atil[((size_t)i * N + n) * nmB + mB] = vec(12 + i)[n];
+            Atil[((size_t)i * N + n) * nmB + mB] = narrow<YT>(vec(12 + i)[n]);
         }
 }
 
-template <int NP>
+template <int NP, class YT>
 __global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags,
-                                                            const double2* __restrict__ P6,
+                                                            const YT* __restrict__ P6,
                                                             const double2* __restrict__ a,
                                                             double dtau, double2* __restrict__ uo,
-                                                            double2* __restrict__ Y) {
+                                                            YT* __restrict__ Y) {
     extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
@@ -804,8 +835,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags,
         for (int n = t; n < N; n += MODE_THREADS) {
             double2 sx = c2(0, 0), sy = c2(0, 0);
             for (int s = 0; s < p.NS; ++s) {
-                sx = cadd(sx, P6[(((size_t)s * 6 + i) * N + n) * nmB + mB]);
-                sy = cadd(sy, P6[(((size_t)s * 6 + 3 + i) * N + n) * nmB + mB]);
+                sx = cadd(sx, widen(P6[(((size_t)s * 6 + i) * N + n) * nmB + mB]));
+                sy = cadd(sy, widen(P6[(((size_t)s * 6 + 3 + i) * N + n) * nmB + mB]));
             }
             vec(i)[n] = sx;
             vec(3 + i)[n] = sy;
@@ -851,8 +882,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags,
         __syncthreads();
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MODE_THREADS) {
-                Y[((size_t)i * N + n) * nmB + mB] = vec(6 + i)[n];
-                Y[((size_t)(3 + i) * N + n) * nmB + mB] = vec(12 + i)[n];
+                Y[((size_t)i * N + n) * nmB + mB] = narrow<YT>(vec(6 + i)[n]);
+                Y[((size_t)(3 + i) * N + n) * nmB + mB] = narrow<YT>(vec(12 + i)[n]);
             }
     } else {
         for (int i = 0; i < 3; ++i)
@@ -1245,8 +1276,8 @@ __global__ void k_axpy(long long n, double a, const double* __restrict__ x, doub
 size_t plane_lds_bytes(const KP& p, int mode) {
     const int ng3 = (mode == PLANE_JVP) ? 6 : 3, ng1 = (mode == PLANE_ADJ) ? 3 : 0;
     const int npf = (mode == PLANE_ADJ) ? 12 : 3;
-    const size_t nxf = 3 * ng3 + ng1;
-    return (size_t)(p.Nx + p.Nz) * 16 + nxf * p.XS * p.nkz * 16 + (size_t)npf * p.XS * p.Nz * 8;
+    const size_t nxf = 3 * ng3 + ng1, r = p.prec == PREC_FP32 ? 4 : 8;
+    return (size_t)(p.Nx + p.Nz) * 2 * r + nxf * p.XS * p.nkz * 2 * r + (size_t)npf * p.XS * p.Nz * r;
 }
 
 size_t mode_lds_bytes(const KP& p) {
@@ -1272,37 +1303,68 @@ static int padded_ny(const KP& p) { return (p.N + 15) / 16 * 16; }
         default: return hipErrorInvalidValue;                     \
     }
 
-hipError_t launch_synth(const KP& p, hipStream_t s, const double2* u, double2* Y) {
-    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_synth<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, u, Y));
+// The y-value and partial arrays are raw storage: FP64 complex for PREC_FP64,
+// FP32 complex (half the bytes, same buffers) for PREC_FP32.
+template <class YT>
+static hipError_t synth_t(const KP& p, hipStream_t s, const double2* u, void* Y) {
+    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL((k_synth<NP, YT>), mode_grid(p), dim3(MODE_THREADS),
+                                                      mode_lds_bytes(p), s, p, u, static_cast<YT*>(Y)));
     return hipGetLastError();
 }
 
-hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const double2* Y1, const double2* Y2,
-                        double2* out) {
+hipError_t launch_synth(const KP& p, hipStream_t s, const double2* u, void* Y) {
+    return p.prec == PREC_FP32 ? synth_t<float2>(p, s, u, Y) : synth_t<double2>(p, s, u, Y);
+}
+
+template <class R>
+static hipError_t plane_t(const KP& p, hipStream_t s, int mode, const void* Y1, const void* Y2, void* out) {
+    typedef C<R> CR;
     const dim3 grid((unsigned)((p.B * p.NS * p.N + NXCD - 1) / NXCD * NXCD)), block(PLANE_THREADS);
     const size_t lds = plane_lds_bytes(p, mode);
+    const CR* y1 = static_cast<const CR*>(Y1);
+    const CR* y2 = static_cast<const CR*>(Y2);
+    CR* o = static_cast<CR*>(out);
     if (mode == PLANE_FWD)
-        hipLaunchKernelGGL(k_plane<PLANE_FWD>, grid, block, lds, s, p, Y1, Y2, out);
+        hipLaunchKernelGGL((k_plane<PLANE_FWD, R>), grid, block, lds, s, p, y1, y2, o);
     else if (mode == PLANE_JVP)
-        hipLaunchKernelGGL(k_plane<PLANE_JVP>, grid, block, lds, s, p, Y1, Y2, out);
+        hipLaunchKernelGGL((k_plane<PLANE_JVP, R>), grid, block, lds, s, p, y1, y2, o);
     else
-        hipLaunchKernelGGL(k_plane<PLANE_ADJ>, grid, block, lds, s, p, Y1, Y2, out);
+        hipLaunchKernelGGL((k_plane<PLANE_ADJ, R>), grid, block, lds, s, p, y1, y2, o);
     return hipGetLastError();
 }
 
-hipError_t launch_mode_res(const KP& p, hipStream_t s, int flags, const double2* P3,
-                           const double2* u, double2* r, double* cost_part, double2* a,
-                           double2* Atil) {
-    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_mode_res<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, flags,
-                       P3, u, r, cost_part, a, Atil));
+hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const void* Y1, const void* Y2, void* out) {
+    return p.prec == PREC_FP32 ? plane_t<float>(p, s, mode, Y1, Y2, out) : plane_t<double>(p, s, mode, Y1, Y2, out);
+}
+
+template <class YT>
+static hipError_t mode_res_t(const KP& p, hipStream_t s, int flags, const void* P3, const double2* u,
+                             double2* r, double* cost_part, double2* a, void* Atil) {
+    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL((k_mode_res<NP, YT>), mode_grid(p), dim3(MODE_THREADS),
+                                                      mode_lds_bytes(p), s, p, flags, static_cast<const YT*>(P3),
+                                                      u, r, cost_part, a, static_cast<YT*>(Atil)));
     return hipGetLastError();
 }
 
-hipError_t launch_mode_grad(const KP& p, hipStream_t s, int flags, const double2* P6,
-                            const double2* a, double dtau, double2* u_or_out, double2* Y) {
-    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_mode_grad<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, flags,
-                       P6, a, dtau, u_or_out, Y));
+hipError_t launch_mode_res(const KP& p, hipStream_t s, int flags, const void* P3, const double2* u,
+                           double2* r, double* cost_part, double2* a, void* Atil) {
+    return p.prec == PREC_FP32 ? mode_res_t<float2>(p, s, flags, P3, u, r, cost_part, a, Atil)
+                               : mode_res_t<double2>(p, s, flags, P3, u, r, cost_part, a, Atil);
+}
+
+template <class YT>
+static hipError_t mode_grad_t(const KP& p, hipStream_t s, int flags, const void* P6, const double2* a,
+                              double dtau, double2* u_or_out, void* Y) {
+    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL((k_mode_grad<NP, YT>), mode_grid(p), dim3(MODE_THREADS),
+                                                      mode_lds_bytes(p), s, p, flags, static_cast<const YT*>(P6),
+                                                      a, dtau, u_or_out, static_cast<YT*>(Y)));
     return hipGetLastError();
+}
+
+hipError_t launch_mode_grad(const KP& p, hipStream_t s, int flags, const void* P6, const double2* a,
+                            double dtau, double2* u_or_out, void* Y) {
+    return p.prec == PREC_FP32 ? mode_grad_t<float2>(p, s, flags, P6, a, dtau, u_or_out, Y)
+                               : mode_grad_t<double2>(p, s, flags, P6, a, dtau, u_or_out, Y);
 }
 
 hipError_t launch_project(const KP& p, hipStream_t s, const double2* g, double2* out) {

@@ -12,6 +12,7 @@ struct KP {
     int B, nmB;              // guesses per launch, B * nm
     long long nstate;        // state-vector length of one guess
     int XS, NS;              // x-slab width of the physical-space kernels, number of slabs
+    int prec;                // PREC_FP64, or PREC_FP32 for the physical-space transforms and products
     double lam, nu, alpha, beta;
     const double* M;         // M_COUNT fixed matrices, N x N slots, transposed
     const double* minfo;     // per-mode scalars (MI_STRIDE each)
@@ -26,6 +27,10 @@ struct KP {
     const double* ygl;       // Gauss-Lobatto points
     const int* indep;        // independent-mode index (state vector)
 };
+
+// Precision of the physical-space stage (transforms in x and z, products, and
+// the y-value / partial arrays that carry them); per-mode work is always FP64.
+enum Precision { PREC_FP64 = 0, PREC_FP32 = 1 };
 
 // Physical-space kernel variants.
 enum PlaneMode { PLANE_FWD = 0, PLANE_JVP = 1, PLANE_ADJ = 2 };
@@ -48,14 +53,16 @@ size_t plane_lds_bytes(const KP& p, int mode);
 size_t mode_lds_bytes(const KP& p);
 
 // All launches are asynchronous on `s`; they return the launch error code.
-hipError_t launch_synth(const KP& p, hipStream_t s, const double2* u, double2* Y);
-hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const double2* Y1,
-                        const double2* Y2, double2* out);
-hipError_t launch_mode_res(const KP& p, hipStream_t s, int flags, const double2* P3,
+// Y, Y1, Y2, P3, P6, Atil and out of launch_plane are y-value / partial
+// arrays whose element type follows p.prec (double2 or float2).
+hipError_t launch_synth(const KP& p, hipStream_t s, const double2* u, void* Y);
+hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const void* Y1, const void* Y2,
+                        void* out);
+hipError_t launch_mode_res(const KP& p, hipStream_t s, int flags, const void* P3,
                            const double2* u, double2* r, double* cost_part, double2* a,
-                           double2* Atil);
-hipError_t launch_mode_grad(const KP& p, hipStream_t s, int flags, const double2* P6,
-                            const double2* a, double dtau, double2* u_or_out, double2* Y);
+                           void* Atil);
+hipError_t launch_mode_grad(const KP& p, hipStream_t s, int flags, const void* P6,
+                            const double2* a, double dtau, double2* u_or_out, void* Y);
 hipError_t launch_project(const KP& p, hipStream_t s, const double2* g, double2* out);
 // Per-guess reductions: out[g * stride + c] = sum (op 0) or max (op 1) over
 // rows i < n of part[(g * n + i) * stride + c], for groups g < ngroups.

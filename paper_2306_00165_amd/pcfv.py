@@ -29,8 +29,10 @@ EXPORTS = [
     "pcfv_residual", "pcfv_cost", "pcfv_jvp", "pcfv_adjoint", "pcfv_project", "pcfv_descend",
     "pcfv_norms", "pcfv_pack_state", "pcfv_unpack_state", "pcfv_check_state",
     "pcfv_time_kernels", "pcfv_last_error", "pcfv_host_table", "pcfv_dmd_extrapolate",
-    "pcfv_host_dmd",
+    "pcfv_host_dmd", "pcfv_set_precision",
 ]
+
+FP64, MIXED = 0, 1
 
 
 class Config(ctypes.Structure):
@@ -52,13 +54,14 @@ class DescentOpts(ctypes.Structure):
                 ("grow_tol", ctypes.c_double), ("max_halvings", ctypes.c_int),
                 ("dmd_window", ctypes.c_int), ("dmd_stride", ctypes.c_int), ("dmd_gap", ctypes.c_int),
                 ("dmd_start", ctypes.c_double), ("dmd_accept", ctypes.c_double),
-                ("dmd_buffer", ctypes.c_void_p)]
+                ("dmd_buffer", ctypes.c_void_p), ("fp64_below", ctypes.c_double)]
 
 
 class DescentReport(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_longlong), ("tau", ctypes.c_double), ("cost", ctypes.c_double),
                 ("rel_res", ctypes.c_double), ("dtau_final", ctypes.c_double),
-                ("n_halvings", ctypes.c_int), ("n_dmd", ctypes.c_int), ("n_dmd_accepted", ctypes.c_int)]
+                ("n_halvings", ctypes.c_int), ("n_dmd", ctypes.c_int), ("n_dmd_accepted", ctypes.c_int),
+                ("steps_fp32", ctypes.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,6 +83,8 @@ def load_library(path=_LIB_PATH):
     lib.pcfv_get_layout.argtypes = [vp, ctypes.POINTER(Layout)]
     lib.pcfv_set_stream.restype = i
     lib.pcfv_set_stream.argtypes = [vp, vp]
+    lib.pcfv_set_precision.restype = i
+    lib.pcfv_set_precision.argtypes = [vp, i]
     lib.pcfv_residual.restype = i
     lib.pcfv_residual.argtypes = [vp, vp, vp, dp]
     lib.pcfv_cost.restype = i
@@ -118,9 +123,9 @@ class PcfvError(RuntimeError):
 
 
 def make_config(Nx, Ny, Nz, Lx=2 * np.pi / 1.14, Lz=2 * np.pi / 2.5, Re=400.0, dt_im=0.25,
-                batch=1):
-    return Config(float(Lx), float(Lz), float(Re), int(Nx), int(Ny), int(Nz), float(dt_im), 0,
-                  int(batch))
+                batch=1, precision=FP64):
+    return Config(float(Lx), float(Lz), float(Re), int(Nx), int(Ny), int(Nz), float(dt_im),
+                  int(precision), int(batch))
 
 
 def workspace_bytes(cfg):
@@ -167,11 +172,11 @@ class Context:
     batch = 1 and (batch, 3, 2Kx+1, Kz+1, Ny) otherwise."""
 
     def __init__(self, Nx, Ny, Nz, Lx=2 * np.pi / 1.14, Lz=2 * np.pi / 2.5, Re=400.0,
-                 dt_im=0.25, device="cuda:0", stream=None, batch=1):
+                 dt_im=0.25, device="cuda:0", stream=None, batch=1, precision=FP64):
         self.torch = torch
         self.device = torch.device(device)
         self.batch = int(batch)
-        self.cfg = make_config(Nx, Ny, Nz, Lx, Lz, Re, dt_im, self.batch)
+        self.cfg = make_config(Nx, Ny, Nz, Lx, Lz, Re, dt_im, self.batch, precision)
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:
             raise PcfvError(EINVAL, "invalid configuration")
@@ -196,7 +201,7 @@ class Context:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.pcfv_destroy(h)
             self._h = None
 
@@ -258,11 +263,17 @@ class Context:
         self._check(_lib.pcfv_project(self._h, _ptr(g), _ptr(out)))
         return out
 
+    def set_precision(self, precision):
+        """FP64 or MIXED (FP32 transforms and products) for later calls."""
+        self._check(_lib.pcfv_set_precision(self._h, int(precision)))
+
     def descend(self, u, max_steps, dtau, rel_tol=0.0, check_every=None, grow_tol=0.0,
                 max_halvings=0, dmd_window=0, dmd_stride=1, dmd_gap=0, dmd_start=0.0,
-                dmd_accept=10.0):
+                dmd_accept=10.0, fp64_below=0.0):
         """Advance u (a contiguous complex128 device tensor) in place; returns
-        (status, report dict).  dmd_window > 0 enables DMD extrapolation."""
+        (status, report dict).  dmd_window > 0 enables DMD extrapolation;
+        fp64_below > 0 on a MIXED context switches to FP64 below that relative
+        residual."""
         if not (u.is_contiguous() and u.dtype == self.torch.complex128 and tuple(u.shape) == self.shape):
             raise ValueError("u must be a contiguous complex128 device tensor of the context shape")
         buf = None
@@ -272,7 +283,7 @@ class Context:
         o = DescentOpts(int(max_steps), float(dtau), float(rel_tol),
                         int(check_every or max(1, max_steps)), float(grow_tol), int(max_halvings),
                         int(dmd_window), int(dmd_stride), int(dmd_gap), float(dmd_start), float(dmd_accept),
-                        ctypes.c_void_p(buf.data_ptr()) if buf is not None else None)
+                        ctypes.c_void_p(buf.data_ptr()) if buf is not None else None, float(fp64_below))
         rep = DescentReport()
         st = _lib.pcfv_descend(self._h, _ptr(u), ctypes.byref(o), ctypes.byref(rep))
         if st not in (OK, ENOTCONV, ENAN, EDIVERGED):

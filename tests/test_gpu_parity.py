@@ -377,3 +377,86 @@ def test_descend_with_dmd_equals_composed_entry_points(ctxs):
           f"state rel err {rel(to_np(u), u_ref):.3e} tol {tol:.1e}", flush=True)
     assert r_s == r_ref
     assert rel(to_np(u), u_ref) < tol
+
+
+# -- mixed precision: FP32 transforms and products, FP64 solves --------------------
+
+# The FP32 stage rounds each y-value once and accumulates sums of at most
+# n_kx + 2 n_kz + N_z + XS (< 100 at these grids) terms per output, so by the
+# recursive-summation bound its relative error on the products is below
+# 100 eps32; the Stokes solves, projection and update are FP64 and contract
+# it.  Stated bound for every mixed-precision result against the FP64 oracle:
+TOL32 = 100 * float(np.finfo(np.float32).eps)
+
+
+@pytest.fixture(scope="module")
+def mixed_ctxs():
+    from paper_2306_00165_amd.pcfv import Context, MIXED
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            dims = GRIDS[name]
+            print(f"[gpu] mixed context {name} {dims}", flush=True)
+            g = Grid(*dims)
+            cache[name] = (g, Method(g), Context(*dims, precision=MIXED))
+        return cache[name]
+    return get
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2", "ragged", "odd"])
+def test_mixed_residual_adjoint_and_step(mixed_ctxs, name):
+    import torch
+    g, m, c = mixed_ctxs(name)
+    u = guess(g, 1)
+    w = guess(g, 2)
+    r = to_np(c.residual(u))
+    rr = m.residual(u)
+    e_r = rel(r, rr)
+    e_a = rel(to_np(c.adjoint(u, w)), m.adjoint(u, w))
+    U = torch.as_tensor(u).to("cuda:0").contiguous()
+    c.descend(U, max_steps=1, dtau=0.02)
+    u1, _ = m.descent_step(u, 0.02)
+    e_s = float(np.abs(to_np(U) - u1).max() / np.abs(u1 - u).max())
+    print(f"[gpu] mixed {name}: residual {e_r:.2e} adjoint {e_a:.2e} step {e_s:.2e} (bound {TOL32:.1e})")
+    assert e_r < TOL32 and e_a < TOL32 and e_s < TOL32
+    assert e_r > 1e-12          # the FP32 stage really ran
+
+
+def test_mixed_descent_refines_in_fp64(ctxs, mixed_ctxs):
+    """fp64_below switches the rest of a call to FP64: always-below gives the
+    FP64 trajectory bit for bit, never-below stays FP32 throughout, and a
+    threshold met mid-run gives both phases; the context keeps its precision."""
+    import torch
+    g, m, c64 = ctxs("cfg1")
+    _, _, c32 = mixed_ctxs("cfg1")
+    u0 = torch.as_tensor(inputs.config1_guess()).to("cuda:0").contiguous()
+    ref = u0.clone()
+    c64.descend(ref, max_steps=300, dtau=0.02, check_every=50)
+    a = u0.clone()
+    st, rep = c32.descend(a, max_steps=300, dtau=0.02, check_every=50, fp64_below=1e30)
+    assert rep["steps_fp32"] == 0 and torch.equal(a, ref)
+    b = u0.clone()
+    st, rep = c32.descend(b, max_steps=300, dtau=0.02, check_every=50, fp64_below=1e-30)
+    assert rep["steps_fp32"] == 300
+    assert rel(to_np(b) - to_np(u0), to_np(ref) - to_np(u0)) < TOL32
+    mid = u0.clone()
+    _, rep100 = c64.descend(mid, max_steps=150, dtau=0.02)
+    d = u0.clone()
+    st, rep = c32.descend(d, max_steps=300, dtau=0.02, check_every=50, fp64_below=rep100["rel_res"])
+    assert 0 < rep["steps_fp32"] < 300
+    assert abs(rep["cost"] - m.cost(to_np(d))) < 1e-10 * rep["cost"]
+    # the context is still mixed afterwards
+    assert rel(to_np(c32.residual(u0)), to_np(c64.residual(u0))) > 1e-12
+
+
+def test_set_precision_rejects_unknown_values(mixed_ctxs):
+    from paper_2306_00165_amd.pcfv import PcfvError, FP64, MIXED
+    g, m, c = mixed_ctxs("tiny")
+    u = guess(g, 3)
+    with pytest.raises(PcfvError):
+        c.set_precision(7)
+    c.set_precision(FP64)
+    assert rel(to_np(c.residual(u)), m.residual(u)) < TOL
+    c.set_precision(MIXED)
+    assert rel(to_np(c.residual(u)), m.residual(u)) < TOL32
