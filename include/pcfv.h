@@ -236,6 +236,45 @@ pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* 
  * failed pcfv_create on the calling thread.  Valid until the next call. */
 const char* pcfv_last_error(const pcfv_ctx* ctx);
 
+/* Autotuner over the launch shape of the physical-space kernels: for every
+ * candidate x-slab width (divisors of Nx up to 8 that fit the LDS budget, at
+ * least half the default) and work-group size (256, 512 threads) it times
+ * `steps` descent steps (after one untimed step) on a scratch copy of u with
+ * dtau = 0, keeps the fastest for every later call, and reports each
+ * candidate in entries[0..cap) (n_entries gets the count).  u is not
+ * modified.  Synchronises. */
+typedef struct {
+    int xs;               /* x-slab width */
+    int plane_threads;    /* work-group size of the physical-space kernels */
+    double ms_per_step;   /* measured descent-step time */
+} pcfv_tune_entry;
+pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_entry* entries, int cap,
+                          int* n_entries);
+/* The launch shape in use (x-slab width, physical-space work-group size). */
+pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads);
+
+/* Groups (batching over uneven grids): n contexts, each with its own grid,
+ * Re, batch and tables but one precision, are advanced together; every
+ * descent step is one launch per stage (physical-space forward, residual and
+ * transposed solve, physical-space adjoint, gradient/projection/update) over
+ * all members, so small members share the chip instead of running one after
+ * another.  The group owns a stream and n + 1 small device records; the
+ * members (and their workspaces) must outlive it.  The physical-space work
+ * group size is members[0]'s. */
+typedef struct pcfv_group pcfv_group;
+pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out);
+void pcfv_group_destroy(pcfv_group* group);
+/* steps plain descent steps (Sec. 4 step (5)) of every member: u[k] is member
+ * k's field array (device, in place), dtau[k] its step.  graph_steps > 0
+ * captures that many steps in a HIP graph once (reused across calls, since
+ * fields and steps are read from the device records) and replays it; the
+ * remainder runs as plain launches.  Waits for the members' streams first
+ * and synchronises before returning.  Costs are read with pcfv_cost on each
+ * member afterwards. */
+pcfv_status pcfv_group_descend(pcfv_group* group, double* const* u, const double* dtau, long long steps,
+                               int graph_steps);
+const char* pcfv_group_last_error(const pcfv_group* group);
+
 /* Host-side copy of a constant table for cfg, computed without a device (for
  * tests of the setup arithmetic).  which: 0 fixed matrices (27 slots of
  * Ny x Ny, each matrix stored transposed), 1 per-mode scalars, 2 Helmholtz diagonals,

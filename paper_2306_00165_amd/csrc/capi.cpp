@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -88,12 +89,33 @@ KP base_kp(const pcfv_config& c) {
     }
     p.NS = c.Nx / p.XS;
     p.prec = c.precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
+    p.pthreads = 512;
     return p;
+}
+
+// x-slab widths the autotuner may choose: divisors of Nx up to 8 whose
+// physical-space kernels fit the LDS budget, no narrower than half the
+// default (so the partial buffers are at most twice the default's).
+std::vector<int> xs_candidates(const pcfv_config& c) {
+    KP p = base_kp(c);
+    p.prec = PREC_FP64;
+    const int xs0 = p.XS;
+    std::vector<int> out;
+    for (int xs = 8; xs >= 1; --xs) {
+        if (c.Nx % xs || 2 * xs < xs0) continue;
+        p.XS = xs;
+        if (plane_lds_bytes(p, PLANE_ADJ) <= kMaxPlaneLds && plane_lds_bytes(p, PLANE_JVP) <= kMaxPlaneLds)
+            out.push_back(xs);
+    }
+    if (out.empty()) out.push_back(xs0);
+    return out;
 }
 
 WsLayout layout(const pcfv_config& c) {
     const KP p = base_kp(c);
-    const size_t N = p.N, nm = p.nm, NS = p.NS, nmB = p.nmB, B = p.B;
+    const std::vector<int> xsc = xs_candidates(c);
+    const size_t N = p.N, nm = p.nm, NS = c.Nx / *std::min_element(xsc.begin(), xsc.end()), nmB = p.nmB,
+                 B = p.B;
     size_t sz[W_COUNT];
     sz[W_MATS] = (size_t)M_COUNT * N * N * 8;
     sz[W_MINFO] = nm * MI_STRIDE * 8;
@@ -709,6 +731,229 @@ pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* 
 }
 
 const char* pcfv_last_error(const pcfv_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_entry* entries, int cap,
+                          int* n_entries) {
+    if (!ctx || !u || steps < 1) return fail(ctx, PCFV_EINVAL, "invalid autotune arguments");
+    const size_t fbytes = (size_t)ctx->nfield() * 16;
+    const KP saved = ctx->kp;
+    std::vector<pcfv_tune_entry> res;
+    hipEvent_t e0, e1;
+    PCFV_TRY(hipEventCreate(&e0), "event");
+    PCFV_TRY(hipEventCreate(&e1), "event");
+    double best = std::numeric_limits<double>::infinity();
+    KP best_kp = saved;
+    pcfv_status st = PCFV_OK;
+    for (int xs : xs_candidates(ctx->cfg)) {
+        for (int nt : {256, 512}) {
+            ctx->kp.XS = xs;
+            ctx->kp.NS = ctx->cfg.Nx / xs;
+            ctx->kp.pthreads = nt;
+            hipError_t he = hipMemcpyAsync(ctx->tmp, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream);
+            if (he == hipSuccess) he = launch_synth(ctx->kp, ctx->stream, ctx->tmp, ctx->Y);
+            // one untimed step, then `steps` timed ones (dtau = 0 leaves the copy unchanged)
+            for (int i = 0; i <= steps && st == PCFV_OK && he == hipSuccess; ++i) {
+                if (i == 1) he = hipEventRecord(e0, ctx->stream);
+                if (he == hipSuccess) st = descent_step(ctx, reinterpret_cast<double*>(ctx->tmp), 0.0);
+            }
+            if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            float ms = 0;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he != hipSuccess) st = hip_check(ctx, he, "autotune");
+            if (st != PCFV_OK) break;
+            pcfv_tune_entry t{xs, nt, ms / steps};
+            res.push_back(t);
+            if (t.ms_per_step < best) {
+                best = t.ms_per_step;
+                best_kp = ctx->kp;
+            }
+        }
+        if (st != PCFV_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->kp = (st == PCFV_OK) ? best_kp : saved;
+    if (st != PCFV_OK) return st;
+    if (n_entries) *n_entries = (int)res.size();
+    for (int i = 0; entries && i < (int)res.size() && i < cap; ++i) entries[i] = res[i];
+    return PCFV_OK;
+}
+
+pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads) {
+    if (!ctx) return PCFV_EINVAL;
+    if (xs) *xs = ctx->kp.XS;
+    if (plane_threads) *plane_threads = ctx->kp.pthreads;
+    return PCFV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Groups: several contexts advanced by one launch per stage
+// ---------------------------------------------------------------------------
+
+struct pcfv_group {
+    std::vector<pcfv_ctx*> members;
+    std::vector<GroupMember> host;   // n + 1 records (the last is the sentinel)
+    GroupMember* dev = nullptr;      // device copy
+    GroupLaunch gl{};
+    hipStream_t stream = nullptr;
+    int graph_steps = 0;             // steps captured in `exec` (0: none)
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+};
+
+namespace {
+
+pcfv_status gfail(pcfv_group* g, pcfv_status s, const std::string& msg) {
+    if (g) g->err = msg;
+    return s;
+}
+
+#define PCFV_GTRY(expr, what)                                                                  \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess) return gfail(g, PCFV_EDEVICE, std::string(what) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+pcfv_status group_step(pcfv_group* g) {
+    for (int k : {GK_PLANE_FWD, GK_MODE_RES, GK_PLANE_ADJ, GK_MODE_GRAD})
+        PCFV_GTRY(launch_group(g->gl, g->stream, k), "grouped launch");
+    return PCFV_OK;
+}
+
+void drop_graph(pcfv_group* g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    g->exec = nullptr;
+    g->graph_steps = 0;
+}
+
+pcfv_status capture(pcfv_group* g, int nsteps) {
+    drop_graph(g);
+    PCFV_GTRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    pcfv_status st = PCFV_OK;
+    for (int i = 0; i < nsteps && st == PCFV_OK; ++i) st = group_step(g);
+    hipGraph_t graph = nullptr;
+    hipError_t he = hipStreamEndCapture(g->stream, &graph);
+    if (st != PCFV_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    PCFV_GTRY(he, "end capture");
+    he = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    PCFV_GTRY(he, "instantiate graph");
+    g->graph_steps = nsteps;
+    return PCFV_OK;
+}
+
+}  // namespace
+
+pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out) {
+    g_create_err.clear();
+    if (!out || !members || n < 1) {
+        g_create_err = "invalid group arguments";
+        return PCFV_EINVAL;
+    }
+    *out = nullptr;
+    for (int k = 0; k < n; ++k)
+        if (!members[k] || members[k]->kp.prec != members[0]->kp.prec) {
+            g_create_err = "group members must be non-NULL and share one precision";
+            return PCFV_EINVAL;
+        }
+    pcfv_group* g = new pcfv_group();
+    g->members.assign(members, members + n);
+    g->host.resize(n + 1);
+    GroupLaunch& gl = g->gl;
+    gl.n = n;
+    gl.prec = members[0]->kp.prec;
+    gl.pthreads = members[0]->kp.pthreads;
+    long long items[2] = {0, 0};
+    for (int k = 0; k < n; ++k) {
+        pcfv_ctx* c = members[k];
+        GroupMember& m = g->host[k];
+        m.kp = c->kp;
+        m.kp.pthreads = gl.pthreads;
+        m.item0[GPH_PLANE] = (int)items[GPH_PLANE];
+        m.item0[GPH_MODE] = (int)items[GPH_MODE];
+        items[GPH_PLANE] += (long long)c->kp.B * c->kp.NS * c->kp.N;
+        items[GPH_MODE] += c->kp.nmB;
+        m.dtau = 0;
+        m.u = nullptr;
+        m.Y = c->Y;
+        m.P3 = c->P3;
+        m.P6 = c->P6;
+        m.Atil = c->Atil;
+        m.a = c->a;
+        m.part = c->part;
+        gl.np = std::max(gl.np, padded_ny(c->kp.N));
+        for (int md : {PLANE_FWD, PLANE_JVP, PLANE_ADJ})
+            gl.plane_lds[md] = std::max(gl.plane_lds[md], plane_lds_bytes(m.kp, md));
+        gl.mode_lds = std::max(gl.mode_lds, mode_lds_bytes(c->kp));
+    }
+    if (items[0] > INT_MAX / 2 || items[1] > INT_MAX / 2) {
+        delete g;
+        g_create_err = "group too large";
+        return PCFV_EINVAL;
+    }
+    GroupMember& sent = g->host[n];
+    sent = GroupMember{};
+    sent.item0[GPH_PLANE] = (int)items[GPH_PLANE];
+    sent.item0[GPH_MODE] = (int)items[GPH_MODE];
+    gl.items[GPH_PLANE] = (int)items[GPH_PLANE];
+    gl.items[GPH_MODE] = (int)items[GPH_MODE];
+    hipError_t he = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipMalloc(&g->dev, sizeof(GroupMember) * (n + 1));
+    if (he != hipSuccess) {
+        g_create_err = std::string("group setup: ") + hipGetErrorString(he);
+        pcfv_group_destroy(g);
+        return PCFV_EDEVICE;
+    }
+    gl.gm = g->dev;
+    *out = g;
+    return PCFV_OK;
+}
+
+void pcfv_group_destroy(pcfv_group* g) {
+    if (!g) return;
+    drop_graph(g);
+    if (g->dev) (void)hipFree(g->dev);
+    if (g->stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+}
+
+pcfv_status pcfv_group_descend(pcfv_group* g, double* const* u, const double* dtau, long long steps,
+                               int graph_steps) {
+    if (!g || !u || !dtau || steps < 0 || graph_steps < 0) return gfail(g, PCFV_EINVAL, "invalid arguments");
+    const int n = g->gl.n;
+    for (int k = 0; k < n; ++k) {
+        if (!u[k] || !std::isfinite(dtau[k])) return gfail(g, PCFV_EINVAL, "NULL field or non-finite dtau");
+        g->host[k].u = dd(u[k]);
+        g->host[k].dtau = dtau[k];
+    }
+    // the members' own streams may still be writing their fields
+    for (pcfv_ctx* c : g->members) PCFV_GTRY(hipStreamSynchronize(c->stream), "member stream");
+    PCFV_GTRY(hipMemcpyAsync(g->dev, g->host.data(), sizeof(GroupMember) * (n + 1), hipMemcpyHostToDevice,
+                             g->stream),
+              "member records");
+    PCFV_GTRY(launch_group(g->gl, g->stream, GK_SYNTH), "grouped synth");
+    long long done = 0;
+    if (graph_steps > 0 && steps >= graph_steps) {
+        if (g->graph_steps != graph_steps) {
+            pcfv_status st = capture(g, graph_steps);
+            if (st != PCFV_OK) return st;
+        }
+        for (; done + graph_steps <= steps; done += graph_steps)
+            PCFV_GTRY(hipGraphLaunch(g->exec, g->stream), "graph launch");
+    }
+    for (; done < steps; ++done) {
+        pcfv_status st = group_step(g);
+        if (st != PCFV_OK) return st;
+    }
+    PCFV_GTRY(hipStreamSynchronize(g->stream), "synchronize");
+    return PCFV_OK;
+}
+
+const char* pcfv_group_last_error(const pcfv_group* g) { return g ? g->err.c_str() : g_create_err.c_str(); }
 
 int pcfv_host_dmd(const double* Ge_hi, const double* Ge_lo, int M, double dtau, double* coef,
                   size_t cap) {

@@ -29,7 +29,6 @@ constexpr int MODE_THREADS = 256;              // one Fourier mode per work grou
 constexpr int MODE_WAVES = MODE_THREADS / WAVE;
 constexpr int KSPLIT = 4;                      // lanes sharing one output row of a contraction
 constexpr int ROWS_PER_WAVE = WAVE / KSPLIT;   // 16
-constexpr int PLANE_THREADS = 512;
 constexpr int MODE_VECS = 24;                  // LDS vectors (length N) used by the mode kernels
 constexpr int RED_SLOTS = 16;                  // doubles per wave for block reductions
 
@@ -495,10 +494,10 @@ __device__ void project0(const KP& p, const double2* gx, const double2* gz, doub
 // y-values of u and of du/dy for the three components: Y[c] = C u_c,
 // Y[3+c] = C D u_c (Gauss-Lobatto synthesis).
 template <int NP, class YT>
-__global__ __launch_bounds__(MODE_THREADS) void k_synth(KP p, const double2* __restrict__ u,
-                                                        YT* __restrict__ Y) {
+__device__ __forceinline__ void synth_body(const KP& p, int mB, const double2* __restrict__ u,
+                                           YT* __restrict__ Y) {
     extern __shared__ double2 sm[];
-    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    const int N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
@@ -514,10 +513,9 @@ __global__ __launch_bounds__(MODE_THREADS) void k_synth(KP p, const double2* __r
             Y[((size_t)f * N + j) * nmB + mB] = narrow<YT>(V[(3 + f) * N + j]);
 }
 
-template <int MODE, class R>
-__global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const C<R>* __restrict__ Y1,
-                                                         const C<R>* __restrict__ Y2,
-                                                         C<R>* __restrict__ out) {
+template <int MODE, class R, int PLANE_THREADS>
+__device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __restrict__ Y1,
+                                           const C<R>* __restrict__ Y2, C<R>* __restrict__ out) {
     typedef C<R> CR;
     extern __shared__ __align__(16) unsigned char smraw[];
     CR* sm = reinterpret_cast<CR*>(smraw);
@@ -526,7 +524,6 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const C<R>* __res
     constexpr int NG1 = (MODE == PLANE_ADJ) ? 3 : 0;  // adjoint fields: single outputs
     constexpr int NXF = 3 * NG3 + NG1;
     constexpr int NZF = (MODE == PLANE_ADJ) ? 9 : 3;  // after the forward z stage
-    const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= p.B * p.NS * p.N) return;
     const int jb = item / p.NS, s = item - jb * p.NS;   // the slabs of a plane run on one XCD
     const int b = jb / p.N, j = jb - b * p.N;          // guess, Gauss-Lobatto plane
@@ -739,12 +736,12 @@ __global__ __launch_bounds__(PLANE_THREADS) void k_plane(KP p, const C<R>* __res
 }
 
 template <int NP, class YT>
-__global__ __launch_bounds__(MODE_THREADS) void k_mode_res(
-    KP p, int flags, const YT* __restrict__ P3, const double2* __restrict__ u,
+__device__ __forceinline__ void mode_res_body(
+    const KP& p, int mB, int flags, const YT* __restrict__ P3, const double2* __restrict__ u,
     double2* __restrict__ r, double* __restrict__ cost_part, double2* __restrict__ a,
     YT* __restrict__ Atil) {
     extern __shared__ double2 sm[];
-    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    const int N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
@@ -817,13 +814,11 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_res(
 }
 
 template <int NP, class YT>
-__global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags,
-                                                            const YT* __restrict__ P6,
-                                                            const double2* __restrict__ a,
-                                                            double dtau, double2* __restrict__ uo,
-                                                            YT* __restrict__ Y) {
+__device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, const YT* __restrict__ P6,
+                                               const double2* __restrict__ a, double dtau,
+                                               double2* __restrict__ uo, YT* __restrict__ Y) {
     extern __shared__ double2 sm[];
-    const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
+    const int N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
@@ -889,6 +884,90 @@ __global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags,
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MODE_THREADS) uo[so + ((size_t)i * nm + m) * N + n] = Fs[i][n];
     }
+}
+
+// Single-context kernels: one logical work item per work group.
+template <int NP, class YT>
+__global__ __launch_bounds__(MODE_THREADS) void k_synth(KP p, const double2* __restrict__ u,
+                                                        YT* __restrict__ Y) {
+    synth_body<NP, YT>(p, xcd_item(blockIdx.x, gridDim.x), u, Y);
+}
+
+template <int MODE, class R, int NT>
+__global__ __launch_bounds__(NT) void k_plane(KP p, const C<R>* __restrict__ Y1, const C<R>* __restrict__ Y2,
+                                              C<R>* __restrict__ out) {
+    plane_body<MODE, R, NT>(p, xcd_item(blockIdx.x, gridDim.x), Y1, Y2, out);
+}
+
+template <int NP, class YT>
+__global__ __launch_bounds__(MODE_THREADS) void k_mode_res(KP p, int flags, const YT* __restrict__ P3,
+                                                           const double2* __restrict__ u,
+                                                           double2* __restrict__ r, double* __restrict__ cost_part,
+                                                           double2* __restrict__ a, YT* __restrict__ Atil) {
+    mode_res_body<NP, YT>(p, xcd_item(blockIdx.x, gridDim.x), flags, P3, u, r, cost_part, a, Atil);
+}
+
+template <int NP, class YT>
+__global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags, const YT* __restrict__ P6,
+                                                            const double2* __restrict__ a, double dtau,
+                                                            double2* __restrict__ uo, YT* __restrict__ Y) {
+    mode_grad_body<NP, YT>(p, xcd_item(blockIdx.x, gridDim.x), flags, P6, a, dtau, uo, Y);
+}
+
+// Grouped kernels: one launch covers every member of a group (contexts of
+// different grids, Re and batch).  The logical items of member k are
+// [item0[k], item0[k+1]); each work group finds its member by binary search
+// and runs the single-context body with that member's parameters.
+__device__ __forceinline__ int group_member(const GroupMember* __restrict__ gm, int n, int it, int phase) {
+    int lo = 0, hi = n;  // invariant: gm[lo].item0[phase] <= it < gm[hi].item0[phase] (gm[n] sentinel)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (gm[mid].item0[phase] <= it) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int NP, class YT>
+__global__ __launch_bounds__(MODE_THREADS) void kg_synth(const GroupMember* __restrict__ gm, int n) {
+    const int it = xcd_item(blockIdx.x, gridDim.x);
+    if (it >= gm[n].item0[GPH_MODE]) return;
+    const int k = group_member(gm, n, it, GPH_MODE);
+    const GroupMember& g = gm[k];
+    synth_body<NP, YT>(g.kp, it - g.item0[GPH_MODE], g.u, static_cast<YT*>(g.Y));
+}
+
+template <int MODE, class R, int NT>
+__global__ __launch_bounds__(NT) void kg_plane(const GroupMember* __restrict__ gm, int n) {
+    const int it = xcd_item(blockIdx.x, gridDim.x);
+    if (it >= gm[n].item0[GPH_PLANE]) return;
+    const int k = group_member(gm, n, it, GPH_PLANE);
+    const GroupMember& g = gm[k];
+    if (MODE == PLANE_FWD)
+        plane_body<MODE, R, NT>(g.kp, it - g.item0[GPH_PLANE], static_cast<const C<R>*>(g.Y), nullptr,
+                                static_cast<C<R>*>(g.P3));
+    else
+        plane_body<MODE, R, NT>(g.kp, it - g.item0[GPH_PLANE], static_cast<const C<R>*>(g.Y),
+                                static_cast<const C<R>*>(g.Atil), static_cast<C<R>*>(g.P6));
+}
+
+template <int NP, class YT>
+__global__ __launch_bounds__(MODE_THREADS) void kg_mode_res(const GroupMember* __restrict__ gm, int n) {
+    const int it = xcd_item(blockIdx.x, gridDim.x);
+    if (it >= gm[n].item0[GPH_MODE]) return;
+    const int k = group_member(gm, n, it, GPH_MODE);
+    const GroupMember& g = gm[k];
+    mode_res_body<NP, YT>(g.kp, it - g.item0[GPH_MODE], RES_COST | RES_ADJ, static_cast<const YT*>(g.P3), g.u,
+                          nullptr, g.part, g.a, static_cast<YT*>(g.Atil));
+}
+
+template <int NP, class YT>
+__global__ __launch_bounds__(MODE_THREADS) void kg_mode_grad(const GroupMember* __restrict__ gm, int n) {
+    const int it = xcd_item(blockIdx.x, gridDim.x);
+    if (it >= gm[n].item0[GPH_MODE]) return;
+    const int k = group_member(gm, n, it, GPH_MODE);
+    const GroupMember& g = gm[k];
+    mode_grad_body<NP, YT>(g.kp, it - g.item0[GPH_MODE], GRAD_PROJECT | GRAD_UPDATE, static_cast<const YT*>(g.P6),
+                           g.a, g.dtau, g.u, static_cast<YT*>(g.Y));
 }
 
 template <int NP>
@@ -1288,7 +1367,8 @@ static dim3 mode_grid(const KP& p) { return dim3((unsigned)((p.nmB + NXCD - 1) /
 
 // The per-mode kernels are compiled for Ny padded to a multiple of 16 so that
 // every contraction loop is fully unrolled.
-static int padded_ny(const KP& p) { return (p.N + 15) / 16 * 16; }
+int padded_ny(int N) { return (N + 15) / 16 * 16; }
+static int padded_ny(const KP& p) { return padded_ny(p.N); }
 
 #define PCFV_DISPATCH_NP(np, ...)                                 \
     switch (np) {                                                 \
@@ -1316,25 +1396,31 @@ hipError_t launch_synth(const KP& p, hipStream_t s, const double2* u, void* Y) {
     return p.prec == PREC_FP32 ? synth_t<float2>(p, s, u, Y) : synth_t<double2>(p, s, u, Y);
 }
 
-template <class R>
+template <class R, int NT>
 static hipError_t plane_t(const KP& p, hipStream_t s, int mode, const void* Y1, const void* Y2, void* out) {
     typedef C<R> CR;
-    const dim3 grid((unsigned)((p.B * p.NS * p.N + NXCD - 1) / NXCD * NXCD)), block(PLANE_THREADS);
+    const dim3 grid((unsigned)((p.B * p.NS * p.N + NXCD - 1) / NXCD * NXCD)), block(NT);
     const size_t lds = plane_lds_bytes(p, mode);
     const CR* y1 = static_cast<const CR*>(Y1);
     const CR* y2 = static_cast<const CR*>(Y2);
     CR* o = static_cast<CR*>(out);
     if (mode == PLANE_FWD)
-        hipLaunchKernelGGL((k_plane<PLANE_FWD, R>), grid, block, lds, s, p, y1, y2, o);
+        hipLaunchKernelGGL((k_plane<PLANE_FWD, R, NT>), grid, block, lds, s, p, y1, y2, o);
     else if (mode == PLANE_JVP)
-        hipLaunchKernelGGL((k_plane<PLANE_JVP, R>), grid, block, lds, s, p, y1, y2, o);
+        hipLaunchKernelGGL((k_plane<PLANE_JVP, R, NT>), grid, block, lds, s, p, y1, y2, o);
     else
-        hipLaunchKernelGGL((k_plane<PLANE_ADJ, R>), grid, block, lds, s, p, y1, y2, o);
+        hipLaunchKernelGGL((k_plane<PLANE_ADJ, R, NT>), grid, block, lds, s, p, y1, y2, o);
     return hipGetLastError();
 }
 
 hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const void* Y1, const void* Y2, void* out) {
-    return p.prec == PREC_FP32 ? plane_t<float>(p, s, mode, Y1, Y2, out) : plane_t<double>(p, s, mode, Y1, Y2, out);
+    if (p.pthreads == 256)
+        return p.prec == PREC_FP32 ? plane_t<float, 256>(p, s, mode, Y1, Y2, out)
+                                   : plane_t<double, 256>(p, s, mode, Y1, Y2, out);
+    if (p.pthreads == 512)
+        return p.prec == PREC_FP32 ? plane_t<float, 512>(p, s, mode, Y1, Y2, out)
+                                   : plane_t<double, 512>(p, s, mode, Y1, Y2, out);
+    return hipErrorInvalidValue;
 }
 
 template <class YT>
@@ -1365,6 +1451,44 @@ hipError_t launch_mode_grad(const KP& p, hipStream_t s, int flags, const void* P
                             double dtau, double2* u_or_out, void* Y) {
     return p.prec == PREC_FP32 ? mode_grad_t<float2>(p, s, flags, P6, a, dtau, u_or_out, Y)
                                : mode_grad_t<double2>(p, s, flags, P6, a, dtau, u_or_out, Y);
+}
+
+static dim3 grid8(int items) { return dim3((unsigned)((items + NXCD - 1) / NXCD * NXCD)); }
+
+template <class R, int NT, class YT>
+static hipError_t group_t(const GroupLaunch& g, hipStream_t s, int which) {
+    const dim3 gp = grid8(g.items[GPH_PLANE]), gmo = grid8(g.items[GPH_MODE]);
+    switch (which) {
+        case GK_SYNTH:
+            PCFV_DISPATCH_NP(g.np, hipLaunchKernelGGL((kg_synth<NP, YT>), gmo, dim3(MODE_THREADS), g.mode_lds, s,
+                                                      g.gm, g.n));
+            break;
+        case GK_PLANE_FWD:
+            hipLaunchKernelGGL((kg_plane<PLANE_FWD, R, NT>), gp, dim3(NT), g.plane_lds[PLANE_FWD], s, g.gm, g.n);
+            break;
+        case GK_MODE_RES:
+            PCFV_DISPATCH_NP(g.np, hipLaunchKernelGGL((kg_mode_res<NP, YT>), gmo, dim3(MODE_THREADS), g.mode_lds,
+                                                      s, g.gm, g.n));
+            break;
+        case GK_PLANE_ADJ:
+            hipLaunchKernelGGL((kg_plane<PLANE_ADJ, R, NT>), gp, dim3(NT), g.plane_lds[PLANE_ADJ], s, g.gm, g.n);
+            break;
+        case GK_MODE_GRAD:
+            PCFV_DISPATCH_NP(g.np, hipLaunchKernelGGL((kg_mode_grad<NP, YT>), gmo, dim3(MODE_THREADS), g.mode_lds,
+                                                      s, g.gm, g.n));
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_group(const GroupLaunch& g, hipStream_t s, int which) {
+    if (g.pthreads == 256)
+        return g.prec == PREC_FP32 ? group_t<float, 256, float2>(g, s, which) : group_t<double, 256, double2>(g, s, which);
+    if (g.pthreads == 512)
+        return g.prec == PREC_FP32 ? group_t<float, 512, float2>(g, s, which) : group_t<double, 512, double2>(g, s, which);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_project(const KP& p, hipStream_t s, const double2* g, double2* out) {

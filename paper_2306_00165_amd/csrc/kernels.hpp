@@ -13,6 +13,7 @@ struct KP {
     long long nstate;        // state-vector length of one guess
     int XS, NS;              // x-slab width of the physical-space kernels, number of slabs
     int prec;                // PREC_FP64, or PREC_FP32 for the physical-space transforms and products
+    int pthreads;            // threads per work group of the physical-space kernels (256 or 512)
     double lam, nu, alpha, beta;
     const double* M;         // M_COUNT fixed matrices, N x N slots, transposed
     const double* minfo;     // per-mode scalars (MI_STRIDE each)
@@ -48,6 +49,39 @@ enum GradFlags {
     GRAD_PROJECT = 1,  // f = -P g instead of g
     GRAD_UPDATE = 2,   // u += dtau f and synthesise the new u (descent step)
 };
+
+// One member of a grouped launch (a context: its parameters and buffers).
+// item0[GPH_PLANE] / item0[GPH_MODE]: first logical work item of the member in
+// the physical-space / per-mode launches; entry n of the array is a sentinel
+// holding the totals.
+enum GroupPhase { GPH_PLANE = 0, GPH_MODE = 1 };
+struct GroupMember {
+    KP kp;
+    int item0[2];
+    double dtau;
+    double2* u;       // the member's fields (updated in place)
+    void* Y;          // y-values (storage type per precision)
+    void* P3;         // forward-transform partials
+    void* P6;
+    void* Atil;       // y-values of a = S* r
+    double2* a;
+    double* part;     // per-mode cost partials
+};
+
+// Everything a grouped launch needs besides the member array.
+struct GroupLaunch {
+    const GroupMember* gm;   // device array of n + 1 entries
+    int n;
+    int items[2];            // total logical items per phase
+    int np;                  // padded Ny (largest over the members)
+    int prec;                // common precision
+    int pthreads;            // common physical-space work-group size
+    size_t plane_lds[3];     // largest LDS per plane mode over the members
+    size_t mode_lds;
+};
+enum GroupKernel { GK_SYNTH = 0, GK_PLANE_FWD = 1, GK_MODE_RES = 2, GK_PLANE_ADJ = 3, GK_MODE_GRAD = 4 };
+hipError_t launch_group(const GroupLaunch& g, hipStream_t s, int which);
+int padded_ny(int N);
 
 size_t plane_lds_bytes(const KP& p, int mode);
 size_t mode_lds_bytes(const KP& p);

@@ -29,7 +29,8 @@ EXPORTS = [
     "pcfv_residual", "pcfv_cost", "pcfv_jvp", "pcfv_adjoint", "pcfv_project", "pcfv_descend",
     "pcfv_norms", "pcfv_pack_state", "pcfv_unpack_state", "pcfv_check_state",
     "pcfv_time_kernels", "pcfv_last_error", "pcfv_host_table", "pcfv_dmd_extrapolate",
-    "pcfv_host_dmd", "pcfv_set_precision",
+    "pcfv_host_dmd", "pcfv_set_precision", "pcfv_autotune", "pcfv_get_tuning", "pcfv_group_create",
+    "pcfv_group_destroy", "pcfv_group_descend", "pcfv_group_last_error",
 ]
 
 FP64, MIXED = 0, 1
@@ -55,6 +56,10 @@ class DescentOpts(ctypes.Structure):
                 ("dmd_window", ctypes.c_int), ("dmd_stride", ctypes.c_int), ("dmd_gap", ctypes.c_int),
                 ("dmd_start", ctypes.c_double), ("dmd_accept", ctypes.c_double),
                 ("dmd_buffer", ctypes.c_void_p), ("fp64_below", ctypes.c_double)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("xs", ctypes.c_int), ("plane_threads", ctypes.c_int), ("ms_per_step", ctypes.c_double)]
 
 
 class DescentReport(ctypes.Structure):
@@ -110,6 +115,18 @@ def load_library(path=_LIB_PATH):
     lib.pcfv_dmd_extrapolate.argtypes = [vp, vp, i, d, vp, dp, ctypes.POINTER(i)]
     lib.pcfv_host_dmd.restype = i
     lib.pcfv_host_dmd.argtypes = [dp, dp, i, d, dp, ctypes.c_size_t]
+    lib.pcfv_autotune.restype = i
+    lib.pcfv_autotune.argtypes = [vp, vp, i, ctypes.POINTER(TuneEntry), i, ctypes.POINTER(i)]
+    lib.pcfv_get_tuning.restype = i
+    lib.pcfv_get_tuning.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.pcfv_group_create.restype = i
+    lib.pcfv_group_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp)]
+    lib.pcfv_group_destroy.restype = None
+    lib.pcfv_group_destroy.argtypes = [vp]
+    lib.pcfv_group_descend.restype = i
+    lib.pcfv_group_descend.argtypes = [vp, ctypes.POINTER(vp), dp, ctypes.c_longlong, i]
+    lib.pcfv_group_last_error.restype = ctypes.c_char_p
+    lib.pcfv_group_last_error.argtypes = [vp]
     return lib
 
 
@@ -342,3 +359,52 @@ class Context:
 
     def synchronize(self):
         self.stream.synchronize()
+
+    def autotune(self, u, steps=20):
+        """Time every launch-shape candidate on a copy of u and keep the
+        fastest; returns the list of (xs, plane_threads, ms_per_step)."""
+        u = self._field(u)
+        cap = 64
+        ent = (TuneEntry * cap)()
+        n = ctypes.c_int(0)
+        self._check(_lib.pcfv_autotune(self._h, _ptr(u), int(steps), ent, cap, ctypes.byref(n)))
+        return [(e.xs, e.plane_threads, e.ms_per_step) for e in ent[:n.value]]
+
+    def tuning(self):
+        xs, nt = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(_lib.pcfv_get_tuning(self._h, ctypes.byref(xs), ctypes.byref(nt)))
+        return xs.value, nt.value
+
+
+class Group:
+    """Several contexts (different grids, Re, batch; one precision) advanced
+    together with one launch per stage of each descent step."""
+
+    def __init__(self, contexts):
+        self.contexts = list(contexts)
+        arr = (ctypes.c_void_p * len(self.contexts))(*[c._h.value for c in self.contexts])
+        h = ctypes.c_void_p()
+        st = _lib.pcfv_group_create(arr, len(self.contexts), ctypes.byref(h))
+        if st != OK:
+            raise PcfvError(st, "pcfv_group_create failed: " + _lib.pcfv_last_error(None).decode())
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.pcfv_group_destroy(h)
+            self._h = None
+
+    def descend(self, fields, dtaus, steps, graph_steps=0):
+        """Advance fields[k] (contiguous complex128 device tensors of member
+        k's shape) in place by `steps` descent steps with dtaus[k]."""
+        if len(fields) != len(self.contexts) or len(dtaus) != len(self.contexts):
+            raise ValueError("one field and one dtau per member")
+        for c, f in zip(self.contexts, fields):
+            if not (f.is_contiguous() and f.dtype == c.torch.complex128 and tuple(f.shape) == c.shape):
+                raise ValueError("fields must be contiguous complex128 device tensors of the member shapes")
+        ptrs = (ctypes.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
+        dt = (ctypes.c_double * len(fields))(*[float(x) for x in dtaus])
+        st = _lib.pcfv_group_descend(self._h, ptrs, dt, int(steps), int(graph_steps))
+        if st != OK:
+            raise PcfvError(st, _lib.pcfv_group_last_error(self._h).decode())

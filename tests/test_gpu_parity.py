@@ -460,3 +460,85 @@ def test_set_precision_rejects_unknown_values(mixed_ctxs):
     assert rel(to_np(c.residual(u)), m.residual(u)) < TOL
     c.set_precision(MIXED)
     assert rel(to_np(c.residual(u)), m.residual(u)) < TOL32
+
+
+# -- groups of uneven grids, HIP graphs, autotuner ---------------------------------
+
+def _group_members(precision=0):
+    from paper_2306_00165_amd.pcfv import Context
+    specs = [((16, 25, 16), 400.0, 2), ((12, 17, 9), 380.0, 1), ((32, 33, 32), 420.0, 1)]
+    out = []
+    for i, (dims, Re, B) in enumerate(specs):
+        g = Grid(*dims, Re=Re)
+        fields = [inputs.random_field(*dims, energy=1e-3, seed=40 + 3 * i + b) for b in range(B)]
+        u = np.stack(fields) if B > 1 else fields[0]
+        out.append((g, Context(*dims, Re=Re, batch=B, precision=precision), u))
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_group_of_uneven_grids_matches_each_member(precision):
+    """One launch per stage over three members (different grids, Re and
+    batch) gives every member exactly its own single-context result, with and
+    without HIP-graph replay; the Re = 380 member also matches the oracle."""
+    import torch
+    from paper_2306_00165_amd.pcfv import Group
+    mem = _group_members(precision)
+    dtaus = [0.02, 0.015, 0.01]
+    grp = Group([c for _, c, _ in mem])
+    fields = [torch.as_tensor(u).to("cuda:0").contiguous() for _, _, u in mem]
+    plain = [f.clone() for f in fields]
+    graph = [f.clone() for f in fields]
+    grp.descend(plain, dtaus, 7)
+    grp.descend(graph, dtaus, 7, graph_steps=3)
+    for (g, c, u), f, d, p_, q_ in zip(mem, fields, dtaus, plain, graph):
+        ref = f.clone()
+        c.descend(ref, max_steps=7, dtau=d)
+        assert torch.equal(p_, ref) and torch.equal(q_, ref)
+    if precision == 0:
+        g, c, u = mem[1]
+        m = Method(g)
+        for _ in range(7):
+            u, _ = m.descent_step(u, dtaus[1])
+        assert rel(to_np(plain[1]), u) < TOL
+
+
+def test_group_graph_is_reused_across_calls():
+    """The captured graph reads fields and steps from device records, so it is
+    replayed across calls with new fields and new dtau, with eager work in
+    between, and every replay agrees with plain launches."""
+    import torch
+    from paper_2306_00165_amd.pcfv import Group
+    mem = _group_members()
+    grp = Group([c for _, c, _ in mem])
+    a = [torch.as_tensor(u).to("cuda:0").contiguous() for _, _, u in mem]
+    b = [x.clone() for x in a]
+    for rep, dts in enumerate([[0.02, 0.015, 0.01], [0.01, 0.01, 0.005], [0.02, 0.02, 0.01]]):
+        grp.descend(a, dts, 4, graph_steps=2)
+        grp.descend(b, dts, 4)
+        for x, y in zip(a, b):
+            assert torch.equal(x, y), rep
+        for (g, c, u), x in zip(mem, a):
+            c.cost(x)                      # eager work on the members' own streams
+
+
+def test_autotune_keeps_parity(ctxs):
+    """The autotuner times every launch-shape candidate and keeps the fastest;
+    results with the chosen shape still match the oracle."""
+    import torch
+    from paper_2306_00165_amd.pcfv import Context
+    g = Grid(32, 33, 32)
+    m = Method(g)
+    c = Context(32, 33, 32)
+    u = guess(g, 9)
+    ent = c.autotune(u, steps=5)
+    assert ent and all(32 % xs == 0 and nt in (256, 512) for xs, nt, _ in ent)
+    best = min(ent, key=lambda e: e[2])
+    assert c.tuning() == (best[0], best[1])
+    print(f"[gpu] autotune 32x33x32: {ent}")
+    assert rel(to_np(c.residual(u)), m.residual(u)) < TOL
+    U = torch.as_tensor(u).to("cuda:0").contiguous()
+    c.descend(U, max_steps=3, dtau=0.02)
+    for _ in range(3):
+        u, _ = m.descent_step(u, 0.02)
+    assert rel(to_np(U), u) < TOL
