@@ -63,6 +63,7 @@ extern "C" {
 #endif
 
 typedef struct pcfv_ctx pcfv_ctx;
+struct pcfv_learned_model;
 
 typedef enum {
     PCFV_OK = 0,
@@ -170,6 +171,11 @@ typedef struct {
      * ||r||/||u_b+u|| < fp64_below at a check, the rest of the call runs in
      * FP64 (the refinement phase); <= 0 keeps the context's precision. */
     double fp64_below;
+    /* Learned extrapolator (may be NULL): at the end of every DMD window its
+     * proposal from the window's last model->window snapshots competes with
+     * the DMD candidate; each guess takes the cheaper of the two by true
+     * cost, under the same dmd_accept rule. */
+    const struct pcfv_learned_model* learned;
 } pcfv_descent_opts;
 
 typedef struct {
@@ -182,6 +188,7 @@ typedef struct {
     int n_dmd;            /* DMD extrapolations performed                            */
     int n_dmd_accepted;   /* guesses restarted from an extrapolated state             */
     long long steps_fp32; /* steps taken with the FP32 physical-space stage           */
+    int n_learned_accepted; /* restarts from a learned proposal (counted in n_dmd_accepted) */
 } pcfv_descent_report;
 
 /* Advance every guess of u in place with the same dtau.  Returns PCFV_OK when
@@ -274,6 +281,115 @@ void pcfv_group_destroy(pcfv_group* group);
 pcfv_status pcfv_group_descend(pcfv_group* group, double* const* u, const double* dtau, long long steps,
                                int graph_steps);
 const char* pcfv_group_last_error(const pcfv_group* group);
+
+/* ---------------------------------------------------------------------------
+ * Learned extrapolator (alongside the DMD extrapolation of Sec. 6): a
+ * multilayer perceptron maps a window of W snapshots, projected on r POD
+ * modes of the state vector, to the POD coefficients of the descent limit.
+ * Matrix products run on the matrix cores in BF16 with FP32 accumulation;
+ * FP32 master weights are trained with Adam.  Every proposal is judged by
+ * the true residual of the method, and DMD stays the fallback.
+ * ------------------------------------------------------------------------- */
+#define PCFV_MLP_MAX_LAYERS 8
+
+/* dims[0] inputs, dims[n_layers] outputs; ReLU after every layer but the
+ * last.  Parameters (FP32, host order): for each layer l, W_l (dims[l] x
+ * dims[l+1], row-major: input index major) then b_l (dims[l+1]). */
+typedef struct {
+    int n_layers;
+    int dims[PCFV_MLP_MAX_LAYERS + 1];
+    int max_batch;        /* rows per call, at most */
+} pcfv_mlp_config;
+typedef struct pcfv_mlp pcfv_mlp;
+
+long long pcfv_mlp_param_count(const pcfv_mlp_config* cfg);           /* 0 if cfg is invalid */
+size_t pcfv_mlp_workspace_bytes(const pcfv_mlp_config* cfg);           /* 0 if cfg is invalid */
+/* workspace: caller-owned device memory, 256-byte aligned, outliving the MLP. */
+pcfv_status pcfv_mlp_create(const pcfv_mlp_config* cfg, void* hip_stream, void* workspace, pcfv_mlp** out);
+void pcfv_mlp_destroy(pcfv_mlp* mlp);
+const char* pcfv_mlp_last_error(const pcfv_mlp* mlp);   /* NULL: the last create error */
+/* Load FP32 parameters from the host (and their BF16 copies); resets Adam.  Synchronises. */
+pcfv_status pcfv_mlp_set_params(pcfv_mlp* mlp, const float* params_host);
+pcfv_status pcfv_mlp_get_params(pcfv_mlp* mlp, float* params_host);    /* synchronises */
+/* Y (device FP32, B x dims[L]) from X (device FP32, B x dims[0]), 1 <= B <= max_batch. */
+pcfv_status pcfv_mlp_forward(pcfv_mlp* mlp, const float* X, float* Y, int B);
+/* Forward pass, loss = mean over all B x dims[L] outputs of (Y - T)^2 and its
+ * gradient with respect to every parameter (kept in the MLP); loss_host, if
+ * non-NULL, receives the loss and the call synchronises. */
+pcfv_status pcfv_mlp_grad(pcfv_mlp* mlp, const float* X, const float* T, int B, float* loss_host);
+/* One Adam step (Kingma & Ba, bias-corrected) with the kept gradient. */
+pcfv_status pcfv_mlp_adam_step(pcfv_mlp* mlp, float lr, float beta1, float beta2, float eps);
+/* Test hook: copy an internal buffer of the last forward / gradient call to
+ * the host: PCFV_MLP_ACT the BF16 input of `layer` (B x dims[layer]),
+ * PCFV_MLP_OUT the FP32 output of the last gradient call, PCFV_MLP_DZ the BF16
+ * gradient with respect to the pre-activation of `layer` (B x dims[layer+1]),
+ * PCFV_MLP_GRAD every parameter gradient (FP32).  Synchronises. */
+enum { PCFV_MLP_ACT = 0, PCFV_MLP_OUT = 1, PCFV_MLP_DZ = 2, PCFV_MLP_GRAD = 3 };
+pcfv_status pcfv_mlp_read(pcfv_mlp* mlp, int what, int layer, void* host, size_t cap_bytes);
+
+/* POD of S snapshots X (device, S x n, row-major) by the method of
+ * snapshots: mean (n), the r leading orthonormal modes basis (r x n,
+ * row-major) of the centred snapshots and, if non-NULL, their singular values
+ * sigma_host (r).  scratch: device, pcfv_pod_scratch_bytes(S, n, r) bytes.
+ * 2 <= S, r <= S.  PCFV_EINVAL if fewer than r modes have positive energy,
+ * PCFV_ENOTCONV if the eigen-iteration fails.  Synchronises. */
+size_t pcfv_pod_scratch_bytes(int S, long long n, int r);
+pcfv_status pcfv_pod_build(void* hip_stream, const double* X, int S, long long n, int r, double* mean, double* basis,
+                           double* sigma_host, void* scratch);
+/* coef (m x r) = (X - mean) basis^T for X (m x n); scratch: device,
+ * pcfv_pod_project_scratch_bytes(m, n, r) bytes.  Asynchronous. */
+size_t pcfv_pod_project_scratch_bytes(int m, long long n, int r);
+pcfv_status pcfv_pod_project(void* hip_stream, const double* X, int m, long long n, int r, const double* mean,
+                             const double* basis, double* coef, void* scratch);
+/* X (m x n) = mean + coef basis.  Asynchronous. */
+pcfv_status pcfv_pod_reconstruct(void* hip_stream, const double* coef, int m, long long n, int r, const double* mean,
+                                 const double* basis, double* X);
+
+/* A trained extrapolator.  Input features of guess b: for w < W-1 the
+ * differences c_w - c_{W-1} of the POD coefficients of the window's snapshots
+ * and c_{W-1} itself (W r values, window position major), normalised as
+ * (x - in_mu) * in_isd; the MLP output y gives the step to the limit in POD
+ * coefficients, dc = y / out_isd + out_mu, and the proposal is the last
+ * snapshot plus that step, psi_{W-1} + dc basis (what the r modes do not
+ * resolve is kept from the last snapshot).  All pointers are device memory
+ * owned by the caller. */
+typedef struct pcfv_learned_model {
+    int window;               /* W */
+    int r;                    /* POD modes */
+    const double* pod_mean;   /* n_state */
+    const double* pod_basis;  /* r x n_state */
+    const float* in_mu;       /* W r */
+    const float* in_isd;      /* W r */
+    const float* out_mu;      /* r */
+    const float* out_isd;     /* r */
+    pcfv_mlp* mlp;            /* dims[0] = W r, dims[last] = r, max_batch >= the context batch */
+    void* scratch;            /* pcfv_learned_scratch_bytes(ctx, window, r) bytes */
+} pcfv_learned_model;
+size_t pcfv_learned_scratch_bytes(const pcfv_ctx* ctx, int window, int r);
+
+/* Training set of the extrapolator from POD coefficients: c (device, [W][B][r]
+ * doubles: W window snapshots of B training windows) and ct (device, B x r:
+ * the coefficients of each window's descent limit, or NULL).  Writes the
+ * features X (device FP32, B x W r) and, if ct, the targets T (B x r) of the
+ * model's definition.  fit != 0 first computes the normalisation from this
+ * set (per-column mean and 1/max(std, 1e-12)) into in_mu, in_isd and, if ct,
+ * out_mu, out_isd; fit = 0 uses the given ones.  Asynchronous on hip_stream. */
+pcfv_status pcfv_learned_prepare(void* hip_stream, int W, int B, int r, const double* c, const double* ct, int fit,
+                                 float* in_mu, float* in_isd, float* out_mu, float* out_isd, float* X, float* T);
+
+/* Minibatch training: `epochs` passes over the N rows of (X, T) (device FP32,
+ * N x dims[0] and N x dims[L]) in batches of `batch` rows (a permutation per
+ * epoch drawn from `seed` by SplitMix64; a short last batch is dropped), one
+ * Adam step (lr, 0.9, 0.999, 1e-8) per batch.  idx: device scratch of N ints;
+ * Xb, Tb: device scratch of batch x dims[0] and batch x dims[L] floats.
+ * loss_host (if non-NULL) receives the mean loss of every epoch.  Synchronises. */
+pcfv_status pcfv_mlp_fit(pcfv_mlp* mlp, const float* X, const float* T, int N, int batch, int epochs, float lr,
+                         unsigned long long seed, int* idx, float* Xb, float* Tb, float* loss_host);
+/* Proposal for every guess from the window snaps (device, [W][batch][n_state],
+ * oldest first, spaced as in training): u_out (batch fields) and its cost
+ * J^2 per guess in cost_host (may be NULL).  Synchronises. */
+pcfv_status pcfv_learned_propose(pcfv_ctx* ctx, const pcfv_learned_model* model, const double* snaps, double* u_out,
+                                 double* cost_host);
 
 /* Host-side copy of a constant table for cfg, computed without a device (for
  * tests of the setup arithmetic).  which: 0 fixed matrices (27 slots of

@@ -25,10 +25,13 @@ per-Fourier-mode matrices and library FFTs, no blocking or fusion:
                 step (5)), diagnostics and the minimal real state vector
                 (Sec. 6.2).
 * ``dmd``    -- dynamic mode decomposition and extrapolation (Sec. 6).
+* ``mlp``, ``pod`` -- the learned extrapolator that sits beside DMD: a
+                bfloat16-quantised multilayer perceptron with back-propagation
+                and Adam, and the POD of snapshot sets.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
 library routines, brute force on tiny grids and invariants of the method.
 """
 
 from .grid import Grid  # noqa: F401
-from . import cheb, flow, stokes, method, state, dmd  # noqa: F401
+from . import cheb, flow, stokes, method, state, dmd, mlp, pod  # noqa: F401

@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libpcfv.so")
-SOURCES = ["csrc/tables.cpp", "csrc/dmd.cpp", "csrc/kernels.hip", "csrc/capi.cpp"]
+SOURCES = ["csrc/tables.cpp", "csrc/dmd.cpp", "csrc/eigsym.cpp", "csrc/kernels.hip", "csrc/learned.hip",
+           "csrc/capi.cpp", "csrc/capi_learned.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

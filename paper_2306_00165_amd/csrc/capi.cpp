@@ -14,6 +14,8 @@
 #include "../../include/pcfv.h"
 #include "dmd.hpp"
 #include "kernels.hpp"
+#include "learned.hpp"
+#include "learned_api.hpp"
 #include "tables.hpp"
 
 using namespace pcfv;
@@ -242,6 +244,78 @@ pcfv_status descent_step(pcfv_ctx* ctx, double* u, double dtau) {
     return PCFV_OK;
 }
 
+
+// Scratch of the learned proposal: POD coefficients of the window, features,
+// MLP output, predicted coefficients, state vectors, projection partials.
+struct LearnedScratch {
+    size_t c, x, y, cs, psi, part, total;
+    int splits;
+};
+
+LearnedScratch learned_scratch(const KP& p, int W, int r) {
+    LearnedScratch L{};
+    const long long n = p.nstate;
+    const int rows = W * p.B;
+    const long long tiles = (long long)((rows + 63) / 64) * ((r + 63) / 64);
+    L.splits = (int)std::min(64LL, std::max(1LL, std::min(512 / std::max(1LL, tiles), n / 256)));
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t at = o;
+        o += up(b);
+        return at;
+    };
+    L.c = take((size_t)rows * r * 8);
+    L.x = take((size_t)p.B * W * r * 4);
+    L.y = take((size_t)p.B * r * 4);
+    L.cs = take((size_t)p.B * r * 8);
+    L.psi = take((size_t)p.B * n * 8);
+    L.part = take((size_t)L.splits * rows * r * 8);
+    L.total = o;
+    return L;
+}
+
+// Learned proposal of every guess into u_out (field layout) and its cost.
+pcfv_status learned_core(pcfv_ctx* ctx, const pcfv_learned_model* md, const double* snaps, double* u_out,
+                         std::vector<double>& cost) {
+    const KP& p = ctx->kp;
+    const int W = md->window, r = md->r, B = p.B;
+    int din = 0, dout = 0, mb = 0;
+    if (!md->mlp || !md->pod_mean || !md->pod_basis || !md->in_mu || !md->in_isd || !md->out_mu || !md->out_isd ||
+        !md->scratch || W < 1 || r < 1)
+        return fail(ctx, PCFV_EINVAL, "incomplete learned model");
+    mlp_shape(md->mlp, &din, &dout, &mb);
+    if (din != W * r || dout != r || mb < B) return fail(ctx, PCFV_EINVAL, "MLP shape does not match the model");
+    const LearnedScratch L = learned_scratch(p, W, r);
+    char* w = reinterpret_cast<char*>(md->scratch);
+    double* c = reinterpret_cast<double*>(w + L.c);
+    float* x = reinterpret_cast<float*>(w + L.x);
+    float* y = reinterpret_cast<float*>(w + L.y);
+    double* cs = reinterpret_cast<double*>(w + L.cs);
+    double* psi = reinterpret_cast<double*>(w + L.psi);
+    double* part = reinterpret_cast<double*>(w + L.part);
+    const long long n = p.nstate;
+    hipStream_t s = ctx->stream;
+    PCFV_TRY(launch_gemm_f64(s, W * B, r, n, snaps, n, false, md->pod_basis, n, true, md->pod_mean, nullptr, c, r,
+                             L.splits, part),
+             "POD projection");
+    PCFV_TRY(launch_features(s, W, B, r, c, md->in_mu, md->in_isd, x), "features");
+    pcfv_status st = mlp_forward_on(md->mlp, s, x, y, B);
+    if (st != PCFV_OK) return fail(ctx, st, "MLP forward failed");
+    // psi = psi_{W-1} + dc basis: the step lies in the POD space, the last
+    // snapshot keeps everything the modes do not resolve
+    PCFV_TRY(launch_prediction(s, B, r, y, md->out_mu, md->out_isd, cs), "prediction");
+    PCFV_TRY(hipMemcpyAsync(psi, snaps + (size_t)(W - 1) * B * n, (size_t)B * n * 8, hipMemcpyDeviceToDevice, s),
+             "last snapshot");
+    PCFV_TRY(launch_gemm_f64(s, B, (int)n, r, cs, r, false, md->pod_basis, n, false, nullptr, nullptr, psi, n, 1,
+                             nullptr, true),
+             "POD step");
+    PCFV_TRY(launch_unpack(p, s, psi, dd(u_out)), "unpack");
+    PCFV_TRY(launch_synth(p, s, cd(u_out), ctx->Y), "synth");
+    st = residual_core(ctx, u_out, nullptr, true);
+    if (st != PCFV_OK) return st;
+    cost.assign(B, 0.0);
+    return read_scalars(ctx, 1, 0, cost.data());
+}
 
 // DMD extrapolation of the window snaps ([M][B][n_state]); writes the best
 // candidate of each guess to u_out (last snapshot if none), its cost and rank.
@@ -500,7 +574,7 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
     const size_t fbytes1 = (size_t)3 * p.nm * p.N * 16;
     double dtau = o->dtau, tau = 0;
     long long steps = 0, steps32 = 0;
-    int halvings = 0, n_dmd = 0, n_acc = 0;
+    int halvings = 0, n_dmd = 0, n_acc = 0, n_lacc = 0;
     std::vector<double> cost, ntot, cost_prev;
     pcfv_descent_report local{};
     if (!rep) rep = &local;
@@ -521,6 +595,7 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
         rep->n_dmd = n_dmd;
         rep->n_dmd_accepted = n_acc;
         rep->steps_fp32 = steps32;
+        rep->n_learned_accepted = n_lacc;
         return st;
     };
     // FP32 -> FP64 once every guess is below fp64_below: new y-values and cost
@@ -577,14 +652,29 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
                              reinterpret_cast<double*>(cand), dcost, drank);
                 if (s != PCFV_OK) return s;
                 ++n_dmd;
-                for (int b = 0; b < B; ++b)
-                    if (drank[b] > 0 && dcost[b] < o->dmd_accept * cnow[b]) {
-                        PCFV_TRY(hipMemcpyAsync(reinterpret_cast<char*>(u) + b * fbytes1,
-                                                reinterpret_cast<const char*>(cand) + b * fbytes1, fbytes1,
-                                                hipMemcpyDeviceToDevice, ctx->stream),
-                                 "accept");
-                        ++n_acc;
-                    }
+                std::vector<double> lcost;
+                double2* lcand = ctx->r;  // scratch: not written by the steps
+                if (o->learned) {
+                    const int W = o->learned->window;
+                    if (W > o->dmd_window) return report(fail(ctx, PCFV_EINVAL, "learned window exceeds dmd_window"));
+                    s = learned_core(ctx, o->learned, o->dmd_buffer + (size_t)(o->dmd_window - W) * B * p.nstate,
+                                     reinterpret_cast<double*>(lcand), lcost);
+                    if (s != PCFV_OK) return s;
+                }
+                for (int b = 0; b < B; ++b) {
+                    const bool dok = drank[b] > 0 && std::isfinite(dcost[b]);
+                    const bool lok = o->learned && std::isfinite(lcost[b]);
+                    const bool use_l = lok && (!dok || lcost[b] < dcost[b]);
+                    const double best = use_l ? lcost[b] : (dok ? dcost[b] : HUGE_VAL);
+                    if (!(best < o->dmd_accept * cnow[b])) continue;
+                    const double2* src = use_l ? lcand : cand;
+                    PCFV_TRY(hipMemcpyAsync(reinterpret_cast<char*>(u) + b * fbytes1,
+                                            reinterpret_cast<const char*>(src) + b * fbytes1, fbytes1,
+                                            hipMemcpyDeviceToDevice, ctx->stream),
+                             "accept");
+                    ++n_acc;
+                    if (use_l) ++n_lacc;
+                }
                 PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth");
                 s = cost_and_norm(ctx, u, cost, ntot);
                 if (s != PCFV_OK) return s;
@@ -954,6 +1044,22 @@ pcfv_status pcfv_group_descend(pcfv_group* g, double* const* u, const double* dt
 }
 
 const char* pcfv_group_last_error(const pcfv_group* g) { return g ? g->err.c_str() : g_create_err.c_str(); }
+
+size_t pcfv_learned_scratch_bytes(const pcfv_ctx* ctx, int window, int r) {
+    if (!ctx || window < 1 || r < 1) return 0;
+    return learned_scratch(ctx->kp, window, r).total;
+}
+
+pcfv_status pcfv_learned_propose(pcfv_ctx* ctx, const pcfv_learned_model* model, const double* snaps, double* u_out,
+                                 double* cost_host) {
+    if (!ctx || !model || !snaps || !u_out) return fail(ctx, PCFV_EINVAL, "NULL argument");
+    std::vector<double> cost;
+    pcfv_status s = learned_core(ctx, model, snaps, u_out, cost);
+    if (s != PCFV_OK) return s;
+    if (cost_host)
+        for (int b = 0; b < ctx->kp.B; ++b) cost_host[b] = cost[b];
+    return PCFV_OK;
+}
 
 int pcfv_host_dmd(const double* Ge_hi, const double* Ge_lo, int M, double dtau, double* coef,
                   size_t cap) {

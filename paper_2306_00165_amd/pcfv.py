@@ -31,7 +31,15 @@ EXPORTS = [
     "pcfv_time_kernels", "pcfv_last_error", "pcfv_host_table", "pcfv_dmd_extrapolate",
     "pcfv_host_dmd", "pcfv_set_precision", "pcfv_autotune", "pcfv_get_tuning", "pcfv_group_create",
     "pcfv_group_destroy", "pcfv_group_descend", "pcfv_group_last_error",
+    "pcfv_mlp_param_count", "pcfv_mlp_workspace_bytes", "pcfv_mlp_create", "pcfv_mlp_destroy",
+    "pcfv_mlp_last_error", "pcfv_mlp_set_params", "pcfv_mlp_get_params", "pcfv_mlp_forward", "pcfv_mlp_grad",
+    "pcfv_mlp_adam_step", "pcfv_mlp_read", "pcfv_mlp_fit", "pcfv_pod_scratch_bytes", "pcfv_pod_build",
+    "pcfv_pod_project_scratch_bytes", "pcfv_pod_project", "pcfv_pod_reconstruct", "pcfv_learned_scratch_bytes",
+    "pcfv_learned_propose", "pcfv_learned_prepare",
 ]
+
+MLP_MAX_LAYERS = 8
+MLP_ACT, MLP_OUT, MLP_DZ, MLP_GRAD = 0, 1, 2, 3
 
 FP64, MIXED = 0, 1
 
@@ -55,7 +63,20 @@ class DescentOpts(ctypes.Structure):
                 ("grow_tol", ctypes.c_double), ("max_halvings", ctypes.c_int),
                 ("dmd_window", ctypes.c_int), ("dmd_stride", ctypes.c_int), ("dmd_gap", ctypes.c_int),
                 ("dmd_start", ctypes.c_double), ("dmd_accept", ctypes.c_double),
-                ("dmd_buffer", ctypes.c_void_p), ("fp64_below", ctypes.c_double)]
+                ("dmd_buffer", ctypes.c_void_p), ("fp64_below", ctypes.c_double),
+                ("learned", ctypes.c_void_p)]
+
+
+class MlpConfig(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int), ("dims", ctypes.c_int * (MLP_MAX_LAYERS + 1)),
+                ("max_batch", ctypes.c_int)]
+
+
+class LearnedModel(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int), ("r", ctypes.c_int), ("pod_mean", ctypes.c_void_p),
+                ("pod_basis", ctypes.c_void_p), ("in_mu", ctypes.c_void_p), ("in_isd", ctypes.c_void_p),
+                ("out_mu", ctypes.c_void_p), ("out_isd", ctypes.c_void_p), ("mlp", ctypes.c_void_p),
+                ("scratch", ctypes.c_void_p)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -66,7 +87,7 @@ class DescentReport(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_longlong), ("tau", ctypes.c_double), ("cost", ctypes.c_double),
                 ("rel_res", ctypes.c_double), ("dtau_final", ctypes.c_double),
                 ("n_halvings", ctypes.c_int), ("n_dmd", ctypes.c_int), ("n_dmd_accepted", ctypes.c_int),
-                ("steps_fp32", ctypes.c_longlong)]
+                ("steps_fp32", ctypes.c_longlong), ("n_learned_accepted", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -127,6 +148,47 @@ def load_library(path=_LIB_PATH):
     lib.pcfv_group_descend.argtypes = [vp, ctypes.POINTER(vp), dp, ctypes.c_longlong, i]
     lib.pcfv_group_last_error.restype = ctypes.c_char_p
     lib.pcfv_group_last_error.argtypes = [vp]
+    mcp = ctypes.POINTER(MlpConfig)
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.pcfv_mlp_param_count.restype = ctypes.c_longlong
+    lib.pcfv_mlp_param_count.argtypes = [mcp]
+    lib.pcfv_mlp_workspace_bytes.restype = ctypes.c_size_t
+    lib.pcfv_mlp_workspace_bytes.argtypes = [mcp]
+    lib.pcfv_mlp_create.restype = i
+    lib.pcfv_mlp_create.argtypes = [mcp, vp, vp, ctypes.POINTER(vp)]
+    lib.pcfv_mlp_destroy.restype = None
+    lib.pcfv_mlp_destroy.argtypes = [vp]
+    lib.pcfv_mlp_last_error.restype = ctypes.c_char_p
+    lib.pcfv_mlp_last_error.argtypes = [vp]
+    for name in ("pcfv_mlp_set_params", "pcfv_mlp_get_params"):
+        getattr(lib, name).restype = i
+        getattr(lib, name).argtypes = [vp, fp]
+    lib.pcfv_mlp_forward.restype = i
+    lib.pcfv_mlp_forward.argtypes = [vp, vp, vp, i]
+    lib.pcfv_mlp_grad.restype = i
+    lib.pcfv_mlp_grad.argtypes = [vp, vp, vp, i, fp]
+    lib.pcfv_mlp_adam_step.restype = i
+    lib.pcfv_mlp_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+    lib.pcfv_mlp_read.restype = i
+    lib.pcfv_mlp_read.argtypes = [vp, i, i, vp, ctypes.c_size_t]
+    lib.pcfv_mlp_fit.restype = i
+    lib.pcfv_mlp_fit.argtypes = [vp, vp, vp, i, i, i, ctypes.c_float, ctypes.c_ulonglong, vp, vp, vp, fp]
+    lib.pcfv_pod_scratch_bytes.restype = ctypes.c_size_t
+    lib.pcfv_pod_scratch_bytes.argtypes = [i, ctypes.c_longlong, i]
+    lib.pcfv_pod_build.restype = i
+    lib.pcfv_pod_build.argtypes = [vp, vp, i, ctypes.c_longlong, i, vp, vp, dp, vp]
+    lib.pcfv_pod_project_scratch_bytes.restype = ctypes.c_size_t
+    lib.pcfv_pod_project_scratch_bytes.argtypes = [i, ctypes.c_longlong, i]
+    lib.pcfv_pod_project.restype = i
+    lib.pcfv_pod_project.argtypes = [vp, vp, i, ctypes.c_longlong, i, vp, vp, vp, vp]
+    lib.pcfv_pod_reconstruct.restype = i
+    lib.pcfv_pod_reconstruct.argtypes = [vp, vp, i, ctypes.c_longlong, i, vp, vp, vp]
+    lib.pcfv_learned_scratch_bytes.restype = ctypes.c_size_t
+    lib.pcfv_learned_scratch_bytes.argtypes = [vp, i, i]
+    lib.pcfv_learned_propose.restype = i
+    lib.pcfv_learned_propose.argtypes = [vp, ctypes.POINTER(LearnedModel), vp, vp, dp]
+    lib.pcfv_learned_prepare.restype = i
+    lib.pcfv_learned_prepare.argtypes = [vp, i, i, i, vp, vp, i, vp, vp, vp, vp, vp, vp]
     return lib
 
 
@@ -286,7 +348,7 @@ class Context:
 
     def descend(self, u, max_steps, dtau, rel_tol=0.0, check_every=None, grow_tol=0.0,
                 max_halvings=0, dmd_window=0, dmd_stride=1, dmd_gap=0, dmd_start=0.0,
-                dmd_accept=10.0, fp64_below=0.0):
+                dmd_accept=10.0, fp64_below=0.0, learned=None):
         """Advance u (a contiguous complex128 device tensor) in place; returns
         (status, report dict).  dmd_window > 0 enables DMD extrapolation;
         fp64_below > 0 on a MIXED context switches to FP64 below that relative
@@ -300,7 +362,8 @@ class Context:
         o = DescentOpts(int(max_steps), float(dtau), float(rel_tol),
                         int(check_every or max(1, max_steps)), float(grow_tol), int(max_halvings),
                         int(dmd_window), int(dmd_stride), int(dmd_gap), float(dmd_start), float(dmd_accept),
-                        ctypes.c_void_p(buf.data_ptr()) if buf is not None else None, float(fp64_below))
+                        ctypes.c_void_p(buf.data_ptr()) if buf is not None else None, float(fp64_below),
+                        ctypes.cast(ctypes.pointer(learned.model), ctypes.c_void_p) if learned is not None else None)
         rep = DescentReport()
         st = _lib.pcfv_descend(self._h, _ptr(u), ctypes.byref(o), ctypes.byref(rep))
         if st not in (OK, ENOTCONV, ENAN, EDIVERGED):
@@ -408,3 +471,194 @@ class Group:
         st = _lib.pcfv_group_descend(self._h, ptrs, dt, int(steps), int(graph_steps))
         if st != OK:
             raise PcfvError(st, _lib.pcfv_group_last_error(self._h).decode())
+
+
+def _cuda_stream_ptr(torch_mod, device):
+    return ctypes.c_void_p(torch_mod.cuda.current_stream(device).cuda_stream)
+
+
+class MLP:
+    """The extrapolator's multilayer perceptron (BF16 matrix cores, FP32
+    master weights, Adam).  dims: layer widths, e.g. [2048, 512, 512, 512, 256]."""
+
+    def __init__(self, dims, max_batch, device="cuda:0"):
+        self.torch = torch
+        self.device = torch.device(device)
+        cfg = MlpConfig()
+        cfg.n_layers = len(dims) - 1
+        for k, d in enumerate(dims):
+            cfg.dims[k] = int(d)
+        cfg.max_batch = int(max_batch)
+        self.cfg, self.dims = cfg, list(dims)
+        self.n_params = _lib.pcfv_mlp_param_count(ctypes.byref(cfg))
+        nbytes = _lib.pcfv_mlp_workspace_bytes(ctypes.byref(cfg))
+        if nbytes == 0:
+            raise PcfvError(EINVAL, "invalid MLP configuration")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        h = ctypes.c_void_p()
+        st = _lib.pcfv_mlp_create(ctypes.byref(cfg), _cuda_stream_ptr(torch, self.device),
+                                  ctypes.c_void_p(self.workspace.data_ptr() + off), ctypes.byref(h))
+        if st != OK:
+            raise PcfvError(st, _lib.pcfv_mlp_last_error(None).decode())
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.pcfv_mlp_destroy(h)
+            self._h = None
+
+    def _check(self, st):
+        if st != OK:
+            raise PcfvError(st, _lib.pcfv_mlp_last_error(self._h).decode())
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.n_params:
+            raise ValueError("wrong parameter count")
+        self._check(_lib.pcfv_mlp_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def get_params(self):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        self._check(_lib.pcfv_mlp_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return p
+
+    def _rows(self, X, width):
+        X = self.torch.as_tensor(X).to(self.device, self.torch.float32).contiguous()
+        if X.dim() != 2 or X.shape[1] != width:
+            raise ValueError("bad matrix shape")
+        return X
+
+    def forward(self, X):
+        X = self._rows(X, self.dims[0])
+        Y = self.torch.empty((X.shape[0], self.dims[-1]), dtype=self.torch.float32, device=self.device)
+        self._check(_lib.pcfv_mlp_forward(self._h, _ptr(X), _ptr(Y), int(X.shape[0])))
+        return Y
+
+    def grad(self, X, T):
+        X, T = self._rows(X, self.dims[0]), self._rows(T, self.dims[-1])
+        loss = ctypes.c_float(0)
+        self._check(_lib.pcfv_mlp_grad(self._h, _ptr(X), _ptr(T), int(X.shape[0]), ctypes.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(_lib.pcfv_mlp_adam_step(self._h, lr, beta1, beta2, eps))
+
+    def read(self, what, layer, B):
+        if what == MLP_ACT:
+            out = np.zeros((B, self.dims[layer]), dtype=np.uint16)
+        elif what == MLP_DZ:
+            out = np.zeros((B, self.dims[layer + 1]), dtype=np.uint16)
+        elif what == MLP_OUT:
+            out = np.zeros((B, self.dims[-1]), dtype=np.float32)
+        else:
+            out = np.zeros(self.n_params, dtype=np.float32)
+        self._check(_lib.pcfv_mlp_read(self._h, int(what), int(layer), out.ctypes.data_as(ctypes.c_void_p),
+                                       out.nbytes))
+        return out
+
+    def fit(self, X, T, batch, epochs, lr=1e-3, seed=0):
+        X, T = self._rows(X, self.dims[0]), self._rows(T, self.dims[-1])
+        N = X.shape[0]
+        t = self.torch
+        idx = t.empty(N, dtype=t.int32, device=self.device)
+        Xb = t.empty((batch, self.dims[0]), dtype=t.float32, device=self.device)
+        Tb = t.empty((batch, self.dims[-1]), dtype=t.float32, device=self.device)
+        hist = np.zeros(max(1, epochs), dtype=np.float32)
+        self._check(_lib.pcfv_mlp_fit(self._h, _ptr(X), _ptr(T), int(N), int(batch), int(epochs), float(lr),
+                                      int(seed), _ptr(idx), _ptr(Xb), _ptr(Tb),
+                                      hist.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return hist[:epochs]
+
+
+def pod_build(X, r):
+    """POD of the rows of X (device float64 S x n): (mean, basis r x n, sigma)."""
+    X = torch.as_tensor(X).to("cuda:0" if not torch.is_tensor(X) else X.device, torch.float64).contiguous()
+    S, n = X.shape
+    mean = torch.empty(n, dtype=torch.float64, device=X.device)
+    basis = torch.empty((r, n), dtype=torch.float64, device=X.device)
+    nb = _lib.pcfv_pod_scratch_bytes(int(S), int(n), int(r))
+    if nb == 0:
+        raise ValueError("invalid POD sizes")
+    scratch = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    sigma = np.zeros(r)
+    st = _lib.pcfv_pod_build(_cuda_stream_ptr(torch, X.device), _ptr(X), int(S), int(n), int(r), _ptr(mean),
+                             _ptr(basis), sigma.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(scratch))
+    if st != OK:
+        raise PcfvError(st, "pcfv_pod_build failed")
+    return mean, basis, sigma
+
+
+def pod_project(X, mean, basis):
+    X = torch.as_tensor(X).to(basis.device, torch.float64).contiguous()
+    m, n = X.shape
+    r = basis.shape[0]
+    coef = torch.empty((m, r), dtype=torch.float64, device=basis.device)
+    nb = _lib.pcfv_pod_project_scratch_bytes(int(m), int(n), int(r))
+    scratch = torch.empty(max(nb, 8), dtype=torch.uint8, device=basis.device)
+    st = _lib.pcfv_pod_project(_cuda_stream_ptr(torch, basis.device), _ptr(X), int(m), int(n), int(r), _ptr(mean),
+                               _ptr(basis), _ptr(coef), _ptr(scratch))
+    if st != OK:
+        raise PcfvError(st, "pcfv_pod_project failed")
+    return coef
+
+
+def pod_reconstruct(coef, mean, basis):
+    coef = torch.as_tensor(coef).to(basis.device, torch.float64).contiguous()
+    m, r = coef.shape
+    n = basis.shape[1]
+    X = torch.empty((m, n), dtype=torch.float64, device=basis.device)
+    st = _lib.pcfv_pod_reconstruct(_cuda_stream_ptr(torch, basis.device), _ptr(coef), int(m), int(n), int(r),
+                                   _ptr(mean), _ptr(basis), _ptr(X))
+    if st != OK:
+        raise PcfvError(st, "pcfv_pod_reconstruct failed")
+    return X
+
+
+def learned_prepare(c, ct=None, stats=None):
+    """Features (and targets) of the extrapolator from POD coefficients c
+    (device [W][B][r]) and limit coefficients ct ([B][r]).  stats None: fit
+    the normalisation and return it as (in_mu, in_isd, out_mu, out_isd)."""
+    c = c.contiguous()
+    W, B, r = c.shape
+    dev = c.device
+    f32 = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
+    fit = stats is None
+    if fit:
+        stats = (f32(W * r), f32(W * r), f32(r), f32(r))
+    X = f32(B, W * r)
+    T = f32(B, r) if ct is not None else None
+    st = _lib.pcfv_learned_prepare(_cuda_stream_ptr(torch, dev), int(W), int(B), int(r), _ptr(c),
+                                   _ptr(ct.contiguous()) if ct is not None else None, int(fit),
+                                   *[_ptr(x) for x in stats], _ptr(X), _ptr(T) if T is not None else None)
+    if st != OK:
+        raise PcfvError(st, "pcfv_learned_prepare failed")
+    return X, T, stats
+
+
+class Learned:
+    """A trained extrapolator bound to one context (its batch and grid)."""
+
+    def __init__(self, ctx, window, mean, basis, stats, mlp):
+        self.ctx, self.mlp = ctx, mlp
+        self.mean, self.basis, self.stats = mean.contiguous(), basis.contiguous(), stats
+        r = basis.shape[0]
+        nb = _lib.pcfv_learned_scratch_bytes(ctx._h, int(window), int(r))
+        self.scratch = torch.empty(nb + 256, dtype=torch.uint8, device=ctx.device)
+        m = LearnedModel()
+        m.window, m.r = int(window), int(r)
+        m.pod_mean, m.pod_basis = self.mean.data_ptr(), self.basis.data_ptr()
+        m.in_mu, m.in_isd, m.out_mu, m.out_isd = [x.data_ptr() for x in stats]
+        m.mlp = mlp._h.value
+        m.scratch = self.scratch.data_ptr() + ((-self.scratch.data_ptr()) % 256)
+        self.model = m
+
+    def propose(self, snaps):
+        """snaps: device float64 [W][batch][n_state]; returns (u, cost(s))."""
+        c = self.ctx
+        snaps = torch.as_tensor(snaps).to(c.device, torch.float64).contiguous()
+        out = c.empty()
+        cost = c._scalars(1)
+        c._check(_lib.pcfv_learned_propose(c._h, ctypes.byref(self.model), _ptr(snaps), _ptr(out), cost))
+        return out, c._unbatch(cost, 1)
