@@ -170,6 +170,48 @@ def extra_legs(torch, inputs, steps):
     return out
 
 
+def time_to_tol_leg(torch, inputs, seconds=6.0, tol=1e-10):
+    """The second half of the metric: wall time to ||r||/||u_b+u|| < 1e-10,
+    plain FP64 descent against the chosen form (FP32 transforms and products
+    with FP64 refinement below 1e-5, DMD extrapolation of windows of 50
+    snapshots 40 steps apart, a candidate taken only if it lowers the cost).  From
+    the guess after 20000 FP64 steps (past the initial fast drop, so that the
+    rate measured is the slow late one), each form runs for `seconds` of wall time;
+    neither reaches 1e-10 in that time (the late decay toward the attracting
+    state is slow, one decade per ~1e8 steps at the laminar state), so the
+    time to 1e-10 is extrapolated from the measured rate in decades per
+    second and reported as such."""
+    import math
+    from paper_2306_00165_amd.pcfv import Context, MIXED
+    out = {"tol": tol, "seconds_measured": seconds, "extrapolated": True}
+    u0 = torch.as_tensor(inputs.metric_guess()).to("cuda:0").contiguous()
+    c0 = Context(*GRID, device="cuda:0")
+    c0.descend(u0, max_steps=20000, dtau=DTAU)
+    forms = {
+        "plain_f64": (Context(*GRID, device="cuda:0"), {}),
+        "chosen_mixed_dmd": (Context(*GRID, device="cuda:0", precision=MIXED),
+                             dict(dmd_window=50, dmd_stride=40, dmd_gap=0, dmd_accept=1.0, fp64_below=1e-5)),
+    }
+    for name, (c, kw) in forms.items():
+        u = u0.clone()
+        _, rep0 = c.descend(u, max_steps=0, dtau=DTAU)
+        r0 = rep0["rel_res"]
+        steps, t0 = 0, time.perf_counter()
+        rep = rep0
+        while time.perf_counter() - t0 < seconds:
+            st, rep = c.descend(u, max_steps=2000, dtau=DTAU, check_every=2000, **kw)
+            steps += rep["steps"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rate = math.log10(r0 / rep["rel_res"]) / dt if rep["rel_res"] < r0 else 0.0
+        est = math.log10(rep["rel_res"] / tol) / rate + dt if rate > 0 else None
+        out[name] = {"rel_res_start": r0, "rel_res_end": rep["rel_res"], "steps": steps, "wall_s": round(dt, 3),
+                     "decades_per_s": rate, "est_wall_s_to_tol": est}
+    a, b = out["plain_f64"]["est_wall_s_to_tol"], out["chosen_mixed_dmd"]["est_wall_s_to_tol"]
+    out["est_speedup"] = (a / b) if (a and b) else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,7 +254,9 @@ def main():
         raise RuntimeError(f"descent returned status {st}: {rep}")
     steps_per_s = args.steps / dt
 
-    ms = c.time_kernels(u, nrep=50)
+    # per-kernel device time inside consecutive descent steps (HIP events on
+    # the context stream), over steps that continue the timed trajectory
+    ms = [c.time_kernels(u, nrep=1)[0]] + c.time_descent_kernels(u, DTAU, nsteps=200)
     model = kernel_model(*GRID)
     step_kernels = KERNELS[1:]
     dom = max(step_kernels, key=lambda k: ms[KERNELS.index(k)])
@@ -226,6 +270,8 @@ def main():
                 "avg_launch_ms": round(ms[KERNELS.index(dom)], 5),
                 "hbm_GBps_algorithmic": round(nbytes / t_dom / 1e9, 2)}
     extra = {} if args.no_extra else extra_legs(torch, inputs, args.steps)
+    if not args.no_extra:
+        extra["time_to_tol"] = time_to_tol_leg(torch, inputs)
     out = {
         "metric": METRIC, "value": round(steps_per_s, 2), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 5),

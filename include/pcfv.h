@@ -236,6 +236,13 @@ pcfv_status pcfv_check_state(pcfv_ctx* ctx, const double* u, double* defects_hos
  * launches each (u is left unchanged).  ms_out[0..4] = synthesis, forward
  * products, residual/adjoint-solve per mode, adjoint products, gradient/
  * projection/update per mode.  Returns the number of entries via *n_out. */
+/* nsteps plain descent steps of u (in place, step dtau) with HIP events on the
+ * context stream around each kernel: ms_out[0..3] = average device time per
+ * launch, in milliseconds, of the forward products, the residual/adjoint-solve
+ * per mode, the adjoint products and the gradient/projection/update per mode,
+ * as they run inside consecutive steps.  1 <= nsteps <= 4096.  Synchronises. */
+pcfv_status pcfv_time_descent_kernels(pcfv_ctx* ctx, double* u, double dtau, int nsteps, double* ms_out);
+
 pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* ms_out,
                               int* n_out);
 
@@ -243,9 +250,11 @@ pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* 
  * failed pcfv_create on the calling thread.  Valid until the next call. */
 const char* pcfv_last_error(const pcfv_ctx* ctx);
 
-/* Autotuner over the launch shape of the physical-space kernels: for every
- * candidate x-slab width (divisors of Nx up to 8 that fit the LDS budget, at
- * least half the default) and work-group size (256, 512 threads) it times
+/* Autotuner over the launch shapes: for every candidate x-slab width of the
+ * physical-space kernels (divisors of Nx up to 8 that fit the LDS budget, at
+ * least half the default), their work-group size (256, 512 threads) and the
+ * per-mode kernels' work-group size (256 threads with 4 lanes per contraction
+ * row, 512 with 8) it times
  * `steps` descent steps (after one untimed step) on a scratch copy of u with
  * dtau = 0, keeps the fastest for every later call, and reports each
  * candidate in entries[0..cap) (n_entries gets the count).  u is not
@@ -253,12 +262,16 @@ const char* pcfv_last_error(const pcfv_ctx* ctx);
 typedef struct {
     int xs;               /* x-slab width */
     int plane_threads;    /* work-group size of the physical-space kernels */
+    int mode_threads;     /* work-group size of the per-mode kernels */
     double ms_per_step;   /* measured descent-step time */
 } pcfv_tune_entry;
 pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_entry* entries, int cap,
                           int* n_entries);
-/* The launch shape in use (x-slab width, physical-space work-group size). */
-pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads);
+/* The launch shape in use (x-slab width, physical-space and per-mode work-group
+ * sizes; any pointer may be NULL).  Without pcfv_autotune: the widest slab
+ * that fits, 512-thread physical-space groups, and 512-thread per-mode groups
+ * when the context holds at most 1024 modes over all guesses (256 above). */
+pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads, int* mode_threads);
 
 /* Groups (batching over uneven grids): n contexts, each with its own grid,
  * Re, batch and tables but one precision, are advanced together; every
@@ -267,7 +280,8 @@ pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads);
  * all members, so small members share the chip instead of running one after
  * another.  The group owns a stream and n + 1 small device records; the
  * members (and their workspaces) must outlive it.  The physical-space work
- * group size is members[0]'s. */
+ * group size is members[0]'s; the per-mode one follows the single-context
+ * default rule applied to the modes of all members together. */
 typedef struct pcfv_group pcfv_group;
 pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out);
 void pcfv_group_destroy(pcfv_group* group);

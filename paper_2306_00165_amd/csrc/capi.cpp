@@ -92,6 +92,8 @@ KP base_kp(const pcfv_config& c) {
     p.NS = c.Nx / p.XS;
     p.prec = c.precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
     p.pthreads = 512;
+    // few modes per launch: latency-bound, the wider per-mode work groups win
+    p.mthreads = (p.nmB <= 1024) ? 512 : 256;
     return p;
 }
 
@@ -820,6 +822,50 @@ pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* 
     return PCFV_OK;
 }
 
+pcfv_status pcfv_time_descent_kernels(pcfv_ctx* ctx, double* u, double dtau, int nsteps, double* ms_out) {
+    if (!ctx || !u || !ms_out || nsteps < 1 || nsteps > 4096) return fail(ctx, PCFV_EINVAL, "bad argument");
+    const KP& p = ctx->kp;
+    hipStream_t s = ctx->stream;
+    std::vector<hipEvent_t> ev((size_t)nsteps * 5, nullptr);
+    pcfv_status st = PCFV_OK;
+    auto cleanup = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (hipEvent_t& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            cleanup();
+            return fail(ctx, PCFV_EDEVICE, "event creation failed");
+        }
+    hipError_t he = launch_synth(p, s, cd(u), ctx->Y);
+    for (int i = 0; i < nsteps && he == hipSuccess; ++i) {   // the kernels of descent_step, bracketed
+        hipEvent_t* e = &ev[(size_t)i * 5];
+        he = hipEventRecord(e[0], s);
+        if (he == hipSuccess) he = launch_plane(p, s, PLANE_FWD, ctx->Y, nullptr, ctx->P3);
+        if (he == hipSuccess) he = hipEventRecord(e[1], s);
+        if (he == hipSuccess)
+            he = launch_mode_res(p, s, RES_COST | RES_ADJ, ctx->P3, cd(u), nullptr, ctx->part, ctx->a, ctx->Atil);
+        if (he == hipSuccess) he = hipEventRecord(e[2], s);
+        if (he == hipSuccess) he = launch_plane(p, s, PLANE_ADJ, ctx->Y, ctx->Atil, ctx->P6);
+        if (he == hipSuccess) he = hipEventRecord(e[3], s);
+        if (he == hipSuccess) he = launch_mode_grad(p, s, GRAD_PROJECT | GRAD_UPDATE, ctx->P6, ctx->a, dtau, dd(u), ctx->Y);
+        if (he == hipSuccess) he = hipEventRecord(e[4], s);
+    }
+    if (he == hipSuccess) he = hipEventSynchronize(ev.back());
+    double acc[4] = {0, 0, 0, 0};
+    for (int i = 0; i < nsteps && he == hipSuccess; ++i)
+        for (int k = 0; k < 4 && he == hipSuccess; ++k) {
+            float ms = 0;
+            he = hipEventElapsedTime(&ms, ev[(size_t)i * 5 + k], ev[(size_t)i * 5 + k + 1]);
+            acc[k] += ms;
+        }
+    cleanup();
+    if (he != hipSuccess) st = hip_check(ctx, he, "timed descent");
+    if (st != PCFV_OK) return st;
+    for (int k = 0; k < 4; ++k) ms_out[k] = acc[k] / nsteps;
+    return PCFV_OK;
+}
+
 const char* pcfv_last_error(const pcfv_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
 pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_entry* entries, int cap,
@@ -835,10 +881,12 @@ pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_e
     KP best_kp = saved;
     pcfv_status st = PCFV_OK;
     for (int xs : xs_candidates(ctx->cfg)) {
-        for (int nt : {256, 512}) {
+        for (int cand = 0; cand < 4; ++cand) {
+            const int nt = (cand & 1) ? 512 : 256, mt = (cand & 2) ? 512 : 256;
             ctx->kp.XS = xs;
             ctx->kp.NS = ctx->cfg.Nx / xs;
             ctx->kp.pthreads = nt;
+            ctx->kp.mthreads = mt;
             hipError_t he = hipMemcpyAsync(ctx->tmp, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream);
             if (he == hipSuccess) he = launch_synth(ctx->kp, ctx->stream, ctx->tmp, ctx->Y);
             // one untimed step, then `steps` timed ones (dtau = 0 leaves the copy unchanged)
@@ -852,7 +900,7 @@ pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_e
             if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
             if (he != hipSuccess) st = hip_check(ctx, he, "autotune");
             if (st != PCFV_OK) break;
-            pcfv_tune_entry t{xs, nt, ms / steps};
+            pcfv_tune_entry t{xs, nt, mt, ms / steps};
             res.push_back(t);
             if (t.ms_per_step < best) {
                 best = t.ms_per_step;
@@ -870,10 +918,11 @@ pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_e
     return PCFV_OK;
 }
 
-pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads) {
+pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads, int* mode_threads) {
     if (!ctx) return PCFV_EINVAL;
     if (xs) *xs = ctx->kp.XS;
     if (plane_threads) *plane_threads = ctx->kp.pthreads;
+    if (mode_threads) *mode_threads = ctx->kp.mthreads;
     return PCFV_OK;
 }
 
@@ -957,12 +1006,16 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out)
     gl.n = n;
     gl.prec = members[0]->kp.prec;
     gl.pthreads = members[0]->kp.pthreads;
+    long long group_modes = 0;
+    for (int k = 0; k < n; ++k) group_modes += members[k]->kp.nmB;
+    gl.mthreads = (group_modes <= 1024) ? 512 : 256;   // the single-context rule, over the whole group
     long long items[2] = {0, 0};
     for (int k = 0; k < n; ++k) {
         pcfv_ctx* c = members[k];
         GroupMember& m = g->host[k];
         m.kp = c->kp;
         m.kp.pthreads = gl.pthreads;
+        m.kp.mthreads = gl.mthreads;
         m.item0[GPH_PLANE] = (int)items[GPH_PLANE];
         m.item0[GPH_MODE] = (int)items[GPH_MODE];
         items[GPH_PLANE] += (long long)c->kp.B * c->kp.NS * c->kp.N;
@@ -978,7 +1031,7 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out)
         gl.np = std::max(gl.np, padded_ny(c->kp.N));
         for (int md : {PLANE_FWD, PLANE_JVP, PLANE_ADJ})
             gl.plane_lds[md] = std::max(gl.plane_lds[md], plane_lds_bytes(m.kp, md));
-        gl.mode_lds = std::max(gl.mode_lds, mode_lds_bytes(c->kp));
+        gl.mode_lds = std::max(gl.mode_lds, mode_lds_bytes(m.kp));
     }
     if (items[0] > INT_MAX / 2 || items[1] > INT_MAX / 2) {
         delete g;

@@ -25,12 +25,17 @@ namespace pcfv {
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int MODE_THREADS = 256;              // one Fourier mode per work group of 4 waves
-constexpr int MODE_WAVES = MODE_THREADS / WAVE;
-constexpr int KSPLIT = 4;                      // lanes sharing one output row of a contraction
-constexpr int ROWS_PER_WAVE = WAVE / KSPLIT;   // 16
 constexpr int MODE_VECS = 24;                  // LDS vectors (length N) used by the mode kernels
 constexpr int RED_SLOTS = 16;                  // doubles per wave for block reductions
+
+// Work-group shapes of the per-mode kernels (one Fourier mode per work group):
+// MT threads; every output row of a contraction is summed by KS lanes of a
+// wave, ROWS rows per wave.  256 threads with KS = 4 suit many modes per
+// launch (throughput); 512 threads with KS = 8 halve each lane's serial
+// chain for few modes per launch (latency).
+template <int MT> struct MC {
+    static constexpr int THREADS = MT, WAVES = MT / WAVE, KS = (MT >= 512) ? 8 : 4, ROWS = WAVE / KS;
+};
 
 __device__ __forceinline__ double2 c2(double x, double y) { return make_double2(x, y); }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return c2(a.x + b.x, a.y + b.y); }
@@ -102,8 +107,8 @@ __device__ __forceinline__ const double* mat(const KP& p, int id) {
 }
 
 // Block reduction of NV values per thread (deterministic order): every thread
-// receives the block totals.  red: LDS scratch of MODE_WAVES * RED_SLOTS doubles.
-template <int NV>
+// receives the block totals.  red: LDS scratch of MC<MT>::WAVES * RED_SLOTS doubles.
+template <int MT, int NV>
 __device__ void bsum(double (&v)[NV], double* red) {
     static_assert(NV <= RED_SLOTS, "too many values");
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
@@ -117,13 +122,13 @@ __device__ void bsum(double (&v)[NV], double* red) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         double t = 0;
-        for (int w = 0; w < MODE_WAVES; ++w) t += red[w * RED_SLOTS + i];
+        for (int w = 0; w < MC<MT>::WAVES; ++w) t += red[w * RED_SLOTS + i];
         v[i] = t;
     }
     __syncthreads();
 }
 
-template <int NV>
+template <int MT, int NV>
 __device__ void bmax(double (&v)[NV], double* red) {
     static_assert(NV <= RED_SLOTS, "too many values");
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
@@ -137,30 +142,30 @@ __device__ void bmax(double (&v)[NV], double* red) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         double t = 0;
-        for (int w = 0; w < MODE_WAVES; ++w) t = fmax(t, red[w * RED_SLOTS + i]);
+        for (int w = 0; w < MC<MT>::WAVES; ++w) t = fmax(t, red[w * RED_SLOTS + i]);
         v[i] = t;
     }
     __syncthreads();
 }
 
 // y = A x for one complex vector; A (nout x nin) stored transposed (slot[k*N+n]).
-// Each output row is computed by KSPLIT lanes of one wave, each summing every
-// KSPLIT-th term, then combined with cross-lane shuffles; rows are dealt out
+// Each output row is computed by MC<MT>::KS lanes of one wave, each summing every
+// MC<MT>::KS-th term, then combined with cross-lane shuffles; rows are dealt out
 // in groups of 16 per wave.  x and y live in LDS and must not alias.  Caller
 // synchronises afterwards.
-template <int NP>
+template <int NP, int MT>
 __device__ void mv(const KP& p, int id, int nin, int nout, const double2* x, double2* y) {
     const double* __restrict__ A = mat(p, id);
     const int N = p.N, lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    const int r = lane % ROWS_PER_WAVE, q = lane / ROWS_PER_WAVE;
+    const int r = lane % MC<MT>::ROWS, q = lane / MC<MT>::ROWS;
 #pragma unroll
-    for (int n0 = 0; n0 < NP; n0 += MODE_WAVES * ROWS_PER_WAVE) {
-        const int n = n0 + wave * ROWS_PER_WAVE + r;
+    for (int n0 = 0; n0 < NP; n0 += MC<MT>::WAVES * MC<MT>::ROWS) {
+        const int n = n0 + wave * MC<MT>::ROWS + r;
         double re = 0.0, im = 0.0;
         if (n < nout) {
 #pragma unroll
-            for (int i = 0; i < NP / KSPLIT; ++i) {   // fully unrolled: all loads in flight
-                const int k = q + KSPLIT * i;
+            for (int i = 0; i < NP / MC<MT>::KS; ++i) {   // fully unrolled: all loads in flight
+                const int k = q + MC<MT>::KS * i;
                 if (k < nin) {
                     const double a = A[k * N + n];
                     const double2 v = x[k];
@@ -169,30 +174,31 @@ __device__ void mv(const KP& p, int id, int nin, int nout, const double2* x, dou
                 }
             }
         }
-        re += __shfl_xor(re, 16, WAVE);
-        im += __shfl_xor(im, 16, WAVE);
-        re += __shfl_xor(re, 32, WAVE);
-        im += __shfl_xor(im, 32, WAVE);
+#pragma unroll
+        for (int o = MC<MT>::ROWS; o < WAVE; o <<= 1) {   // lanes of one row are MC<MT>::ROWS apart
+            re += __shfl_xor(re, o, WAVE);
+            im += __shfl_xor(im, o, WAVE);
+        }
         if (q == 0 && n < nout) y[n] = c2(re, im);
     }
 }
 
 // The same matrix applied to three vectors.
-template <int NP>
+template <int NP, int MT>
 __device__ void mv3(const KP& p, int id, int nin, int nout, const double2* x0,
                     const double2* x1, const double2* x2, double2* y0, double2* y1,
                     double2* y2) {
     const double* __restrict__ A = mat(p, id);
     const int N = p.N, lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    const int r = lane % ROWS_PER_WAVE, q = lane / ROWS_PER_WAVE;
+    const int r = lane % MC<MT>::ROWS, q = lane / MC<MT>::ROWS;
 #pragma unroll
-    for (int n0 = 0; n0 < NP; n0 += MODE_WAVES * ROWS_PER_WAVE) {
-        const int n = n0 + wave * ROWS_PER_WAVE + r;
+    for (int n0 = 0; n0 < NP; n0 += MC<MT>::WAVES * MC<MT>::ROWS) {
+        const int n = n0 + wave * MC<MT>::ROWS + r;
         double acc[6] = {0, 0, 0, 0, 0, 0};
         if (n < nout) {
 #pragma unroll
-            for (int i = 0; i < NP / KSPLIT; ++i) {
-                const int k = q + KSPLIT * i;
+            for (int i = 0; i < NP / MC<MT>::KS; ++i) {
+                const int k = q + MC<MT>::KS * i;
                 if (k < nin) {
                     const double a = A[k * N + n];
                     const double2 v0 = x0[k], v1 = x1[k], v2 = x2[k];
@@ -207,8 +213,8 @@ __device__ void mv3(const KP& p, int id, int nin, int nout, const double2* x0,
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
-            acc[i] += __shfl_xor(acc[i], 16, WAVE);
-            acc[i] += __shfl_xor(acc[i], 32, WAVE);
+#pragma unroll
+            for (int o = MC<MT>::ROWS; o < WAVE; o <<= 1) acc[i] += __shfl_xor(acc[i], o, WAVE);
         }
         if (q == 0 && n < nout) {
             y0[n] = c2(acc[0], acc[1]);
@@ -239,7 +245,7 @@ __device__ void mv3(const KP& p, int id, int nin, int nout, const double2* x0,
 //   C: v0 = Pl t2, Dv0 = DPL t2, eta = Pl te, and p0(N-1) = Pl[N-1,:] t1
 // w: 10 scratch vectors.
 // ---------------------------------------------------------------------------
-template <int NP>
+template <int NP, int MT>
 __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const double2* Fy,
                        const double2* Fz, double2* ox, double2* oy, double2* oz, double2* w,
                        double* red) {
@@ -248,31 +254,31 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
             *s4 = w + 5 * N, *t2 = w + 6 * N, *v0 = w + 7 * N, *Dv0 = w + 8 * N, *eta = w + 9 * N;
     const double* dH = p.dH + (size_t)m * N;
     const double* dP = p.dP + (size_t)m * N;
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         const double2 fx = Fx[n], fz = Fz[n];
         Fh[n] = cadd(imul(c.a, fx), imul(c.b, fz));
         Fe[n] = csub(imul(c.b, fx), imul(c.a, fz));
     }
     __syncthreads();
-    mv3<NP>(p, M_PR, M, M, Fh, Fe, Fy, s1, s2, s3);
-    mv<NP>(p, M_PRD, N, M, Fy, s4);
+    mv3<NP, MT>(p, M_PR, M, M, Fh, Fe, Fy, s1, s2, s3);
+    mv<NP, MT>(p, M_PRD, N, M, Fy, s4);
     __syncthreads();
-    for (int n = t; n < M; n += MODE_THREADS) {
+    for (int n = t; n < M; n += MT) {
         s1[n] = cscl(-dP[n], cadd(s4[n], s1[n]));   // t1
         s2[n] = cscl(dH[n], s2[n]);                 // te
     }
     __syncthreads();
-    mv<NP>(p, M_PRDPL, M, M, s1, t2);
+    mv<NP, MT>(p, M_PRDPL, M, M, s1, t2);
     __syncthreads();
-    for (int n = t; n < M; n += MODE_THREADS) t2[n] = cscl(dH[n], csub(s3[n], t2[n]));
+    for (int n = t; n < M; n += MT) t2[n] = cscl(dH[n], csub(s3[n], t2[n]));
     __syncthreads();
-    mv<NP>(p, M_PL, M, N, t2, v0);
-    mv<NP>(p, M_DPL, M, N, t2, Dv0);
-    mv<NP>(p, M_PL, M, N, s2, eta);
+    mv<NP, MT>(p, M_PL, M, N, t2, v0);
+    mv<NP, MT>(p, M_DPL, M, N, t2, Dv0);
+    mv<NP, MT>(p, M_PL, M, N, s2, eta);
     __syncthreads();
     const double* PLlast = mat(p, M_PL) + (N - 1);      // row N-1 of Pl: PLlast[k * N]
     double sums[6] = {0, 0, 0, 0, 0, 0};
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         const double2 d = Dv0[n];
         sums[0] += d.x;
         sums[1] += d.y;
@@ -283,7 +289,7 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
             sums[5] += PLlast[(size_t)n * N] * s1[n].y;
         }
     }
-    bsum(sums, red);
+    bsum<MT>(sums, red);
     const double2 e0 = c2(sums[0], sums[1]), e1 = c2(sums[2], sums[3]), p0last = c2(sums[4], sums[5]);
     const double tn = 2.0 * (N - 1);
     const double2 e2 = csub(cadd(cscl(c.sig, v0[N - 2]), cscl(tn, p0last)), Fy[N - 2]);
@@ -298,7 +304,7 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
     }
     const double* Vk = p.Vk + (size_t)m * 4 * N;
     const double* DVk = p.DVk + (size_t)m * 4 * N;
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         double2 v = v0[n], Dv = Dv0[n];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -316,7 +322,7 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
 // Conjugate transpose of stokes(): (yx, yy, yz) = S^H (xu, xv, xw), the steps
 // above run backwards with every matrix transposed (three contraction phases).
 // w: 11 scratch vectors.
-template <int NP>
+template <int NP, int MT>
 __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, const double2* xv,
                          const double2* xw, double2* yx, double2* yy, double2* yz,
                          double2* w, double* red) {
@@ -329,7 +335,7 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
     const double* Vk = p.Vk + (size_t)m * 4 * N;
     const double* DVk = p.DVk + (size_t)m * 4 * N;
     double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         const double2 a0 = xu[n], a2 = xw[n], bv = xv[n];
         const double2 bd = cscl(c.ik2, cadd(imul(-c.a, a0), imul(-c.b, a2)));
         bDv[n] = bd;
@@ -340,7 +346,7 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
             dots[2 * k + 1] += Vk[k * N + n] * bv.y + DVk[k * N + n] * bd.y;
         }
     }
-    bsum(dots, red);
+    bsum<MT>(dots, red);
     const double* Ai = p.Ainv + (size_t)m * 16;
     double2 be[4];
 #pragma unroll
@@ -350,7 +356,7 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
         for (int k = 0; k < 4; ++k) sj = cadd(sj, cscl(Ai[4 * k + j], c2(dots[2 * k], dots[2 * k + 1])));
         be[j] = cscl(-1.0, sj);
     }
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         double2 x = xv[n];
         if (n == N - 2) x = cadd(x, cscl(c.sig, be[2]));
         if (n == N - 1) x = cadd(x, cscl(c.sig, be[3]));
@@ -358,28 +364,28 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
         bDv0[n] = cadd(bDv[n], (n & 1) ? csub(be[0], be[1]) : cadd(be[0], be[1]));
     }
     __syncthreads();
-    mv<NP>(p, M_PLT, N, M, bv0, bt2);
-    mv<NP>(p, M_DPLT, N, M, bDv0, tmp);
-    mv<NP>(p, M_PLT, N, M, beta, bte);
+    mv<NP, MT>(p, M_PLT, N, M, bv0, bt2);
+    mv<NP, MT>(p, M_DPLT, N, M, bDv0, tmp);
+    mv<NP, MT>(p, M_PLT, N, M, beta, bte);
     __syncthreads();
-    for (int n = t; n < M; n += MODE_THREADS) {
+    for (int n = t; n < M; n += MT) {
         bt2[n] = cscl(dH[n], cadd(bt2[n], tmp[n]));   // u2 = dH (PL^T bv0 + DPL^T bDv0)
         bte[n] = cscl(dH[n], bte[n]);                 // bs2
     }
     __syncthreads();
-    mv<NP>(p, M_PRDPLT, M, M, bt2, tmp);
+    mv<NP, MT>(p, M_PRDPLT, M, M, bt2, tmp);
     __syncthreads();
     const double2 bp0last = cscl(2.0 * (N - 1), be[2]);
     const double* PLlast = mat(p, M_PL) + (N - 1);
-    for (int n = t; n < M; n += MODE_THREADS)   // bs1 = -dP (Pl[N-1,:] bp0last - PRDPL^T u2)
+    for (int n = t; n < M; n += MT)   // bs1 = -dP (Pl[N-1,:] bp0last - PRDPL^T u2)
         tmp[n] = cscl(-dP[n], csub(cscl(PLlast[(size_t)n * N], bp0last), tmp[n]));
     __syncthreads();
-    mv<NP>(p, M_PRT, M, M, tmp, bFh);
-    mv<NP>(p, M_PRT, M, M, bte, bFe);
-    mv<NP>(p, M_PRT, M, M, bt2, bFy);
-    mv<NP>(p, M_PRDT, M, N, tmp, bFy2);
+    mv<NP, MT>(p, M_PRT, M, M, tmp, bFh);
+    mv<NP, MT>(p, M_PRT, M, M, bte, bFe);
+    mv<NP, MT>(p, M_PRT, M, M, bt2, bFy);
+    mv<NP, MT>(p, M_PRDT, M, N, tmp, bFy2);
     __syncthreads();
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         const double2 h = (n < M) ? bFh[n] : c2(0, 0), e = (n < M) ? bFe[n] : c2(0, 0);
         double2 y = cadd((n < M) ? bFy[n] : c2(0, 0), bFy2[n]);
         if (n == N - 2) y = csub(y, be[2]);
@@ -391,43 +397,43 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
     __syncthreads();
 }
 
-template <int NP>
+template <int NP, int MT>
 __device__ void stokes0(const KP& p, const double2* Fx, const double2* Fz, double2* ox,
                         double2* oy, double2* oz, double2* w) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
     double2 *t1 = w, *t2 = w + N;
     const double* dH = p.dH;
-    mv<NP>(p, M_PR, M, M, Fx, t1);
-    mv<NP>(p, M_PR, M, M, Fz, t2);
+    mv<NP, MT>(p, M_PR, M, M, Fx, t1);
+    mv<NP, MT>(p, M_PR, M, M, Fz, t2);
     __syncthreads();
-    for (int n = t; n < M; n += MODE_THREADS) {
+    for (int n = t; n < M; n += MT) {
         t1[n] = cscl(dH[n], t1[n]);
         t2[n] = cscl(dH[n], t2[n]);
     }
     __syncthreads();
-    mv<NP>(p, M_PL, M, N, t1, ox);
-    mv<NP>(p, M_PL, M, N, t2, oz);
-    for (int n = t; n < N; n += MODE_THREADS) oy[n] = c2(0, 0);
+    mv<NP, MT>(p, M_PL, M, N, t1, ox);
+    mv<NP, MT>(p, M_PL, M, N, t2, oz);
+    for (int n = t; n < N; n += MT) oy[n] = c2(0, 0);
     __syncthreads();
 }
 
-template <int NP>
+template <int NP, int MT>
 __device__ void stokes0_h(const KP& p, const double2* xu, const double2* xw, double2* yx,
                           double2* yy, double2* yz, double2* w) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
     double2 *t1 = w, *t2 = w + N;
     const double* dH = p.dH;
-    mv<NP>(p, M_PLT, N, M, xu, t1);
-    mv<NP>(p, M_PLT, N, M, xw, t2);
+    mv<NP, MT>(p, M_PLT, N, M, xu, t1);
+    mv<NP, MT>(p, M_PLT, N, M, xw, t2);
     __syncthreads();
-    for (int n = t; n < M; n += MODE_THREADS) {
+    for (int n = t; n < M; n += MT) {
         t1[n] = cscl(dH[n], t1[n]);
         t2[n] = cscl(dH[n], t2[n]);
     }
     __syncthreads();
-    mv<NP>(p, M_PRT, M, M, t1, yx);
-    mv<NP>(p, M_PRT, M, M, t2, yz);
-    for (int n = t; n < N; n += MODE_THREADS) {
+    mv<NP, MT>(p, M_PRT, M, M, t1, yx);
+    mv<NP, MT>(p, M_PRT, M, M, t2, yz);
+    for (int n = t; n < N; n += MT) {
         yy[n] = c2(0, 0);
         if (n >= M) {
             yx[n] = c2(0, 0);
@@ -442,33 +448,33 @@ __device__ void stokes0_h(const KP& p, const double2* xu, const double2* xw, dou
 // the eta block is the fixed G-orthogonal Dirichlet projector and the v block
 // is diagonalised by fixed vectors X with diagonal 1/(1 + Lambda/kappa^2).
 // Three contraction phases.  w: 8 scratch vectors.
-template <int NP>
+template <int NP, int MT>
 __device__ void project(const KP& p, int m, const MS& c, const double2* gx, const double2* gy,
                         const double2* gz, double2* ox, double2* oy, double2* oz, double2* w) {
     const int N = p.N, t = threadIdx.x;
     double2 *gh = w, *ge = w + N, *t1 = w + 2 * N, *t2 = w + 3 * N, *t4 = w + 4 * N,
             *v = w + 5 * N, *eta = w + 6 * N, *Dv = w + 7 * N;
     const double* dq = p.dproj + (size_t)m * N;
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         const double2 x = gx[n], z = gz[n];
         gh[n] = cadd(imul(c.a, x), imul(c.b, z));
         ge[n] = csub(imul(c.b, x), imul(c.a, z));
     }
     __syncthreads();
-    mv<NP>(p, M_DTG, N, N, gh, t1);
-    mv<NP>(p, M_G, N, N, gy, t2);
-    mv<NP>(p, M_PID, N, N, ge, eta);
+    mv<NP, MT>(p, M_DTG, N, N, gh, t1);
+    mv<NP, MT>(p, M_G, N, N, gy, t2);
+    mv<NP, MT>(p, M_PID, N, N, ge, eta);
     __syncthreads();
-    for (int n = t; n < N; n += MODE_THREADS) t2[n] = csub(t2[n], cscl(c.ik2, t1[n]));
+    for (int n = t; n < N; n += MT) t2[n] = csub(t2[n], cscl(c.ik2, t1[n]));
     __syncthreads();
-    mv<NP>(p, M_PVLT, N, N - 4, t2, t4);
+    mv<NP, MT>(p, M_PVLT, N, N - 4, t2, t4);
     __syncthreads();
-    for (int n = t; n < N - 4; n += MODE_THREADS) t4[n] = cscl(dq[n], t4[n]);
+    for (int n = t; n < N - 4; n += MT) t4[n] = cscl(dq[n], t4[n]);
     __syncthreads();
-    mv<NP>(p, M_PVL, N - 4, N, t4, v);
-    mv<NP>(p, M_DPVL, N - 4, N, t4, Dv);
+    mv<NP, MT>(p, M_PVL, N - 4, N, t4, v);
+    mv<NP, MT>(p, M_DPVL, N - 4, N, t4, Dv);
     __syncthreads();
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         const double2 d = Dv[n], e = eta[n];
         ox[n] = cscl(c.ik2, csub(imul(c.a, d), imul(c.b, e)));
         oy[n] = v[n];
@@ -477,13 +483,13 @@ __device__ void project(const KP& p, int m, const MS& c, const double2* gx, cons
     __syncthreads();
 }
 
-template <int NP>
+template <int NP, int MT>
 __device__ void project0(const KP& p, const double2* gx, const double2* gz, double2* ox,
                          double2* oy, double2* oz) {
     const int N = p.N;
-    mv<NP>(p, M_PID, N, N, gx, ox);
-    mv<NP>(p, M_PID, N, N, gz, oz);
-    for (int n = threadIdx.x; n < N; n += MODE_THREADS) oy[n] = c2(0, 0);
+    mv<NP, MT>(p, M_PID, N, N, gx, ox);
+    mv<NP, MT>(p, M_PID, N, N, gz, oz);
+    for (int n = threadIdx.x; n < N; n += MT) oy[n] = c2(0, 0);
     __syncthreads();
 }
 
@@ -493,7 +499,7 @@ __device__ void project0(const KP& p, const double2* gx, const double2* gz, doub
 
 // y-values of u and of du/dy for the three components: Y[c] = C u_c,
 // Y[3+c] = C D u_c (Gauss-Lobatto synthesis).
-template <int NP, class YT>
+template <int NP, int MT, class YT>
 __device__ __forceinline__ void synth_body(const KP& p, int mB, const double2* __restrict__ u,
                                            YT* __restrict__ Y) {
     extern __shared__ double2 sm[];
@@ -503,13 +509,13 @@ __device__ __forceinline__ void synth_body(const KP& p, int mB, const double2* _
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     double2* V = sm;
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) V[i * N + n] = u[so + ((size_t)i * nm + m) * N + n];
+        for (int n = t; n < N; n += MT) V[i * N + n] = u[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
-    mv3<NP>(p, M_C, N, N, V, V + N, V + 2 * N, V + 3 * N, V + 4 * N, V + 5 * N);
-    mv3<NP>(p, M_CD, N, N, V, V + N, V + 2 * N, V + 6 * N, V + 7 * N, V + 8 * N);
+    mv3<NP, MT>(p, M_C, N, N, V, V + N, V + 2 * N, V + 3 * N, V + 4 * N, V + 5 * N);
+    mv3<NP, MT>(p, M_CD, N, N, V, V + N, V + 2 * N, V + 6 * N, V + 7 * N, V + 8 * N);
     __syncthreads();
     for (int f = 0; f < 6; ++f)
-        for (int j = t; j < N; j += MODE_THREADS)
+        for (int j = t; j < N; j += MT)
             Y[((size_t)f * N + j) * nmB + mB] = narrow<YT>(V[(3 + f) * N + j]);
 }
 
@@ -735,7 +741,7 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     }
 }
 
-template <int NP, class YT>
+template <int NP, int MT, class YT>
 __device__ __forceinline__ void mode_res_body(
     const KP& p, int mB, int flags, const YT* __restrict__ P3, const double2* __restrict__ u,
     double2* __restrict__ r, double* __restrict__ cost_part, double2* __restrict__ a,
@@ -752,32 +758,32 @@ __device__ __forceinline__ void mode_res_body(
     double2 *R0 = vec(9), *R1 = vec(10), *R2 = vec(11);
     if (flags & RES_INPUT_W) {
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) vec(9 + i)[n] = u[so + ((size_t)i * nm + m) * N + n];
+            for (int n = t; n < N; n += MT) vec(9 + i)[n] = u[so + ((size_t)i * nm + m) * N + n];
         __syncthreads();
     } else {
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) {
+            for (int n = t; n < N; n += MT) {
                 double2 acc = c2(0, 0);
                 for (int s = 0; s < p.NS; ++s) acc = cadd(acc, widen(P3[(((size_t)s * 3 + i) * N + n) * nmB + mB]));
                 vec(i)[n] = acc;
                 vec(3 + i)[n] = u[so + ((size_t)i * nm + m) * N + n];
             }
         __syncthreads();
-        mv3<NP>(p, M_CINV, N, N, vec(0), vec(1), vec(2), vec(6), vec(7), vec(8));
-        mv3<NP>(p, M_D2, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
+        mv3<NP, MT>(p, M_CINV, N, N, vec(0), vec(1), vec(2), vec(6), vec(7), vec(8));
+        mv3<NP, MT>(p, M_D2, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
         __syncthreads();
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) {
+            for (int n = t; n < N; n += MT) {
                 const double2 L = csub(vec(12 + i)[n], cscl(c.k2, vec(3 + i)[n]));
                 vec(6 + i)[n] = cadd(cscl(-1.0, vec(6 + i)[n]), cscl(p.nu, L));
             }
         __syncthreads();
         if (zero)
-            stokes0<NP>(p, vec(6), vec(8), R0, R1, R2, vec(12));
+            stokes0<NP, MT>(p, vec(6), vec(8), R0, R1, R2, vec(12));
         else
-            stokes<NP>(p, m, c, vec(6), vec(7), vec(8), R0, R1, R2, vec(12), red);
+            stokes<NP, MT>(p, m, c, vec(6), vec(7), vec(8), R0, R1, R2, vec(12), red);
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) {
+            for (int n = t; n < N; n += MT) {
                 const double2 v = cscl(p.lam, vec(9 + i)[n]);
                 vec(9 + i)[n] = v;
                 if (flags & RES_WRITE_R) r[so + ((size_t)i * nm + m) * N + n] = v;
@@ -785,35 +791,35 @@ __device__ __forceinline__ void mode_res_body(
         __syncthreads();
     }
     if (!(flags & (RES_COST | RES_ADJ))) return;
-    mv3<NP>(p, M_G, N, N, R0, R1, R2, vec(3), vec(4), vec(5));
+    mv3<NP, MT>(p, M_G, N, N, R0, R1, R2, vec(3), vec(4), vec(5));
     __syncthreads();
     if (flags & RES_COST) {
         double s = 0;
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) {
+            for (int n = t; n < N; n += MT) {
                 const double2 x = vec(9 + i)[n], y = vec(3 + i)[n];
                 s += x.x * y.x + x.y * y.y;
             }
         double tot[1] = {s};
-        bsum(tot, red);
+        bsum<MT>(tot, red);
         if (t == 0) cost_part[mB] = c.wgt * tot[0];
     }
     if (!(flags & RES_ADJ)) return;
     if (zero)
-        stokes0_h<NP>(p, vec(3), vec(5), vec(6), vec(7), vec(8), vec(12));
+        stokes0_h<NP, MT>(p, vec(3), vec(5), vec(6), vec(7), vec(8), vec(12));
     else
-        stokes_h<NP>(p, m, c, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8), vec(12), red);
-    mv3<NP>(p, M_GINV, N, N, vec(6), vec(7), vec(8), vec(0), vec(1), vec(2));
-    mv3<NP>(p, M_CINVT, N, N, vec(6), vec(7), vec(8), vec(12), vec(13), vec(14));
+        stokes_h<NP, MT>(p, m, c, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8), vec(12), red);
+    mv3<NP, MT>(p, M_GINV, N, N, vec(6), vec(7), vec(8), vec(0), vec(1), vec(2));
+    mv3<NP, MT>(p, M_CINVT, N, N, vec(6), vec(7), vec(8), vec(12), vec(13), vec(14));
     __syncthreads();
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) {
+        for (int n = t; n < N; n += MT) {
             a[so + ((size_t)i * nm + m) * N + n] = vec(i)[n];
             Atil[((size_t)i * N + n) * nmB + mB] = narrow<YT>(vec(12 + i)[n]);
         }
 }
 
-template <int NP, class YT>
+template <int NP, int MT, class YT>
 __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, const YT* __restrict__ P6,
                                                const double2* __restrict__ a, double dtau,
                                                double2* __restrict__ uo, YT* __restrict__ Y) {
@@ -827,7 +833,7 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) {
+        for (int n = t; n < N; n += MT) {
             double2 sx = c2(0, 0), sy = c2(0, 0);
             for (int s = 0; s < p.NS; ++s) {
                 sx = cadd(sx, widen(P6[(((size_t)s * 6 + i) * N + n) * nmB + mB]));
@@ -838,12 +844,12 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
             vec(6 + i)[n] = a[so + ((size_t)i * nm + m) * N + n];
         }
     __syncthreads();
-    mv3<NP>(p, M_MA, N, N, vec(0), vec(1), vec(2), vec(9), vec(10), vec(11));
-    mv3<NP>(p, M_MB, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
-    mv3<NP>(p, M_ML, N, N, vec(6), vec(7), vec(8), vec(15), vec(16), vec(17));
+    mv3<NP, MT>(p, M_MA, N, N, vec(0), vec(1), vec(2), vec(9), vec(10), vec(11));
+    mv3<NP, MT>(p, M_MB, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
+    mv3<NP, MT>(p, M_ML, N, N, vec(6), vec(7), vec(8), vec(15), vec(16), vec(17));
     __syncthreads();
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) {
+        for (int n = t; n < N; n += MT) {
             const double2 adv = cadd(vec(9 + i)[n], vec(12 + i)[n]);
             const double2 lap = csub(vec(15 + i)[n], cscl(c.k2, vec(6 + i)[n]));
             vec(9 + i)[n] = cscl(p.lam, csub(cscl(p.nu, lap), adv));
@@ -852,11 +858,11 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
     double2 *F0 = vec(9), *F1 = vec(10), *F2 = vec(11);
     if (flags & GRAD_PROJECT) {
         if (zero)
-            project0<NP>(p, vec(9), vec(11), vec(0), vec(1), vec(2));
+            project0<NP, MT>(p, vec(9), vec(11), vec(0), vec(1), vec(2));
         else
-            project<NP>(p, m, c, vec(9), vec(10), vec(11), vec(0), vec(1), vec(2), vec(12));
+            project<NP, MT>(p, m, c, vec(9), vec(10), vec(11), vec(0), vec(1), vec(2), vec(12));
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = cscl(-1.0, vec(i)[n]);
+            for (int n = t; n < N; n += MT) vec(i)[n] = cscl(-1.0, vec(i)[n]);
         __syncthreads();
         F0 = vec(0);
         F1 = vec(1);
@@ -865,32 +871,32 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
     double2* Fs[3] = {F0, F1, F2};
     if (flags & GRAD_UPDATE) {
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) {
+            for (int n = t; n < N; n += MT) {
                 const size_t gi = so + ((size_t)i * nm + m) * N + n;
                 const double2 un = cadd(uo[gi], cscl(dtau, Fs[i][n]));
                 uo[gi] = un;
                 vec(3 + i)[n] = un;
             }
         __syncthreads();
-        mv3<NP>(p, M_C, N, N, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8));
-        mv3<NP>(p, M_CD, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
+        mv3<NP, MT>(p, M_C, N, N, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8));
+        mv3<NP, MT>(p, M_CD, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
         __syncthreads();
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) {
+            for (int n = t; n < N; n += MT) {
                 Y[((size_t)i * N + n) * nmB + mB] = narrow<YT>(vec(6 + i)[n]);
                 Y[((size_t)(3 + i) * N + n) * nmB + mB] = narrow<YT>(vec(12 + i)[n]);
             }
     } else {
         for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MODE_THREADS) uo[so + ((size_t)i * nm + m) * N + n] = Fs[i][n];
+            for (int n = t; n < N; n += MT) uo[so + ((size_t)i * nm + m) * N + n] = Fs[i][n];
     }
 }
 
 // Single-context kernels: one logical work item per work group.
-template <int NP, class YT>
-__global__ __launch_bounds__(MODE_THREADS) void k_synth(KP p, const double2* __restrict__ u,
+template <int NP, int MT, class YT>
+__global__ __launch_bounds__(MT) void k_synth(KP p, const double2* __restrict__ u,
                                                         YT* __restrict__ Y) {
-    synth_body<NP, YT>(p, xcd_item(blockIdx.x, gridDim.x), u, Y);
+    synth_body<NP, MT, YT>(p, xcd_item(blockIdx.x, gridDim.x), u, Y);
 }
 
 template <int MODE, class R, int NT>
@@ -899,19 +905,19 @@ __global__ __launch_bounds__(NT) void k_plane(KP p, const C<R>* __restrict__ Y1,
     plane_body<MODE, R, NT>(p, xcd_item(blockIdx.x, gridDim.x), Y1, Y2, out);
 }
 
-template <int NP, class YT>
-__global__ __launch_bounds__(MODE_THREADS) void k_mode_res(KP p, int flags, const YT* __restrict__ P3,
+template <int NP, int MT, class YT>
+__global__ __launch_bounds__(MT) void k_mode_res(KP p, int flags, const YT* __restrict__ P3,
                                                            const double2* __restrict__ u,
                                                            double2* __restrict__ r, double* __restrict__ cost_part,
                                                            double2* __restrict__ a, YT* __restrict__ Atil) {
-    mode_res_body<NP, YT>(p, xcd_item(blockIdx.x, gridDim.x), flags, P3, u, r, cost_part, a, Atil);
+    mode_res_body<NP, MT, YT>(p, xcd_item(blockIdx.x, gridDim.x), flags, P3, u, r, cost_part, a, Atil);
 }
 
-template <int NP, class YT>
-__global__ __launch_bounds__(MODE_THREADS) void k_mode_grad(KP p, int flags, const YT* __restrict__ P6,
+template <int NP, int MT, class YT>
+__global__ __launch_bounds__(MT) void k_mode_grad(KP p, int flags, const YT* __restrict__ P6,
                                                             const double2* __restrict__ a, double dtau,
                                                             double2* __restrict__ uo, YT* __restrict__ Y) {
-    mode_grad_body<NP, YT>(p, xcd_item(blockIdx.x, gridDim.x), flags, P6, a, dtau, uo, Y);
+    mode_grad_body<NP, MT, YT>(p, xcd_item(blockIdx.x, gridDim.x), flags, P6, a, dtau, uo, Y);
 }
 
 // Grouped kernels: one launch covers every member of a group (contexts of
@@ -927,13 +933,13 @@ __device__ __forceinline__ int group_member(const GroupMember* __restrict__ gm, 
     return lo;
 }
 
-template <int NP, class YT>
-__global__ __launch_bounds__(MODE_THREADS) void kg_synth(const GroupMember* __restrict__ gm, int n) {
+template <int NP, int MT, class YT>
+__global__ __launch_bounds__(MT) void kg_synth(const GroupMember* __restrict__ gm, int n) {
     const int it = xcd_item(blockIdx.x, gridDim.x);
     if (it >= gm[n].item0[GPH_MODE]) return;
     const int k = group_member(gm, n, it, GPH_MODE);
     const GroupMember& g = gm[k];
-    synth_body<NP, YT>(g.kp, it - g.item0[GPH_MODE], g.u, static_cast<YT*>(g.Y));
+    synth_body<NP, MT, YT>(g.kp, it - g.item0[GPH_MODE], g.u, static_cast<YT*>(g.Y));
 }
 
 template <int MODE, class R, int NT>
@@ -950,28 +956,28 @@ __global__ __launch_bounds__(NT) void kg_plane(const GroupMember* __restrict__ g
                                 static_cast<const C<R>*>(g.Atil), static_cast<C<R>*>(g.P6));
 }
 
-template <int NP, class YT>
-__global__ __launch_bounds__(MODE_THREADS) void kg_mode_res(const GroupMember* __restrict__ gm, int n) {
+template <int NP, int MT, class YT>
+__global__ __launch_bounds__(MT) void kg_mode_res(const GroupMember* __restrict__ gm, int n) {
     const int it = xcd_item(blockIdx.x, gridDim.x);
     if (it >= gm[n].item0[GPH_MODE]) return;
     const int k = group_member(gm, n, it, GPH_MODE);
     const GroupMember& g = gm[k];
-    mode_res_body<NP, YT>(g.kp, it - g.item0[GPH_MODE], RES_COST | RES_ADJ, static_cast<const YT*>(g.P3), g.u,
+    mode_res_body<NP, MT, YT>(g.kp, it - g.item0[GPH_MODE], RES_COST | RES_ADJ, static_cast<const YT*>(g.P3), g.u,
                           nullptr, g.part, g.a, static_cast<YT*>(g.Atil));
 }
 
-template <int NP, class YT>
-__global__ __launch_bounds__(MODE_THREADS) void kg_mode_grad(const GroupMember* __restrict__ gm, int n) {
+template <int NP, int MT, class YT>
+__global__ __launch_bounds__(MT) void kg_mode_grad(const GroupMember* __restrict__ gm, int n) {
     const int it = xcd_item(blockIdx.x, gridDim.x);
     if (it >= gm[n].item0[GPH_MODE]) return;
     const int k = group_member(gm, n, it, GPH_MODE);
     const GroupMember& g = gm[k];
-    mode_grad_body<NP, YT>(g.kp, it - g.item0[GPH_MODE], GRAD_PROJECT | GRAD_UPDATE, static_cast<const YT*>(g.P6),
+    mode_grad_body<NP, MT, YT>(g.kp, it - g.item0[GPH_MODE], GRAD_PROJECT | GRAD_UPDATE, static_cast<const YT*>(g.P6),
                            g.a, g.dtau, g.u, static_cast<YT*>(g.Y));
 }
 
-template <int NP>
-__global__ __launch_bounds__(MODE_THREADS) void k_project(KP p, const double2* __restrict__ g,
+template <int NP, int MT>
+__global__ __launch_bounds__(MT) void k_project(KP p, const double2* __restrict__ g,
                                                           double2* __restrict__ out) {
     extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
@@ -981,14 +987,14 @@ __global__ __launch_bounds__(MODE_THREADS) void k_project(KP p, const double2* _
     auto vec = [&](int k) { return sm + (size_t)k * N; };
     double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = g[so + ((size_t)i * nm + m) * N + n];
+        for (int n = t; n < N; n += MT) vec(i)[n] = g[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
     if (m == 0)
-        project0<NP>(p, vec(0), vec(2), vec(3), vec(4), vec(5));
+        project0<NP, MT>(p, vec(0), vec(2), vec(3), vec(4), vec(5));
     else
-        project<NP>(p, m, mscal(p, m), vec(0), vec(1), vec(2), vec(3), vec(4), vec(5), vec(12));
+        project<NP, MT>(p, m, mscal(p, m), vec(0), vec(1), vec(2), vec(3), vec(4), vec(5), vec(12));
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) out[so + ((size_t)i * nm + m) * N + n] = vec(3 + i)[n];
+        for (int n = t; n < N; n += MT) out[so + ((size_t)i * nm + m) * N + n] = vec(3 + i)[n];
 }
 
 // Deterministic per-guess reductions of per-mode partials: out[g * stride + c]
@@ -1019,8 +1025,8 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
 }
 
 // Per-mode partials of ||u||^2, ||u_b + u||^2 and <curl U, curl U> (U = u_b + u).
-template <int NP>
-__global__ __launch_bounds__(MODE_THREADS) void k_norms(KP p, const double2* __restrict__ u,
+template <int NP, int MT>
+__global__ __launch_bounds__(MT) void k_norms(KP p, const double2* __restrict__ u,
                                                         double* __restrict__ part) {
     extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
@@ -1031,49 +1037,49 @@ __global__ __launch_bounds__(MODE_THREADS) void k_norms(KP p, const double2* __r
     double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
     const MS c = mscal(p, m);
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = u[so + ((size_t)i * nm + m) * N + n];
+        for (int n = t; n < N; n += MT) vec(i)[n] = u[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
-    mv3<NP>(p, M_G, N, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
+    mv3<NP, MT>(p, M_G, N, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
     __syncthreads();
     double s0 = 0;
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) s0 += vec(i)[n].x * vec(3 + i)[n].x + vec(i)[n].y * vec(3 + i)[n].y;
+        for (int n = t; n < N; n += MT) s0 += vec(i)[n].x * vec(3 + i)[n].x + vec(i)[n].y * vec(3 + i)[n].y;
     {
         double tot[1] = {s0};
-        bsum(tot, red);
+        bsum<MT>(tot, red);
         s0 = tot[0];
     }
     if (m == 0 && t == 0) vec(0)[1] = cadd(vec(0)[1], c2(1.0, 0.0));  // + u_b = T_1(y) e_x
     __syncthreads();
-    mv3<NP>(p, M_G, N, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
-    mv<NP>(p, M_D, N, N, vec(0), vec(6));
-    mv<NP>(p, M_D, N, N, vec(2), vec(7));
+    mv3<NP, MT>(p, M_G, N, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
+    mv<NP, MT>(p, M_D, N, N, vec(0), vec(6));
+    mv<NP, MT>(p, M_D, N, N, vec(2), vec(7));
     __syncthreads();
     double s1 = 0;
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) s1 += vec(i)[n].x * vec(3 + i)[n].x + vec(i)[n].y * vec(3 + i)[n].y;
+        for (int n = t; n < N; n += MT) s1 += vec(i)[n].x * vec(3 + i)[n].x + vec(i)[n].y * vec(3 + i)[n].y;
     {
         double tot[1] = {s1};
-        bsum(tot, red);
+        bsum<MT>(tot, red);
         s1 = tot[0];
     }
     // vorticity: (D U_z - i b U_y, i b U_x - i a U_z, i a U_y - D U_x)
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         const double2 ux = vec(0)[n], uy = vec(1)[n], uz = vec(2)[n];
         vec(8)[n] = csub(vec(7)[n], imul(c.b, uy));
         vec(9)[n] = csub(imul(c.b, ux), imul(c.a, uz));
         vec(10)[n] = csub(imul(c.a, uy), vec(6)[n]);
     }
     __syncthreads();
-    mv3<NP>(p, M_G, N, N, vec(8), vec(9), vec(10), vec(11), vec(12), vec(13));
+    mv3<NP, MT>(p, M_G, N, N, vec(8), vec(9), vec(10), vec(11), vec(12), vec(13));
     __syncthreads();
     double s2 = 0;
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS)
+        for (int n = t; n < N; n += MT)
             s2 += vec(8 + i)[n].x * vec(11 + i)[n].x + vec(8 + i)[n].y * vec(11 + i)[n].y;
     {
         double tot[1] = {s2};
-        bsum(tot, red);
+        bsum<MT>(tot, red);
         s2 = tot[0];
     }
     if (t == 0) {
@@ -1084,8 +1090,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_norms(KP p, const double2* __r
 }
 
 // Per-mode admissibility defects: max |div|, max |wall value|, Hermitian defect.
-template <int NP>
-__global__ __launch_bounds__(MODE_THREADS) void k_check(KP p, const double2* __restrict__ u,
+template <int NP, int MT>
+__global__ __launch_bounds__(MT) void k_check(KP p, const double2* __restrict__ u,
                                                         double* __restrict__ part) {
     extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
@@ -1096,16 +1102,16 @@ __global__ __launch_bounds__(MODE_THREADS) void k_check(KP p, const double2* __r
     double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
     const MS c = mscal(p, m);
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MODE_THREADS) vec(i)[n] = u[so + ((size_t)i * nm + m) * N + n];
+        for (int n = t; n < N; n += MT) vec(i)[n] = u[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
-    mv<NP>(p, M_D, N, N, vec(1), vec(3));
+    mv<NP, MT>(p, M_D, N, N, vec(1), vec(3));
     __syncthreads();
     double dv = 0, herm = 0;
     double wr[6] = {0, 0, 0, 0, 0, 0}, wi[6] = {0, 0, 0, 0, 0, 0};
     const int ikx = m / p.nkz, kz = m - ikx * p.nkz;
     const int kx = (ikx <= p.Kx) ? ikx : ikx - p.nkx;
     const int mp = ((p.nkx - ikx) % p.nkx) * p.nkz;
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         const double2 d = cadd(cadd(imul(c.a, vec(0)[n]), vec(3)[n]), imul(c.b, vec(2)[n]));
         dv = fmax(dv, hypot(d.x, d.y));
         for (int i = 0; i < 3; ++i) {
@@ -1126,11 +1132,11 @@ __global__ __launch_bounds__(MODE_THREADS) void k_check(KP p, const double2* __r
         sums[2 * q] = wr[q];
         sums[2 * q + 1] = wi[q];
     }
-    bsum(sums, red);
+    bsum<MT>(sums, red);
     double wall = 0;
     for (int q = 0; q < 6; ++q) wall = fmax(wall, hypot(sums[2 * q], sums[2 * q + 1]));
     double mx[2] = {dv, herm};
-    bmax(mx, red);
+    bmax<MT>(mx, red);
     dv = mx[0];
     herm = mx[1];
     if (t == 0) {
@@ -1140,7 +1146,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_check(KP p, const double2* __r
     }
 }
 
-__global__ __launch_bounds__(MODE_THREADS) void k_pack(KP p, const double2* __restrict__ u,
+template <int MT>
+__global__ __launch_bounds__(MT) void k_pack(KP p, const double2* __restrict__ u,
                                                        double* __restrict__ psi) {
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
@@ -1149,7 +1156,7 @@ __global__ __launch_bounds__(MODE_THREADS) void k_pack(KP p, const double2* __re
     const int idx = p.indep[m];
     if (idx < 0) return;
     if (m == 0) {
-        for (int n = t; n < N - 2; n += MODE_THREADS) {
+        for (int n = t; n < N - 2; n += MT) {
             psi[(size_t)b * p.nstate + n] = u[so + (size_t)m * N + n].x;
             psi[(size_t)b * p.nstate + (N - 2) + n] = u[so + ((size_t)2 * nm + m) * N + n].x;
         }
@@ -1157,7 +1164,7 @@ __global__ __launch_bounds__(MODE_THREADS) void k_pack(KP p, const double2* __re
     }
     const MS c = mscal(p, m);
     double* o = psi + (size_t)b * p.nstate + 2 * (N - 2) + (size_t)idx * (4 * N - 12);
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         const double2 v = u[so + ((size_t)nm + m) * N + n];
         const double2 e = csub(imul(c.b, u[so + (size_t)m * N + n]), imul(c.a, u[so + ((size_t)2 * nm + m) * N + n]));
         if (n < N - 4) {
@@ -1172,20 +1179,21 @@ __global__ __launch_bounds__(MODE_THREADS) void k_pack(KP p, const double2* __re
 }
 
 // Sum over lanes of x[n] (n < lim, n = par mod 2), optionally weighted by n^2.
+template <int MT>
 __device__ double2 par_sum(const double2* x, int lim, int par, bool sq, double* red) {
     double v[2] = {0, 0};
-    for (int n = threadIdx.x; n < lim; n += MODE_THREADS)
+    for (int n = threadIdx.x; n < lim; n += MT)
         if ((n & 1) == par) {
             const double w = sq ? (double)n * n : 1.0;
             v[0] += w * x[n].x;
             v[1] += w * x[n].y;
         }
-    bsum(v, red);
+    bsum<MT>(v, red);
     return c2(v[0], v[1]);
 }
 
-template <int NP>
-__global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __restrict__ psi,
+template <int NP, int MT>
+__global__ __launch_bounds__(MT) void k_unpack(KP p, const double* __restrict__ psi,
                                                          double2* __restrict__ u) {
     extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
@@ -1197,14 +1205,14 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
     auto vec = [&](int k) { return sm + (size_t)k * N; };
     double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
     if (m == 0) {
-        for (int n = t; n < N; n += MODE_THREADS) {
+        for (int n = t; n < N; n += MT) {
             vec(0)[n] = c2(n < N - 2 ? psi[(size_t)b * p.nstate + n] : 0.0, 0);
             vec(1)[n] = c2(n < N - 2 ? psi[(size_t)b * p.nstate + (N - 2) + n] : 0.0, 0);
         }
         __syncthreads();
         for (int f = 0; f < 2; ++f) {  // Dirichlet: each parity class sums to zero
-            const double2 s0 = par_sum(vec(f), N - 2, (N - 2) & 1, false, red);
-            const double2 s1 = par_sum(vec(f), N - 2, (N - 1) & 1, false, red);
+            const double2 s0 = par_sum<MT>(vec(f), N - 2, (N - 2) & 1, false, red);
+            const double2 s1 = par_sum<MT>(vec(f), N - 2, (N - 1) & 1, false, red);
             __syncthreads();
             if (t == 0) {
                 vec(f)[N - 2] = cscl(-1.0, s0);
@@ -1212,7 +1220,7 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
             }
             __syncthreads();
         }
-        for (int n = t; n < N; n += MODE_THREADS) {
+        for (int n = t; n < N; n += MT) {
             u[so + (size_t)m * N + n] = vec(0)[n];
             u[so + ((size_t)nm + m) * N + n] = c2(0, 0);
             u[so + ((size_t)2 * nm + m) * N + n] = vec(1)[n];
@@ -1222,7 +1230,7 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
     const MS c = mscal(p, m);
     const double* o = psi + (size_t)b * p.nstate + 2 * (N - 2) + (size_t)idx * (4 * N - 12);
     double2 *v = vec(0), *e = vec(1), *Dv = vec(2);
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         v[n] = (n < N - 4) ? c2(o[n], o[(N - 4) + n]) : c2(0, 0);
         e[n] = (n < N - 2) ? c2(o[2 * (N - 4) + n], o[2 * (N - 4) + (N - 2) + n]) : c2(0, 0);
     }
@@ -1230,7 +1238,7 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
     // clamped v: within each parity class sum v_n = 0 and sum n^2 v_n = 0
     for (int q = N - 2; q < N; ++q) {
         const int pp = q - 2, par = q & 1;
-        const double2 s0 = par_sum(v, pp, par, false, red), s2 = par_sum(v, pp, par, true, red);
+        const double2 s0 = par_sum<MT>(v, pp, par, false, red), s2 = par_sum<MT>(v, pp, par, true, red);
         const double2 vq = cscl(1.0 / ((double)q * q - (double)pp * pp), csub(cscl((double)pp * pp, s0), s2));
         __syncthreads();
         if (t == 0) {
@@ -1240,8 +1248,8 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
         __syncthreads();
     }
     {
-        const double2 s0 = par_sum(e, N - 2, (N - 2) & 1, false, red);
-        const double2 s1 = par_sum(e, N - 2, (N - 1) & 1, false, red);
+        const double2 s0 = par_sum<MT>(e, N - 2, (N - 2) & 1, false, red);
+        const double2 s1 = par_sum<MT>(e, N - 2, (N - 1) & 1, false, red);
         __syncthreads();
         if (t == 0) {
             e[N - 2] = cscl(-1.0, s0);
@@ -1249,11 +1257,11 @@ __global__ __launch_bounds__(MODE_THREADS) void k_unpack(KP p, const double* __r
         }
         __syncthreads();
     }
-    mv<NP>(p, M_D, N, N, v, Dv);
+    mv<NP, MT>(p, M_D, N, N, v, Dv);
     __syncthreads();
     const int ikx = m / p.nkz, kz = m - ikx * p.nkz;
     const int mp = ((p.nkx - ikx) % p.nkx) * p.nkz;
-    for (int n = t; n < N; n += MODE_THREADS) {
+    for (int n = t; n < N; n += MT) {
         const double2 ux = cscl(c.ik2, csub(imul(c.a, Dv[n]), imul(c.b, e[n])));
         const double2 uz = cscl(c.ik2, cadd(imul(c.b, Dv[n]), imul(c.a, e[n])));
         const double2 vals[3] = {ux, v[n], uz};
@@ -1360,7 +1368,7 @@ size_t plane_lds_bytes(const KP& p, int mode) {
 }
 
 size_t mode_lds_bytes(const KP& p) {
-    return (size_t)MODE_VECS * p.N * 16 + (size_t)MODE_WAVES * RED_SLOTS * 8;
+    return (size_t)MODE_VECS * p.N * 16 + (size_t)(p.mthreads / WAVE) * RED_SLOTS * 8;
 }
 
 static dim3 mode_grid(const KP& p) { return dim3((unsigned)((p.nmB + NXCD - 1) / NXCD * NXCD)); }
@@ -1383,11 +1391,19 @@ static int padded_ny(const KP& p) { return padded_ny(p.N); }
         default: return hipErrorInvalidValue;                     \
     }
 
+// Dispatch on the padded Ny (NP) and the per-mode work-group size (MT).
+#define PCFV_DISPATCH_MODE(np, mt, ...)                                                  \
+    switch (mt) {                                                                        \
+        case 256: { constexpr int MT = 256; PCFV_DISPATCH_NP(np, __VA_ARGS__); } break;  \
+        case 512: { constexpr int MT = 512; PCFV_DISPATCH_NP(np, __VA_ARGS__); } break;  \
+        default: return hipErrorInvalidValue;                                            \
+    }
+
 // The y-value and partial arrays are raw storage: FP64 complex for PREC_FP64,
 // FP32 complex (half the bytes, same buffers) for PREC_FP32.
 template <class YT>
 static hipError_t synth_t(const KP& p, hipStream_t s, const double2* u, void* Y) {
-    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL((k_synth<NP, YT>), mode_grid(p), dim3(MODE_THREADS),
+    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_synth<NP, MT, YT>), mode_grid(p), dim3(MT),
                                                       mode_lds_bytes(p), s, p, u, static_cast<YT*>(Y)));
     return hipGetLastError();
 }
@@ -1426,7 +1442,7 @@ hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const void* Y1, co
 template <class YT>
 static hipError_t mode_res_t(const KP& p, hipStream_t s, int flags, const void* P3, const double2* u,
                              double2* r, double* cost_part, double2* a, void* Atil) {
-    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL((k_mode_res<NP, YT>), mode_grid(p), dim3(MODE_THREADS),
+    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_mode_res<NP, MT, YT>), mode_grid(p), dim3(MT),
                                                       mode_lds_bytes(p), s, p, flags, static_cast<const YT*>(P3),
                                                       u, r, cost_part, a, static_cast<YT*>(Atil)));
     return hipGetLastError();
@@ -1441,7 +1457,7 @@ hipError_t launch_mode_res(const KP& p, hipStream_t s, int flags, const void* P3
 template <class YT>
 static hipError_t mode_grad_t(const KP& p, hipStream_t s, int flags, const void* P6, const double2* a,
                               double dtau, double2* u_or_out, void* Y) {
-    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL((k_mode_grad<NP, YT>), mode_grid(p), dim3(MODE_THREADS),
+    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_mode_grad<NP, MT, YT>), mode_grid(p), dim3(MT),
                                                       mode_lds_bytes(p), s, p, flags, static_cast<const YT*>(P6),
                                                       a, dtau, u_or_out, static_cast<YT*>(Y)));
     return hipGetLastError();
@@ -1460,21 +1476,21 @@ static hipError_t group_t(const GroupLaunch& g, hipStream_t s, int which) {
     const dim3 gp = grid8(g.items[GPH_PLANE]), gmo = grid8(g.items[GPH_MODE]);
     switch (which) {
         case GK_SYNTH:
-            PCFV_DISPATCH_NP(g.np, hipLaunchKernelGGL((kg_synth<NP, YT>), gmo, dim3(MODE_THREADS), g.mode_lds, s,
+            PCFV_DISPATCH_MODE(g.np, g.mthreads, hipLaunchKernelGGL((kg_synth<NP, MT, YT>), gmo, dim3(MT), g.mode_lds, s,
                                                       g.gm, g.n));
             break;
         case GK_PLANE_FWD:
             hipLaunchKernelGGL((kg_plane<PLANE_FWD, R, NT>), gp, dim3(NT), g.plane_lds[PLANE_FWD], s, g.gm, g.n);
             break;
         case GK_MODE_RES:
-            PCFV_DISPATCH_NP(g.np, hipLaunchKernelGGL((kg_mode_res<NP, YT>), gmo, dim3(MODE_THREADS), g.mode_lds,
+            PCFV_DISPATCH_MODE(g.np, g.mthreads, hipLaunchKernelGGL((kg_mode_res<NP, MT, YT>), gmo, dim3(MT), g.mode_lds,
                                                       s, g.gm, g.n));
             break;
         case GK_PLANE_ADJ:
             hipLaunchKernelGGL((kg_plane<PLANE_ADJ, R, NT>), gp, dim3(NT), g.plane_lds[PLANE_ADJ], s, g.gm, g.n);
             break;
         case GK_MODE_GRAD:
-            PCFV_DISPATCH_NP(g.np, hipLaunchKernelGGL((kg_mode_grad<NP, YT>), gmo, dim3(MODE_THREADS), g.mode_lds,
+            PCFV_DISPATCH_MODE(g.np, g.mthreads, hipLaunchKernelGGL((kg_mode_grad<NP, MT, YT>), gmo, dim3(MT), g.mode_lds,
                                                       s, g.gm, g.n));
             break;
         default:
@@ -1492,7 +1508,7 @@ hipError_t launch_group(const GroupLaunch& g, hipStream_t s, int which) {
 }
 
 hipError_t launch_project(const KP& p, hipStream_t s, const double2* g, double2* out) {
-    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_project<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, g, out));
+    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_project<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, g, out));
     return hipGetLastError();
 }
 
@@ -1503,22 +1519,25 @@ hipError_t launch_reduce(hipStream_t s, const double* part, int ngroups, int n, 
 }
 
 hipError_t launch_norms(const KP& p, hipStream_t s, const double2* u, double* part) {
-    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_norms<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, u, part));
+    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_norms<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, u, part));
     return hipGetLastError();
 }
 
 hipError_t launch_check(const KP& p, hipStream_t s, const double2* u, double* part) {
-    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_check<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, u, part));
+    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_check<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, u, part));
     return hipGetLastError();
 }
 
 hipError_t launch_pack(const KP& p, hipStream_t s, const double2* u, double* psi) {
-    hipLaunchKernelGGL(k_pack, mode_grid(p), dim3(MODE_THREADS), 0, s, p, u, psi);
+    if (p.mthreads == 512)
+        hipLaunchKernelGGL(k_pack<512>, mode_grid(p), dim3(512), 0, s, p, u, psi);
+    else
+        hipLaunchKernelGGL(k_pack<256>, mode_grid(p), dim3(256), 0, s, p, u, psi);
     return hipGetLastError();
 }
 
 hipError_t launch_unpack(const KP& p, hipStream_t s, const double* psi, double2* u) {
-    PCFV_DISPATCH_NP(padded_ny(p), hipLaunchKernelGGL(k_unpack<NP>, mode_grid(p), dim3(MODE_THREADS), mode_lds_bytes(p), s, p, psi, u));
+    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_unpack<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, psi, u));
     return hipGetLastError();
 }
 

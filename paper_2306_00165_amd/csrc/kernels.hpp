@@ -14,6 +14,7 @@ struct KP {
     int XS, NS;              // x-slab width of the physical-space kernels, number of slabs
     int prec;                // PREC_FP64, or PREC_FP32 for the physical-space transforms and products
     int pthreads;            // threads per work group of the physical-space kernels (256 or 512)
+    int mthreads;            // threads per work group of the per-mode kernels (256 or 512)
     double lam, nu, alpha, beta;
     const double* M;         // M_COUNT fixed matrices, N x N slots, transposed
     const double* minfo;     // per-mode scalars (MI_STRIDE each)
@@ -76,6 +77,7 @@ struct GroupLaunch {
     int np;                  // padded Ny (largest over the members)
     int prec;                // common precision
     int pthreads;            // common physical-space work-group size
+    int mthreads;            // common per-mode work-group size
     size_t plane_lds[3];     // largest LDS per plane mode over the members
     size_t mode_lds;
 };

@@ -35,7 +35,7 @@ EXPORTS = [
     "pcfv_mlp_last_error", "pcfv_mlp_set_params", "pcfv_mlp_get_params", "pcfv_mlp_forward", "pcfv_mlp_grad",
     "pcfv_mlp_adam_step", "pcfv_mlp_read", "pcfv_mlp_fit", "pcfv_pod_scratch_bytes", "pcfv_pod_build",
     "pcfv_pod_project_scratch_bytes", "pcfv_pod_project", "pcfv_pod_reconstruct", "pcfv_learned_scratch_bytes",
-    "pcfv_learned_propose", "pcfv_learned_prepare",
+    "pcfv_learned_propose", "pcfv_learned_prepare", "pcfv_time_descent_kernels",
 ]
 
 MLP_MAX_LAYERS = 8
@@ -80,7 +80,8 @@ class LearnedModel(ctypes.Structure):
 
 
 class TuneEntry(ctypes.Structure):
-    _fields_ = [("xs", ctypes.c_int), ("plane_threads", ctypes.c_int), ("ms_per_step", ctypes.c_double)]
+    _fields_ = [("xs", ctypes.c_int), ("plane_threads", ctypes.c_int), ("mode_threads", ctypes.c_int),
+                ("ms_per_step", ctypes.c_double)]
 
 
 class DescentReport(ctypes.Structure):
@@ -126,6 +127,8 @@ def load_library(path=_LIB_PATH):
     for name in ("pcfv_norms", "pcfv_check_state"):
         getattr(lib, name).restype = i
         getattr(lib, name).argtypes = [vp, vp, dp]
+    lib.pcfv_time_descent_kernels.restype = i
+    lib.pcfv_time_descent_kernels.argtypes = [vp, vp, d, i, dp]
     lib.pcfv_time_kernels.restype = i
     lib.pcfv_time_kernels.argtypes = [vp, vp, i, dp, ctypes.POINTER(i)]
     lib.pcfv_last_error.restype = ctypes.c_char_p
@@ -139,7 +142,7 @@ def load_library(path=_LIB_PATH):
     lib.pcfv_autotune.restype = i
     lib.pcfv_autotune.argtypes = [vp, vp, i, ctypes.POINTER(TuneEntry), i, ctypes.POINTER(i)]
     lib.pcfv_get_tuning.restype = i
-    lib.pcfv_get_tuning.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.pcfv_get_tuning.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
     lib.pcfv_group_create.restype = i
     lib.pcfv_group_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp)]
     lib.pcfv_group_destroy.restype = None
@@ -420,23 +423,32 @@ class Context:
         self._check(_lib.pcfv_time_kernels(self._h, _ptr(u), int(nrep), out, ctypes.byref(n)))
         return list(out)[:n.value]
 
+    def time_descent_kernels(self, u, dtau, nsteps=50):
+        """Advance u by nsteps descent steps, timing each kernel inside the
+        steps; returns ms per launch [plane_fwd, mode_res, plane_adj, mode_grad]."""
+        if not (u.is_contiguous() and u.dtype == self.torch.complex128 and tuple(u.shape) == self.shape):
+            raise ValueError("u must be a contiguous complex128 device tensor of the context shape")
+        out = (ctypes.c_double * 4)()
+        self._check(_lib.pcfv_time_descent_kernels(self._h, _ptr(u), float(dtau), int(nsteps), out))
+        return list(out)
+
     def synchronize(self):
         self.stream.synchronize()
 
     def autotune(self, u, steps=20):
         """Time every launch-shape candidate on a copy of u and keep the
-        fastest; returns the list of (xs, plane_threads, ms_per_step)."""
+        fastest; returns the list of (xs, plane_threads, mode_threads, ms_per_step)."""
         u = self._field(u)
         cap = 64
         ent = (TuneEntry * cap)()
         n = ctypes.c_int(0)
         self._check(_lib.pcfv_autotune(self._h, _ptr(u), int(steps), ent, cap, ctypes.byref(n)))
-        return [(e.xs, e.plane_threads, e.ms_per_step) for e in ent[:n.value]]
+        return [(e.xs, e.plane_threads, e.mode_threads, e.ms_per_step) for e in ent[:n.value]]
 
     def tuning(self):
-        xs, nt = ctypes.c_int(0), ctypes.c_int(0)
-        self._check(_lib.pcfv_get_tuning(self._h, ctypes.byref(xs), ctypes.byref(nt)))
-        return xs.value, nt.value
+        xs, nt, mt = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        self._check(_lib.pcfv_get_tuning(self._h, ctypes.byref(xs), ctypes.byref(nt), ctypes.byref(mt)))
+        return xs.value, nt.value, mt.value
 
 
 class Group:

@@ -532,9 +532,9 @@ def test_autotune_keeps_parity(ctxs):
     c = Context(32, 33, 32)
     u = guess(g, 9)
     ent = c.autotune(u, steps=5)
-    assert ent and all(32 % xs == 0 and nt in (256, 512) for xs, nt, _ in ent)
-    best = min(ent, key=lambda e: e[2])
-    assert c.tuning() == (best[0], best[1])
+    assert ent and all(32 % xs == 0 and nt in (256, 512) and mt in (256, 512) for xs, nt, mt, _ in ent)
+    best = min(ent, key=lambda e: e[3])
+    assert c.tuning() == best[:3]
     print(f"[gpu] autotune 32x33x32: {ent}")
     assert rel(to_np(c.residual(u)), m.residual(u)) < TOL
     U = torch.as_tensor(u).to("cuda:0").contiguous()
