@@ -305,6 +305,7 @@ const char* pcfv_group_last_error(const pcfv_group* group);
  * the true residual of the method, and DMD stays the fallback.
  * ------------------------------------------------------------------------- */
 #define PCFV_MLP_MAX_LAYERS 8
+#define PCFV_LEARNED_MAX_SCALES 8
 
 /* dims[0] inputs, dims[n_layers] outputs; ReLU after every layer but the
  * last.  Parameters (FP32, host order): for each layer l, W_l (dims[l] x
@@ -360,36 +361,45 @@ pcfv_status pcfv_pod_reconstruct(void* hip_stream, const double* coef, int m, lo
                                  const double* basis, double* X);
 
 /* A trained extrapolator.  Input features of guess b: for w < W-1 the
- * differences c_w - c_{W-1} of the POD coefficients of the window's snapshots
- * and c_{W-1} itself (W r values, window position major), normalised as
- * (x - in_mu) * in_isd; the MLP output y gives the step to the limit in POD
- * coefficients, dc = y / out_isd + out_mu, and the proposal is the last
- * snapshot plus that step, psi_{W-1} + dc basis (what the r modes do not
- * resolve is kept from the last snapshot).  All pointers are device memory
- * owned by the caller. */
+ * differences c_w - c_{W-1} of the POD coefficients of the window's snapshots,
+ * c_{W-1} itself and, if use_base, c_base - c_{W-1} for the POD coefficients
+ * of a base candidate ((W + use_base) r values, window position major),
+ * normalised as (x - in_mu) * in_isd.  The MLP output y gives a step in POD
+ * coefficients, dc = y / out_isd + out_mu, and the proposal is the base plus
+ * that step: psi_{W-1} + dc basis, or psi_base + dc basis with use_base (what
+ * the r modes do not resolve is kept from the base).  With use_base the
+ * descent passes the DMD candidate as the base, so the network learns a
+ * correction to DMD.  All pointers are device memory owned by the caller. */
 typedef struct pcfv_learned_model {
     int window;               /* W */
+    int use_base;             /* 0: step from the last snapshot; 1: from a base candidate */
     int r;                    /* POD modes */
     const double* pod_mean;   /* n_state */
     const double* pod_basis;  /* r x n_state */
-    const float* in_mu;       /* W r */
-    const float* in_isd;      /* W r */
+    const float* in_mu;       /* (W + use_base) r */
+    const float* in_isd;      /* (W + use_base) r */
     const float* out_mu;      /* r */
     const float* out_isd;     /* r */
-    pcfv_mlp* mlp;            /* dims[0] = W r, dims[last] = r, max_batch >= the context batch */
+    pcfv_mlp* mlp;            /* dims[0] = (W + use_base) r, dims[last] = r, max_batch >= the context batch */
+    /* Step lengths tried along the predicted step (psi = base + s dc basis);
+     * each guess gets the one of least true cost.  n_scales = 0: s = 1 only. */
+    int n_scales;
+    double scales[PCFV_LEARNED_MAX_SCALES];
     void* scratch;            /* pcfv_learned_scratch_bytes(ctx, window, r) bytes */
 } pcfv_learned_model;
 size_t pcfv_learned_scratch_bytes(const pcfv_ctx* ctx, int window, int r);
 
 /* Training set of the extrapolator from POD coefficients: c (device, [W][B][r]
- * doubles: W window snapshots of B training windows) and ct (device, B x r:
- * the coefficients of each window's descent limit, or NULL).  Writes the
- * features X (device FP32, B x W r) and, if ct, the targets T (B x r) of the
- * model's definition.  fit != 0 first computes the normalisation from this
+ * doubles: W window snapshots of B training windows), cb (device, B x r: the
+ * base candidates' coefficients, or NULL for a model without base) and ct
+ * (device, B x r: the coefficients of each window's descent limit, or NULL).
+ * Writes the features X (device FP32, B x (W + [cb]) r) and, if ct, the
+ * targets T (B x r: ct - cb, or ct - c_{W-1}) of the model's definition.  fit != 0 first computes the normalisation from this
  * set (per-column mean and 1/max(std, 1e-12)) into in_mu, in_isd and, if ct,
  * out_mu, out_isd; fit = 0 uses the given ones.  Asynchronous on hip_stream. */
-pcfv_status pcfv_learned_prepare(void* hip_stream, int W, int B, int r, const double* c, const double* ct, int fit,
-                                 float* in_mu, float* in_isd, float* out_mu, float* out_isd, float* X, float* T);
+pcfv_status pcfv_learned_prepare(void* hip_stream, int W, int B, int r, const double* c, const double* cb,
+                                 const double* ct, int fit, float* in_mu, float* in_isd, float* out_mu, float* out_isd,
+                                 float* X, float* T);
 
 /* Minibatch training: `epochs` passes over the N rows of (X, T) (device FP32,
  * N x dims[0] and N x dims[L]) in batches of `batch` rows (a permutation per
@@ -400,10 +410,11 @@ pcfv_status pcfv_learned_prepare(void* hip_stream, int W, int B, int r, const do
 pcfv_status pcfv_mlp_fit(pcfv_mlp* mlp, const float* X, const float* T, int N, int batch, int epochs, float lr,
                          unsigned long long seed, int* idx, float* Xb, float* Tb, float* loss_host);
 /* Proposal for every guess from the window snaps (device, [W][batch][n_state],
- * oldest first, spaced as in training): u_out (batch fields) and its cost
- * J^2 per guess in cost_host (may be NULL).  Synchronises. */
-pcfv_status pcfv_learned_propose(pcfv_ctx* ctx, const pcfv_learned_model* model, const double* snaps, double* u_out,
-                                 double* cost_host);
+ * oldest first, spaced as in training) and, if model->use_base, the base
+ * candidates base (device, [batch][n_state]; ignored otherwise): u_out (batch
+ * fields) and its cost J^2 per guess in cost_host (may be NULL).  Synchronises. */
+pcfv_status pcfv_learned_propose(pcfv_ctx* ctx, const pcfv_learned_model* model, const double* snaps,
+                                 const double* base, double* u_out, double* cost_host);
 
 /* Host-side copy of a constant table for cfg, computed without a device (for
  * tests of the setup arithmetic).  which: 0 fixed matrices (27 slots of

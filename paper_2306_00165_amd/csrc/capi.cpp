@@ -250,7 +250,7 @@ pcfv_status descent_step(pcfv_ctx* ctx, double* u, double dtau) {
 // Scratch of the learned proposal: POD coefficients of the window, features,
 // MLP output, predicted coefficients, state vectors, projection partials.
 struct LearnedScratch {
-    size_t c, x, y, cs, psi, part, total;
+    size_t c, cb, x, y, cs, psi, part, total;
     int splits;
 };
 
@@ -267,7 +267,8 @@ LearnedScratch learned_scratch(const KP& p, int W, int r) {
         return at;
     };
     L.c = take((size_t)rows * r * 8);
-    L.x = take((size_t)p.B * W * r * 4);
+    L.cb = take((size_t)p.B * r * 8);
+    L.x = take((size_t)p.B * (W + 1) * r * 4);
     L.y = take((size_t)p.B * r * 4);
     L.cs = take((size_t)p.B * r * 8);
     L.psi = take((size_t)p.B * n * 8);
@@ -277,19 +278,24 @@ LearnedScratch learned_scratch(const KP& p, int W, int r) {
 }
 
 // Learned proposal of every guess into u_out (field layout) and its cost.
-pcfv_status learned_core(pcfv_ctx* ctx, const pcfv_learned_model* md, const double* snaps, double* u_out,
-                         std::vector<double>& cost) {
+// base (state vectors [B][n], required iff the model uses a base candidate)
+// is the state the predicted POD step starts from; otherwise the last snapshot.
+pcfv_status learned_core(pcfv_ctx* ctx, const pcfv_learned_model* md, const double* snaps, const double* base,
+                         double* u_out, std::vector<double>& cost) {
     const KP& p = ctx->kp;
     const int W = md->window, r = md->r, B = p.B;
     int din = 0, dout = 0, mb = 0;
     if (!md->mlp || !md->pod_mean || !md->pod_basis || !md->in_mu || !md->in_isd || !md->out_mu || !md->out_isd ||
         !md->scratch || W < 1 || r < 1)
         return fail(ctx, PCFV_EINVAL, "incomplete learned model");
+    if (md->use_base && !base) return fail(ctx, PCFV_EINVAL, "the model needs a base candidate");
     mlp_shape(md->mlp, &din, &dout, &mb);
-    if (din != W * r || dout != r || mb < B) return fail(ctx, PCFV_EINVAL, "MLP shape does not match the model");
+    if (din != (W + (md->use_base ? 1 : 0)) * r || dout != r || mb < B)
+        return fail(ctx, PCFV_EINVAL, "MLP shape does not match the model");
     const LearnedScratch L = learned_scratch(p, W, r);
     char* w = reinterpret_cast<char*>(md->scratch);
     double* c = reinterpret_cast<double*>(w + L.c);
+    double* cb = md->use_base ? reinterpret_cast<double*>(w + L.cb) : nullptr;
     float* x = reinterpret_cast<float*>(w + L.x);
     float* y = reinterpret_cast<float*>(w + L.y);
     double* cs = reinterpret_cast<double*>(w + L.cs);
@@ -300,23 +306,46 @@ pcfv_status learned_core(pcfv_ctx* ctx, const pcfv_learned_model* md, const doub
     PCFV_TRY(launch_gemm_f64(s, W * B, r, n, snaps, n, false, md->pod_basis, n, true, md->pod_mean, nullptr, c, r,
                              L.splits, part),
              "POD projection");
-    PCFV_TRY(launch_features(s, W, B, r, c, md->in_mu, md->in_isd, x), "features");
+    if (cb)
+        PCFV_TRY(launch_gemm_f64(s, B, r, n, base, n, false, md->pod_basis, n, true, md->pod_mean, nullptr, cb, r,
+                                 L.splits, part),
+                 "POD projection of the base");
+    PCFV_TRY(launch_features(s, W, B, r, c, cb, md->in_mu, md->in_isd, x), "features");
     pcfv_status st = mlp_forward_on(md->mlp, s, x, y, B);
     if (st != PCFV_OK) return fail(ctx, st, "MLP forward failed");
-    // psi = psi_{W-1} + dc basis: the step lies in the POD space, the last
-    // snapshot keeps everything the modes do not resolve
+    // psi = base + dc basis: the step lies in the POD space, the base (last
+    // snapshot or candidate) keeps everything the modes do not resolve
     PCFV_TRY(launch_prediction(s, B, r, y, md->out_mu, md->out_isd, cs), "prediction");
-    PCFV_TRY(hipMemcpyAsync(psi, snaps + (size_t)(W - 1) * B * n, (size_t)B * n * 8, hipMemcpyDeviceToDevice, s),
-             "last snapshot");
-    PCFV_TRY(launch_gemm_f64(s, B, (int)n, r, cs, r, false, md->pod_basis, n, false, nullptr, nullptr, psi, n, 1,
-                             nullptr, true),
-             "POD step");
-    PCFV_TRY(launch_unpack(p, s, psi, dd(u_out)), "unpack");
-    PCFV_TRY(launch_synth(p, s, cd(u_out), ctx->Y), "synth");
-    st = residual_core(ctx, u_out, nullptr, true);
-    if (st != PCFV_OK) return st;
-    cost.assign(B, 0.0);
-    return read_scalars(ctx, 1, 0, cost.data());
+    // a short line search along the predicted step, judged by the true cost
+    const double* psi0 = cb ? base : snaps + (size_t)(W - 1) * B * n;
+    const int ns = std::min(std::max(md->n_scales, 0), PCFV_LEARNED_MAX_SCALES);
+    const size_t fbytes1 = (size_t)3 * p.nm * p.N * 16;
+    cost.assign(B, HUGE_VAL);
+    std::vector<double> ck(B);
+    for (int k = 0; k < std::max(ns, 1); ++k) {
+        const double a = ns ? md->scales[k] : 1.0;
+        double2* trial = (ns > 1) ? ctx->tmp : dd(u_out);
+        PCFV_TRY(hipMemcpyAsync(psi, psi0, (size_t)B * n * 8, hipMemcpyDeviceToDevice, s), "base state");
+        PCFV_TRY(launch_gemm_f64(s, B, (int)n, r, cs, r, false, md->pod_basis, n, false, nullptr, nullptr, psi, n, 1,
+                                 nullptr, true, a),
+                 "POD step");
+        PCFV_TRY(launch_unpack(p, s, psi, trial), "unpack");
+        PCFV_TRY(launch_synth(p, s, trial, ctx->Y), "synth");
+        st = residual_core(ctx, reinterpret_cast<const double*>(trial), nullptr, true);
+        if (st != PCFV_OK) return st;
+        st = read_scalars(ctx, 1, 0, ck.data());
+        if (st != PCFV_OK) return st;
+        for (int b = 0; b < B; ++b)
+            if (ck[b] < cost[b] || !std::isfinite(cost[b])) {
+                cost[b] = ck[b];
+                if (trial != dd(u_out))
+                    PCFV_TRY(hipMemcpyAsync(reinterpret_cast<char*>(u_out) + b * fbytes1,
+                                            reinterpret_cast<const char*>(trial) + b * fbytes1, fbytes1,
+                                            hipMemcpyDeviceToDevice, s),
+                             "keep candidate");
+            }
+    }
+    return PCFV_OK;
 }
 
 // DMD extrapolation of the window snaps ([M][B][n_state]); writes the best
@@ -659,8 +688,13 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
                 if (o->learned) {
                     const int W = o->learned->window;
                     if (W > o->dmd_window) return report(fail(ctx, PCFV_EINVAL, "learned window exceeds dmd_window"));
+                    const double* base = nullptr;
+                    if (o->learned->use_base) {   // the DMD candidates (last snapshot where DMD had none)
+                        PCFV_TRY(launch_pack(p, ctx->stream, cand, ctx->dmdPsi), "pack");
+                        base = ctx->dmdPsi;
+                    }
                     s = learned_core(ctx, o->learned, o->dmd_buffer + (size_t)(o->dmd_window - W) * B * p.nstate,
-                                     reinterpret_cast<double*>(lcand), lcost);
+                                     base, reinterpret_cast<double*>(lcand), lcost);
                     if (s != PCFV_OK) return s;
                 }
                 for (int b = 0; b < B; ++b) {
@@ -1103,11 +1137,11 @@ size_t pcfv_learned_scratch_bytes(const pcfv_ctx* ctx, int window, int r) {
     return learned_scratch(ctx->kp, window, r).total;
 }
 
-pcfv_status pcfv_learned_propose(pcfv_ctx* ctx, const pcfv_learned_model* model, const double* snaps, double* u_out,
-                                 double* cost_host) {
+pcfv_status pcfv_learned_propose(pcfv_ctx* ctx, const pcfv_learned_model* model, const double* snaps,
+                                 const double* base, double* u_out, double* cost_host) {
     if (!ctx || !model || !snaps || !u_out) return fail(ctx, PCFV_EINVAL, "NULL argument");
     std::vector<double> cost;
-    pcfv_status s = learned_core(ctx, model, snaps, u_out, cost);
+    pcfv_status s = learned_core(ctx, model, snaps, base, u_out, cost);
     if (s != PCFV_OK) return s;
     if (cost_host)
         for (int b = 0; b < ctx->kp.B; ++b) cost_host[b] = cost[b];

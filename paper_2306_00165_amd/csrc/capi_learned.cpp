@@ -318,21 +318,23 @@ pcfv_status pcfv_mlp_fit(pcfv_mlp* mlp, const float* X, const float* T, int N, i
     return PCFV_OK;
 }
 
-pcfv_status pcfv_learned_prepare(void* hip_stream, int W, int B, int r, const double* c, const double* ct, int fit,
-                                 float* in_mu, float* in_isd, float* out_mu, float* out_isd, float* X, float* T) {
+pcfv_status pcfv_learned_prepare(void* hip_stream, int W, int B, int r, const double* c, const double* cb,
+                                 const double* ct, int fit, float* in_mu, float* in_isd, float* out_mu, float* out_isd,
+                                 float* X, float* T) {
     if (W < 1 || B < 1 || r < 1 || !c || !in_mu || !in_isd || !X || (ct && (!out_mu || !out_isd || !T)))
         return PCFV_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     const float kFloor = 1e-12f;
+    const int F = (W + (cb ? 1 : 0)) * r;
     if (fit) {
-        if (launch_features(s, W, B, r, c, nullptr, nullptr, X) != hipSuccess) return PCFV_EDEVICE;
-        if (launch_colstats(s, B, W * r, X, kFloor, in_mu, in_isd) != hipSuccess) return PCFV_EDEVICE;
-        if (launch_normalize(s, B, W * r, X, in_mu, in_isd) != hipSuccess) return PCFV_EDEVICE;
-    } else if (launch_features(s, W, B, r, c, in_mu, in_isd, X) != hipSuccess) {
+        if (launch_features(s, W, B, r, c, cb, nullptr, nullptr, X) != hipSuccess) return PCFV_EDEVICE;
+        if (launch_colstats(s, B, F, X, kFloor, in_mu, in_isd) != hipSuccess) return PCFV_EDEVICE;
+        if (launch_normalize(s, B, F, X, in_mu, in_isd) != hipSuccess) return PCFV_EDEVICE;
+    } else if (launch_features(s, W, B, r, c, cb, in_mu, in_isd, X) != hipSuccess) {
         return PCFV_EDEVICE;
     }
     if (ct) {
-        if (launch_targets(s, W, B, r, c, ct, T) != hipSuccess) return PCFV_EDEVICE;
+        if (launch_targets(s, W, B, r, c, cb, ct, T) != hipSuccess) return PCFV_EDEVICE;
         if (fit && launch_colstats(s, B, r, T, kFloor, out_mu, out_isd) != hipSuccess) return PCFV_EDEVICE;
         if (launch_normalize(s, B, r, T, out_mu, out_isd) != hipSuccess) return PCFV_EDEVICE;
     }

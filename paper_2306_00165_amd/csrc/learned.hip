@@ -148,8 +148,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, long long K, lon
                                                   const double* __restrict__ A, long long lda, int TA,
                                                   const double* __restrict__ B, long long ldb, int TB,
                                                   const double* __restrict__ Ashift, double* __restrict__ part,
-                                                  int direct, int accumulate, const double* __restrict__ Cadd,
-                                                  double* __restrict__ C, long long ldc) {
+                                                  int direct, int accumulate, double alpha,
+                                                  const double* __restrict__ Cadd, double* __restrict__ C,
+                                                  long long ldc) {
     __shared__ double sA[FK][FT + 1];
     __shared__ double sB[FK][FT + 1];
     const int m0 = blockIdx.y * FT, n0 = blockIdx.x * FT, z = blockIdx.z;
@@ -198,20 +199,22 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, long long K, lon
             const int row = m0 + ty + 16 * i, col = n0 + tx + 16 * j;
             if (row >= M || col >= N) continue;
             if (direct)
-                C[row * ldc + col] = (accumulate ? C[row * ldc + col] : 0.0) + acc[i][j] + (Cadd ? Cadd[col] : 0.0);
+                C[row * ldc + col] =
+                    (accumulate ? C[row * ldc + col] : 0.0) + alpha * acc[i][j] + (Cadd ? Cadd[col] : 0.0);
             else
                 part[((size_t)z * M + row) * N + col] = acc[i][j];
         }
 }
 
 __global__ void k_gemm_f64_reduce(int M, int N, int splits, const double* __restrict__ part, int accumulate,
-                                  const double* __restrict__ Cadd, double* __restrict__ C, long long ldc) {
+                                  double alpha, const double* __restrict__ Cadd, double* __restrict__ C,
+                                  long long ldc) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long long)M * N) return;
     const int row = (int)(e / N), col = (int)(e - (long long)row * N);
     double s = 0.0;
     for (int z = 0; z < splits; ++z) s += part[(size_t)z * M * N + e];
-    C[row * ldc + col] = (accumulate ? C[row * ldc + col] : 0.0) + s + (Cadd ? Cadd[col] : 0.0);
+    C[row * ldc + col] = (accumulate ? C[row * ldc + col] : 0.0) + alpha * s + (Cadd ? Cadd[col] : 0.0);
 }
 
 __global__ void k_rowmean(int S, long long n, const double* __restrict__ X, double* __restrict__ mean) {
@@ -246,22 +249,29 @@ __global__ void k_colstats(int B, int n, const float* __restrict__ F, float floo
     isd[j] = (float)(1.0 / (sd > floor_ ? sd : (double)floor_));
 }
 
-__global__ void k_features(int W, int B, int r, const double* __restrict__ c, const float* __restrict__ mu,
-                           const float* __restrict__ isd, float* __restrict__ x) {
+__global__ void k_features(int W, int B, int r, const double* __restrict__ c, const double* __restrict__ cb,
+                           const float* __restrict__ mu, const float* __restrict__ isd, float* __restrict__ x) {
+    const int F = (W + (cb ? 1 : 0)) * r;
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long long)B * W * r) return;
-    const int b = (int)(e / ((long long)W * r)), rem = (int)(e - (long long)b * W * r), w = rem / r, i = rem - w * r;
+    if (e >= (long long)B * F) return;
+    const int b = (int)(e / F), rem = (int)(e - (long long)b * F), w = rem / r, i = rem - w * r;
     const double last = c[((size_t)(W - 1) * B + b) * r + i];
-    const double v = (w < W - 1) ? c[((size_t)w * B + b) * r + i] - last : last;
+    double v;
+    if (w < W - 1)
+        v = c[((size_t)w * B + b) * r + i] - last;
+    else if (w == W - 1)
+        v = last;
+    else
+        v = cb[(size_t)b * r + i] - last;
     x[e] = mu ? (float)((v - mu[rem]) * isd[rem]) : (float)v;
 }
 
-__global__ void k_targets(int W, int B, int r, const double* __restrict__ c, const double* __restrict__ ct,
-                          float* __restrict__ t) {
+__global__ void k_targets(int W, int B, int r, const double* __restrict__ c, const double* __restrict__ cb,
+                          const double* __restrict__ ct, float* __restrict__ t) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= B * r) return;
     const int b = e / r, i = e - b * r;
-    t[e] = (float)(ct[e] - c[((size_t)(W - 1) * B + b) * r + i]);
+    t[e] = (float)(ct[e] - (cb ? cb[e] : c[((size_t)(W - 1) * B + b) * r + i]));
 }
 
 __global__ void k_normalize(int B, int n, float* __restrict__ F, const float* __restrict__ mu,
@@ -329,18 +339,18 @@ hipError_t launch_adam(hipStream_t s, long long n, const float* g, float* m, flo
 
 hipError_t launch_gemm_f64(hipStream_t s, int M, int N, long long K, const double* A, long long lda, bool TA,
                            const double* B, long long ldb, bool TB, const double* Ashift, const double* Cadd,
-                           double* C, long long ldc, int splits, double* part, bool accumulate) {
+                           double* C, long long ldc, int splits, double* part, bool accumulate, double alpha) {
     if (M <= 0 || N <= 0 || K <= 0 || splits < 1) return hipErrorInvalidValue;
     long long kchunk = (K + splits - 1) / splits;
     kchunk = (kchunk + FK - 1) / FK * FK;
     const int z = (int)((K + kchunk - 1) / kchunk);
     const int direct = (z == 1);
     hipLaunchKernelGGL(k_gemm_f64, dim3(blocks(N, FT), blocks(M, FT), z), dim3(256), 0, s, M, N, K, kchunk, A, lda,
-                       (int)TA, B, ldb, (int)TB, Ashift, part, direct, (int)accumulate, Cadd, C, ldc);
+                       (int)TA, B, ldb, (int)TB, Ashift, part, direct, (int)accumulate, alpha, Cadd, C, ldc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || direct) return e;
     hipLaunchKernelGGL(k_gemm_f64_reduce, dim3(blocks((long long)M * N, 256)), dim3(256), 0, s, M, N, z, part,
-                       (int)accumulate, Cadd, C, ldc);
+                       (int)accumulate, alpha, Cadd, C, ldc);
     return hipGetLastError();
 }
 
@@ -359,9 +369,10 @@ hipError_t launch_colstats(hipStream_t s, int B, int n, const float* F, float fl
     return hipGetLastError();
 }
 
-hipError_t launch_features(hipStream_t s, int W, int B, int r, const double* c, const float* mu, const float* isd,
-                           float* x) {
-    hipLaunchKernelGGL(k_features, dim3(blocks((long long)B * W * r, 256)), dim3(256), 0, s, W, B, r, c, mu, isd, x);
+hipError_t launch_features(hipStream_t s, int W, int B, int r, const double* c, const double* cb, const float* mu,
+                           const float* isd, float* x) {
+    const long long n = (long long)B * (W + (cb ? 1 : 0)) * r;
+    hipLaunchKernelGGL(k_features, dim3(blocks(n, 256)), dim3(256), 0, s, W, B, r, c, cb, mu, isd, x);
     return hipGetLastError();
 }
 
@@ -371,8 +382,9 @@ hipError_t launch_prediction(hipStream_t s, int B, int r, const float* y, const 
     return hipGetLastError();
 }
 
-hipError_t launch_targets(hipStream_t s, int W, int B, int r, const double* c, const double* ct, float* t) {
-    hipLaunchKernelGGL(k_targets, dim3(blocks((long long)B * r, 256)), dim3(256), 0, s, W, B, r, c, ct, t);
+hipError_t launch_targets(hipStream_t s, int W, int B, int r, const double* c, const double* cb, const double* ct,
+                          float* t) {
+    hipLaunchKernelGGL(k_targets, dim3(blocks((long long)B * r, 256)), dim3(256), 0, s, W, B, r, c, cb, ct, t);
     return hipGetLastError();
 }
 

@@ -44,12 +44,13 @@ hipError_t launch_adam(hipStream_t s, long long n, const float* g, float* m, flo
 // FP64 GEMM with split K: C = op(A) op(B) (+ epilogue), M x N, row stride ldc.
 // Ashift (length K, or NULL) is subtracted from every row of op(A) along k
 // (op(A)(m, k) - Ashift[k]); Cadd (length N, or NULL) is added to every row
-// of the result; accumulate adds the result to C's previous contents.  part:
-// scratch of splits * M * N doubles (unused, may be NULL, when K fits one
-// split).
+// of the result; the product is scaled by alpha and, with accumulate, added
+// to C's previous contents.  part: scratch of splits * M * N doubles (unused,
+// may be NULL, when K fits one split).
 hipError_t launch_gemm_f64(hipStream_t s, int M, int N, long long K, const double* A, long long lda, bool TA,
                            const double* B, long long ldb, bool TB, const double* Ashift, const double* Cadd,
-                           double* C, long long ldc, int splits, double* part, bool accumulate = false);
+                           double* C, long long ldc, int splits, double* part, bool accumulate = false,
+                           double alpha = 1.0);
 
 // mean[k] = (1/S) sum_s X[s][k] (X is S x n, FP64).
 hipError_t launch_rowmean(hipStream_t s, int S, long long n, const double* X, double* mean);
@@ -62,10 +63,12 @@ hipError_t launch_center(hipStream_t s, int S, long long n, const double* X, con
 hipError_t launch_colstats(hipStream_t s, int B, int n, const float* F, float floor_, float* mu, float* isd);
 
 // Features of the learned extrapolator from POD coefficients c (rows: guess
-// b, window position w < W, r coefficients; double, [W][B][r]):
-//   x[b][w r + i] = ((c[w][b][i] - c[W-1][b][i]) for w < W-1, c[W-1][b][i] for
-//   w = W-1, then normalised (x - mu) * isd (raw if mu is NULL), as FP32.
-hipError_t launch_features(hipStream_t s, int W, int B, int r, const double* c, const float* mu,
+// b, window position w < W, r coefficients; double, [W][B][r]) and, if cb is
+// non-NULL, the coefficients cb ([B][r]) of a base candidate:
+//   x[b][w r + i] = c[w][b][i] - c[W-1][b][i] for w < W-1, c[W-1][b][i] for
+//   w = W-1, cb[b][i] - c[W-1][b][i] for w = W (with cb), then normalised
+//   (x - mu) * isd (raw if mu is NULL), as FP32; (W + [cb]) r per row.
+hipError_t launch_features(hipStream_t s, int W, int B, int r, const double* c, const double* cb, const float* mu,
                            const float* isd, float* x);
 
 // Prediction: the step from the last snapshot to the limit in POD
@@ -73,8 +76,9 @@ hipError_t launch_features(hipStream_t s, int W, int B, int r, const double* c, 
 hipError_t launch_prediction(hipStream_t s, int B, int r, const float* y, const float* omu, const float* oisd,
                              double* dc);
 
-// Raw training targets t[b][i] = ct[b][i] - c[W-1][b][i] (FP32).
-hipError_t launch_targets(hipStream_t s, int W, int B, int r, const double* c, const double* ct, float* t);
+// Raw training targets t[b][i] = ct[b][i] - (cb ? cb[b][i] : c[W-1][b][i]) (FP32).
+hipError_t launch_targets(hipStream_t s, int W, int B, int r, const double* c, const double* cb, const double* ct,
+                          float* t);
 // F[b][j] = (F[b][j] - mu[j]) * isd[j] (B x n, FP32, in place).
 hipError_t launch_normalize(hipStream_t s, int B, int n, float* F, const float* mu, const float* isd);
 // dst[i][j] = src[idx[i]][j] (rows x n, FP32).

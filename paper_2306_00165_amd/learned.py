@@ -74,23 +74,48 @@ def training_set(ctx, seeds, energy, envelope_guess, dtau, warm, window, stride,
     return torch.cat(allw, dim=1).contiguous(), torch.cat(allt, dim=0).contiguous()
 
 
+def dmd_bases(ctx, windows, dtau_snap):
+    """DMD candidates of every window ([M][Nw][n], ctx.batch windows at a
+    time; a short last chunk is padded) as state vectors [Nw][n]."""
+    M, Nw, n = windows.shape
+    B = ctx.batch
+    out = []
+    for i in range(0, Nw, B):
+        chunk = windows[:, i:i + B]
+        k = chunk.shape[1]
+        if k < B:
+            chunk = torch.cat([chunk, chunk[:, :1].expand(M, B - k, n)], dim=1)
+        u, _, _ = ctx.dmd_extrapolate(chunk.contiguous(), dtau_snap)
+        out.append(_pack(ctx, u)[:k])
+    return torch.cat(out, dim=0).contiguous()
+
+
 def fit(ctx, windows, targets, r, hidden=(512, 512, 512), epochs=40, batch=128, lr=1e-3, seed=0,
-        pod_rows=512, max_batch=None):
-    """Train an extrapolator for ctx from windows [W][Nw][n] and targets
-    [Nw][n].  Returns (pcfv.Learned, loss history)."""
-    W, Nw, n = windows.shape
+        pod_rows=512, max_batch=None, feat_window=8, base_dmd_dtau=None, scales=(0.1, 0.25, 0.5, 1.0)):
+    """Train an extrapolator for ctx from windows [M][Nw][n] and targets
+    [Nw][n]; its input is the last feat_window snapshots of each window.
+    base_dmd_dtau (the snapshot spacing in tau) makes it a correction to the
+    DMD candidate of the whole window.  scales: step lengths along the
+    predicted step that each proposal tries (the least true cost wins).
+    Returns (pcfv.Learned, loss history)."""
+    M, Nw, n = windows.shape
+    W = min(feat_window, M)
+    feats = windows[M - W:]
     rng = np.random.default_rng(seed)
-    pool = torch.cat([windows[-1], targets], dim=0)
+    pool = torch.cat([feats[-1], targets], dim=0)
     rows = rng.choice(pool.shape[0], size=min(pod_rows, pool.shape[0]), replace=False)
     mean, basis, _ = pcfv.pod_build(pool[torch.as_tensor(np.sort(rows), device=pool.device)].contiguous(), r)
-    c = pcfv.pod_project(windows.reshape(W * Nw, n), mean, basis).reshape(W, Nw, r)
+    c = pcfv.pod_project(feats.reshape(W * Nw, n), mean, basis).reshape(W, Nw, r)
     ct = pcfv.pod_project(targets, mean, basis)
-    X, T, stats = pcfv.learned_prepare(c, ct)
-    dims = [W * r, *hidden, r]
+    cb = None
+    if base_dmd_dtau is not None:
+        cb = pcfv.pod_project(dmd_bases(ctx, windows, base_dmd_dtau), mean, basis)
+    X, T, stats = pcfv.learned_prepare(c, ct, cb=cb)
+    dims = [X.shape[1], *hidden, r]
     mlp = pcfv.MLP(dims, max_batch=max(batch, max_batch or ctx.batch))
     mlp.set_params(he_params(dims, seed))
     hist = mlp.fit(X, T, batch=min(batch, Nw), epochs=epochs, lr=lr, seed=seed)
-    return pcfv.Learned(ctx, W, mean, basis, stats, mlp), hist
+    return pcfv.Learned(ctx, W, mean, basis, stats, mlp, use_base=cb is not None, scales=scales), hist
 
 
 def kolmogorov(dims, energy):

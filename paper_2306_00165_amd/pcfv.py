@@ -73,10 +73,10 @@ class MlpConfig(ctypes.Structure):
 
 
 class LearnedModel(ctypes.Structure):
-    _fields_ = [("window", ctypes.c_int), ("r", ctypes.c_int), ("pod_mean", ctypes.c_void_p),
+    _fields_ = [("window", ctypes.c_int), ("use_base", ctypes.c_int), ("r", ctypes.c_int), ("pod_mean", ctypes.c_void_p),
                 ("pod_basis", ctypes.c_void_p), ("in_mu", ctypes.c_void_p), ("in_isd", ctypes.c_void_p),
                 ("out_mu", ctypes.c_void_p), ("out_isd", ctypes.c_void_p), ("mlp", ctypes.c_void_p),
-                ("scratch", ctypes.c_void_p)]
+                ("n_scales", ctypes.c_int), ("scales", ctypes.c_double * 8), ("scratch", ctypes.c_void_p)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -189,9 +189,9 @@ def load_library(path=_LIB_PATH):
     lib.pcfv_learned_scratch_bytes.restype = ctypes.c_size_t
     lib.pcfv_learned_scratch_bytes.argtypes = [vp, i, i]
     lib.pcfv_learned_propose.restype = i
-    lib.pcfv_learned_propose.argtypes = [vp, ctypes.POINTER(LearnedModel), vp, vp, dp]
+    lib.pcfv_learned_propose.argtypes = [vp, ctypes.POINTER(LearnedModel), vp, vp, vp, dp]
     lib.pcfv_learned_prepare.restype = i
-    lib.pcfv_learned_prepare.argtypes = [vp, i, i, i, vp, vp, i, vp, vp, vp, vp, vp, vp]
+    lib.pcfv_learned_prepare.argtypes = [vp, i, i, i, vp, vp, vp, i, vp, vp, vp, vp, vp, vp]
     return lib
 
 
@@ -628,20 +628,23 @@ def pod_reconstruct(coef, mean, basis):
     return X
 
 
-def learned_prepare(c, ct=None, stats=None):
+def learned_prepare(c, ct=None, stats=None, cb=None):
     """Features (and targets) of the extrapolator from POD coefficients c
-    (device [W][B][r]) and limit coefficients ct ([B][r]).  stats None: fit
-    the normalisation and return it as (in_mu, in_isd, out_mu, out_isd)."""
+    (device [W][B][r]), limit coefficients ct ([B][r]) and, for a model with a
+    base candidate, the candidates' coefficients cb ([B][r]).  stats None:
+    fit the normalisation and return it as (in_mu, in_isd, out_mu, out_isd)."""
     c = c.contiguous()
     W, B, r = c.shape
     dev = c.device
+    F = (W + (1 if cb is not None else 0)) * r
     f32 = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
     fit = stats is None
     if fit:
-        stats = (f32(W * r), f32(W * r), f32(r), f32(r))
-    X = f32(B, W * r)
+        stats = (f32(F), f32(F), f32(r), f32(r))
+    X = f32(B, F)
     T = f32(B, r) if ct is not None else None
     st = _lib.pcfv_learned_prepare(_cuda_stream_ptr(torch, dev), int(W), int(B), int(r), _ptr(c),
+                                   _ptr(cb.contiguous()) if cb is not None else None,
                                    _ptr(ct.contiguous()) if ct is not None else None, int(fit),
                                    *[_ptr(x) for x in stats], _ptr(X), _ptr(T) if T is not None else None)
     if st != OK:
@@ -652,25 +655,33 @@ def learned_prepare(c, ct=None, stats=None):
 class Learned:
     """A trained extrapolator bound to one context (its batch and grid)."""
 
-    def __init__(self, ctx, window, mean, basis, stats, mlp):
+    def __init__(self, ctx, window, mean, basis, stats, mlp, use_base=False, scales=(1.0,)):
         self.ctx, self.mlp = ctx, mlp
         self.mean, self.basis, self.stats = mean.contiguous(), basis.contiguous(), stats
         r = basis.shape[0]
         nb = _lib.pcfv_learned_scratch_bytes(ctx._h, int(window), int(r))
         self.scratch = torch.empty(nb + 256, dtype=torch.uint8, device=ctx.device)
         m = LearnedModel()
-        m.window, m.r = int(window), int(r)
+        m.window, m.r, m.use_base = int(window), int(r), int(bool(use_base))
         m.pod_mean, m.pod_basis = self.mean.data_ptr(), self.basis.data_ptr()
         m.in_mu, m.in_isd, m.out_mu, m.out_isd = [x.data_ptr() for x in stats]
         m.mlp = mlp._h.value
+        m.n_scales = len(scales)
+        for k, a in enumerate(scales):
+            m.scales[k] = float(a)
         m.scratch = self.scratch.data_ptr() + ((-self.scratch.data_ptr()) % 256)
         self.model = m
 
-    def propose(self, snaps):
-        """snaps: device float64 [W][batch][n_state]; returns (u, cost(s))."""
+    def propose(self, snaps, base=None):
+        """snaps: device float64 [W][batch][n_state]; base: [batch][n_state]
+        state vectors of the base candidates (models with a base); returns
+        (u, cost(s))."""
         c = self.ctx
         snaps = torch.as_tensor(snaps).to(c.device, torch.float64).contiguous()
+        if base is not None:
+            base = torch.as_tensor(base).to(c.device, torch.float64).contiguous()
         out = c.empty()
         cost = c._scalars(1)
-        c._check(_lib.pcfv_learned_propose(c._h, ctypes.byref(self.model), _ptr(snaps), _ptr(out), cost))
+        c._check(_lib.pcfv_learned_propose(c._h, ctypes.byref(self.model), _ptr(snaps),
+                                           _ptr(base) if base is not None else None, _ptr(out), cost))
         return out, c._unbatch(cost, 1)
