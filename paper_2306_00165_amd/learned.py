@@ -55,9 +55,11 @@ def trajectories(ctx, U, dtau, warm, window, stride, n_windows, gap, horizon, dm
     return torch.stack(wins), _pack(ctx, U)
 
 
-def training_set(ctx, seeds, energy, envelope_guess, dtau, warm, window, stride, n_windows, gap, horizon, dmd=None):
+def training_set(ctx, seeds, energy, envelope_guess, dtau, warm, window, stride, n_windows, gap, horizon, dmd=None,
+                 progress=None):
     """Windows [W][Nw][n] and targets [Nw][n] from guesses seeds (batched by
-    ctx.batch); envelope_guess(seed) returns one initial field."""
+    ctx.batch); envelope_guess(seed) returns one initial field.  progress, if
+    given, is called with a message after every batch of trajectories."""
     B = ctx.batch
     allw, allt = [], []
     for i in range(0, len(seeds), B):
@@ -71,6 +73,8 @@ def training_set(ctx, seeds, energy, envelope_guess, dtau, warm, window, stride,
         for k in range(n_windows):
             allw.append(wins[k][:, :nreal])
             allt.append(lim[:nreal])
+        if progress:
+            progress(f"trajectories {i + nreal}/{len(seeds)}")
     return torch.cat(allw, dim=1).contiguous(), torch.cat(allt, dim=0).contiguous()
 
 
@@ -121,3 +125,82 @@ def fit(ctx, windows, targets, r, hidden=(512, 512, 512), epochs=40, batch=128, 
 def kolmogorov(dims, energy):
     Nx, Ny, Nz = dims
     return lambda seed: inputs.kolmogorov_guess(Nx, Ny, Nz, energy, seed)
+
+
+def evaluate(ctx, L, windows, dtau_snap, feat_window=8):
+    """True costs on held-out windows [M][Nh][n] (ctx.batch at a time): the
+    last snapshot, the DMD candidate and the learned proposal."""
+    M, Nh, n = windows.shape
+    B = ctx.batch
+    cur, dmd, lrn = [], [], []
+    for i in range(0, Nh - B + 1, B):
+        snaps = windows[:, i:i + B].contiguous()
+        u_d, c_d, _ = ctx.dmd_extrapolate(snaps, dtau_snap)
+        _, c_l = L.propose(snaps[M - feat_window:].contiguous(), _pack(ctx, u_d) if L.model.use_base else None)
+        cur += list(np.atleast_1d(ctx.cost(ctx.unpack(snaps[-1].contiguous()))))
+        dmd += list(np.atleast_1d(c_d))
+        lrn += list(np.atleast_1d(c_l))
+    return np.array(cur), np.array(dmd), np.array(lrn)
+
+
+def main(argv=None):
+    """End-to-end run at the extrapolator's full size: seeded trajectories on
+    one grid, POD, training, and the held-out comparison with DMD.  Prints one
+    JSON line."""
+    import argparse
+    import json
+    import time
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--grid", type=int, nargs=3, default=[48, 49, 48])
+    ap.add_argument("--dtau", type=float, default=0.012)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--train-seeds", type=int, default=128)
+    ap.add_argument("--test-seeds", type=int, default=32)
+    ap.add_argument("--windows", type=int, default=8, help="windows per trajectory")
+    ap.add_argument("--snapshots", type=int, default=16, help="snapshots per DMD window")
+    ap.add_argument("--stride", type=int, default=40)
+    ap.add_argument("--horizon", type=int, default=10000)
+    ap.add_argument("--r", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--energy", type=float, default=0.03)
+    args = ap.parse_args(argv)
+    t0 = time.perf_counter()
+    import sys
+
+    def progress(msg):
+        print(f"[{time.perf_counter() - t0:.0f}s] {msg}", file=sys.stderr, flush=True)
+    dims = tuple(args.grid)
+    ctx = pcfv.Context(*dims, batch=args.batch)
+    gen = kolmogorov(dims, args.energy)
+    dmd = dict(dmd_window=args.snapshots, dmd_stride=args.stride, dmd_gap=4 * args.stride, dmd_accept=10.0)
+    kw = dict(dtau=args.dtau, warm=200, window=args.snapshots, stride=args.stride, n_windows=args.windows,
+              gap=2 * args.stride)
+    wins, tg = training_set(ctx, list(range(1000, 1000 + args.train_seeds)), args.energy, gen,
+                            horizon=args.horizon, dmd=dmd, progress=progress, **kw)
+    t_data = time.perf_counter() - t0
+    hw, _ = training_set(ctx, list(range(5000, 5000 + args.test_seeds)), args.energy, gen, horizon=0,
+                         progress=progress, **dict(kw, n_windows=2))
+    t1 = time.perf_counter()
+    L, hist = fit(ctx, wins, tg, r=args.r, hidden=(512, 512, 512), epochs=args.epochs, batch=128,
+                  pod_rows=512, base_dmd_dtau=args.stride * args.dtau)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t1
+    progress("trained")
+    cur, d, l = evaluate(ctx, L, hw, args.stride * args.dtau)
+    best = np.minimum(d, l)
+    out = {
+        "grid": list(dims), "batch": args.batch, "train_windows": int(wins.shape[1]),
+        "held_out_windows": int(len(d)), "pod_modes": args.r, "mlp_dims": L.mlp.dims,
+        "mlp_params": int(L.mlp.n_params), "data_seconds": round(t_data, 1), "fit_seconds": round(t_fit, 2),
+        "loss_first_last": [float(hist[0]), float(hist[-1])],
+        "learned_beats_dmd": int(np.sum(l < d)),
+        "median_cost_ratio_learned_over_dmd": float(np.median(l / d)),
+        "median_cost_ratio_chosen_over_dmd": float(np.median(best / d)),
+        "mean_cost_ratio_chosen_over_dmd": float(np.mean(best / d)),
+        "median_cost_ratio_dmd_over_current": float(np.median(d / cur)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
