@@ -57,9 +57,12 @@ def kernel_model(Nx, Ny, Nz):
 
 
 def kernel_source_hash():
+    """Hash of the sources that decide what the hot-path kernels do and how
+    they are launched (a counter summary is valid only for these)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2306_00165_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("kernels.hip", "kernels.hpp", "capi.cpp"):
+        with open(os.path.join(ROOT, "paper_2306_00165_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -251,8 +251,8 @@ pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* 
 const char* pcfv_last_error(const pcfv_ctx* ctx);
 
 /* Autotuner over the launch shapes: for every candidate x-slab width of the
- * physical-space kernels (divisors of Nx up to 8 that fit the LDS budget, at
- * least half the default), their work-group size (256, 512 threads) and the
+ * physical-space kernels (divisors of Nx up to 16 whose staging fits the
+ * 160 KiB of LDS a work group may use, at least half the default), their work-group size (256, 512 threads) and the
  * per-mode kernels' work-group size (256 threads with 4 lanes per contraction
  * row, 512 with 8) it times
  * `steps` descent steps (after one untimed step) on a scratch copy of u with
@@ -269,8 +269,9 @@ pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_e
                           int* n_entries);
 /* The launch shape in use (x-slab width, physical-space and per-mode work-group
  * sizes; any pointer may be NULL).  Without pcfv_autotune: the widest slab
- * that fits, 512-thread physical-space groups, and 512-thread per-mode groups
- * when the context holds at most 1024 modes over all guesses (256 above). */
+ * that fits, up to 12 (8 when the context holds more than 1024 modes over all
+ * guesses), 512-thread physical-space groups, and 512-thread per-mode groups
+ * when the context holds at most 1024 modes (256 above). */
 pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads, int* mode_threads);
 
 /* Groups (batching over uneven grids): n contexts, each with its own grid,

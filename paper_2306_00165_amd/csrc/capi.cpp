@@ -34,7 +34,7 @@ struct WsLayout {
 };
 
 constexpr size_t kAlign = 256;
-constexpr size_t kMaxPlaneLds = 64 * 1024;
+constexpr size_t kMaxPlaneLds = 160 * 1024;   // the LDS a gfx950 work group may allocate
 constexpr int kMaxDmd = 256;   // largest DMD window
 
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -80,10 +80,12 @@ KP base_kp(const pcfv_config& c) {
     p.nm = p.nkx * p.nkz;
     p.B = c.batch > 0 ? c.batch : 1;
     p.nmB = p.B * p.nm;
-    // widest x slab (a divisor of Nx, at most 8) whose physical-space kernels
-    // fit in 64 KiB of LDS
+    // widest x slab (a divisor of Nx) whose physical-space kernels fit the LDS
+    // budget, at most 12 when a launch holds few modes (fewer slabs, less
+    // partial traffic for the latency-bound case) and at most 8 otherwise
     p.XS = 1;
-    for (int xs = 8; xs >= 1; --xs) {
+    const int xs_max = (p.nmB <= 1024) ? 12 : 8;
+    for (int xs = xs_max; xs >= 1; --xs) {
         if (c.Nx % xs) continue;
         p.XS = xs;
         if (plane_lds_bytes(p, PLANE_ADJ) <= kMaxPlaneLds && plane_lds_bytes(p, PLANE_JVP) <= kMaxPlaneLds)
@@ -97,7 +99,7 @@ KP base_kp(const pcfv_config& c) {
     return p;
 }
 
-// x-slab widths the autotuner may choose: divisors of Nx up to 8 whose
+// x-slab widths the autotuner may choose: divisors of Nx up to 16 whose
 // physical-space kernels fit the LDS budget, no narrower than half the
 // default (so the partial buffers are at most twice the default's).
 std::vector<int> xs_candidates(const pcfv_config& c) {
@@ -105,7 +107,7 @@ std::vector<int> xs_candidates(const pcfv_config& c) {
     p.prec = PREC_FP64;
     const int xs0 = p.XS;
     std::vector<int> out;
-    for (int xs = 8; xs >= 1; --xs) {
+    for (int xs = 16; xs >= 1; --xs) {
         if (c.Nx % xs || 2 * xs < xs0) continue;
         p.XS = xs;
         if (plane_lds_bytes(p, PLANE_ADJ) <= kMaxPlaneLds && plane_lds_bytes(p, PLANE_JVP) <= kMaxPlaneLds)

@@ -17,6 +17,7 @@
 //   k_mode_grad     per mode: g = J* r = lam [M'* a + nu L* a] (Sec. 3.3 in
 //                   discrete form), f = -P g (Sec. 3.4), u += dtau f (step (5)),
 //                   and the y-values of the new u for the next step.
+#include <algorithm>
 #include <cstdio>
 
 #include "kernels.hpp"
@@ -544,6 +545,21 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     R* pb = reinterpret_cast<R*>(xb + NXF * per);
     for (int i = tid; i < Nx; i += PLANE_THREADS) twx[i] = narrow<CR>(p.twx[i]);
     for (int i = tid; i < Nz; i += PLANE_THREADS) twz[i] = narrow<CR>(p.twz[i]);
+    // The plane's y-values are staged in LDS with one coalesced pass (they are
+    // read nkx times each by the inverse x transform); the staging area is the
+    // products buffer, which is not live yet.  Staged fields: V and W of each
+    // velocity group (2 g, 2 g + 1), then the adjoint fields.
+    constexpr bool STAGE = (MODE != PLANE_JVP);
+    constexpr int NSF = 2 * NG3 + NG1;
+    CR* st = reinterpret_cast<CR*>(pb);
+    if constexpr (STAGE) {
+        for (int e = tid; e < NSF * nm; e += PLANE_THREADS) {
+            const int f = e / nm, m = e - f * nm;
+            const CR* src = (f < 2 * NG3) ? Y1 : Y2;
+            const int comp = (f < 2 * NG3) ? ((f & 1) ? 3 + (f >> 1) : (f >> 1)) : f - 2 * NG3;
+            st[e] = src[((size_t)comp * N + j) * nmB + mo + m];
+        }
+    }
     __syncthreads();
 
     // inverse transform in x for the slab's x positions, all retained kz
@@ -551,10 +567,17 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
         const int g = it / per, rem = it - g * per, xl = rem / nkz, kz = rem - xl * nkz;
         const int x = x0 + xl;
         if (g < NG3) {
-            const CR* src = (g < 3) ? Y1 : Y2;
-            const int comp = g % 3;
-            const CR* Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
-            const CR* Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
+            const CR* Vp;
+            const CR* Wp;
+            if constexpr (STAGE) {
+                Vp = st + (2 * g) * nm + kz;
+                Wp = st + (2 * g + 1) * nm + kz;
+            } else {
+                const CR* src = (g < 3) ? Y1 : Y2;
+                const int comp = g % 3;
+                Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
+                Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
+            }
             CR aV = mkc(zero, zero), aA = mkc(zero, zero), aW = mkc(zero, zero);
             const int step = x % Nx;
             int idx = 0;                                   // (kx * x) mod Nx, kx = 0, 1, ..
@@ -574,7 +597,11 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             xb[(3 * g + 2) * per + rem] = aW;
         } else {
             const int comp = g - NG3;
-            const CR* Ap = Y2 + ((size_t)comp * N + j) * nmB + mo + kz;
+            const CR* Ap;
+            if constexpr (STAGE)
+                Ap = st + (2 * NG3 + comp) * nm + kz;
+            else
+                Ap = Y2 + ((size_t)comp * N + j) * nmB + mo + kz;
             CR acc = mkc(zero, zero);
             const int step = x % Nx;
             int idx = 0;
@@ -1364,7 +1391,9 @@ size_t plane_lds_bytes(const KP& p, int mode) {
     const int ng3 = (mode == PLANE_JVP) ? 6 : 3, ng1 = (mode == PLANE_ADJ) ? 3 : 0;
     const int npf = (mode == PLANE_ADJ) ? 12 : 3;
     const size_t nxf = 3 * ng3 + ng1, r = p.prec == PREC_FP32 ? 4 : 8;
-    return (size_t)(p.Nx + p.Nz) * 2 * r + nxf * p.XS * p.nkz * 2 * r + (size_t)npf * p.XS * p.Nz * r;
+    const size_t products = (size_t)npf * p.XS * p.Nz * r;
+    const size_t staged = (mode == PLANE_JVP) ? 0 : (size_t)(2 * ng3 + ng1) * p.nm * 2 * r;   // aliases products
+    return (size_t)(p.Nx + p.Nz) * 2 * r + nxf * p.XS * p.nkz * 2 * r + std::max(products, staged);
 }
 
 size_t mode_lds_bytes(const KP& p) {
