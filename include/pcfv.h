@@ -281,8 +281,9 @@ pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads, in
  * all members, so small members share the chip instead of running one after
  * another.  The group owns a stream and n + 1 small device records; the
  * members (and their workspaces) must outlive it.  The physical-space work
- * group size is members[0]'s; the per-mode one follows the single-context
- * default rule applied to the modes of all members together. */
+ * group size is members[0]'s; the per-mode one, the slab width and the LDS
+ * staging follow the single-context default rules applied to the modes of all
+ * members together. */
 typedef struct pcfv_group pcfv_group;
 pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out);
 void pcfv_group_destroy(pcfv_group* group);

@@ -83,6 +83,7 @@ KP base_kp(const pcfv_config& c) {
     // widest x slab (a divisor of Nx) whose physical-space kernels fit the LDS
     // budget, at most 12 when a launch holds few modes (fewer slabs, less
     // partial traffic for the latency-bound case) and at most 8 otherwise
+    p.stage = (p.nmB <= 1024) ? 1 : 0;
     p.XS = 1;
     const int xs_max = (p.nmB <= 1024) ? 12 : 8;
     for (int xs = xs_max; xs >= 1; --xs) {
@@ -96,6 +97,7 @@ KP base_kp(const pcfv_config& c) {
     p.pthreads = 512;
     // few modes per launch: latency-bound, the wider per-mode work groups win
     p.mthreads = (p.nmB <= 1024) ? 512 : 256;
+    p.stage = (p.nmB <= 1024) ? 1 : 0;   // LDS staging pays when occupancy is not the limit
     return p;
 }
 
@@ -1052,9 +1054,21 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out)
         m.kp = c->kp;
         m.kp.pthreads = gl.pthreads;
         m.kp.mthreads = gl.mthreads;
+        if (group_modes > 1024) {
+            // a throughput launch: no LDS staging, slabs of at most 8 (the
+            // single-context defaults for many modes), from the member's
+            // candidates so that its partial buffers fit
+            m.kp.stage = 0;
+            for (int xs : xs_candidates(c->cfg))   // descending
+                if (xs <= 8) {
+                    m.kp.XS = xs;
+                    m.kp.NS = c->cfg.Nx / xs;
+                    break;
+                }
+        }
         m.item0[GPH_PLANE] = (int)items[GPH_PLANE];
         m.item0[GPH_MODE] = (int)items[GPH_MODE];
-        items[GPH_PLANE] += (long long)c->kp.B * c->kp.NS * c->kp.N;
+        items[GPH_PLANE] += (long long)m.kp.B * m.kp.NS * m.kp.N;
         items[GPH_MODE] += c->kp.nmB;
         m.dtau = 0;
         m.u = nullptr;

@@ -19,6 +19,7 @@
 //                   and the y-values of the new u for the next step.
 #include <algorithm>
 #include <cstdio>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -545,14 +546,15 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     R* pb = reinterpret_cast<R*>(xb + NXF * per);
     for (int i = tid; i < Nx; i += PLANE_THREADS) twx[i] = narrow<CR>(p.twx[i]);
     for (int i = tid; i < Nz; i += PLANE_THREADS) twz[i] = narrow<CR>(p.twz[i]);
-    // The plane's y-values are staged in LDS with one coalesced pass (they are
-    // read nkx times each by the inverse x transform); the staging area is the
-    // products buffer, which is not live yet.  Staged fields: V and W of each
+    // With p.stage the plane's y-values are staged in LDS with one coalesced
+    // pass (they are read nkx times each by the inverse x transform); the
+    // staging area is the products buffer, which is not live yet.  Staging
+    // costs LDS (occupancy), so it is used for launches with few modes.  Staged fields: V and W of each
     // velocity group (2 g, 2 g + 1), then the adjoint fields.
-    constexpr bool STAGE = (MODE != PLANE_JVP);
+    const bool stage = (MODE != PLANE_JVP) && p.stage;
     constexpr int NSF = 2 * NG3 + NG1;
     CR* st = reinterpret_cast<CR*>(pb);
-    if constexpr (STAGE) {
+    if (stage) {
         for (int e = tid; e < NSF * nm; e += PLANE_THREADS) {
             const int f = e / nm, m = e - f * nm;
             const CR* src = (f < 2 * NG3) ? Y1 : Y2;
@@ -562,58 +564,67 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     }
     __syncthreads();
 
-    // inverse transform in x for the slab's x positions, all retained kz
-    for (int it = tid; it < (NG3 + NG1) * per; it += PLANE_THREADS) {
-        const int g = it / per, rem = it - g * per, xl = rem / nkz, kz = rem - xl * nkz;
-        const int x = x0 + xl;
-        if (g < NG3) {
-            const CR* Vp;
-            const CR* Wp;
-            if constexpr (STAGE) {
-                Vp = st + (2 * g) * nm + kz;
-                Wp = st + (2 * g + 1) * nm + kz;
+    // inverse transform in x for the slab's x positions, all retained kz; the
+    // y-values come from LDS (staged) or straight from global memory, as two
+    // instantiations so that each pointer has one address space
+    auto inverse_x = [&](auto staged) {
+        constexpr bool ST = decltype(staged)::value;
+        for (int it = tid; it < (NG3 + NG1) * per; it += PLANE_THREADS) {
+            const int g = it / per, rem = it - g * per, xl = rem / nkz, kz = rem - xl * nkz;
+            const int x = x0 + xl;
+            if (g < NG3) {
+                const CR* Vp;
+                const CR* Wp;
+                if constexpr (ST) {
+                    Vp = st + (2 * g) * nm + kz;
+                    Wp = st + (2 * g + 1) * nm + kz;
+                } else {
+                    const CR* src = (g < 3) ? Y1 : Y2;
+                    const int comp = g % 3;
+                    Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
+                    Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
+                }
+                CR aV = mkc(zero, zero), aA = mkc(zero, zero), aW = mkc(zero, zero);
+                const int step = x % Nx;
+                int idx = 0;                                   // (kx * x) mod Nx, kx = 0, 1, ..
+                for (int ikx = 0; ikx < nkx; ++ikx) {
+                    if (ikx == Kx + 1) idx = (Nx - (Kx * x) % Nx) % Nx;   // kx = -Kx
+                    const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
+                    const CR tw = twx[idx];
+                    const CR vt = cmul(Vp[(size_t)ikx * nkz], tw);
+                    aV = cadd(aV, vt);
+                    aA = cadd(aA, imul(alpha * (R)kx, vt));
+                    aW = cadd(aW, cmul(Wp[(size_t)ikx * nkz], tw));
+                    idx += step;
+                    if (idx >= Nx) idx -= Nx;
+                }
+                xb[(3 * g) * per + rem] = aV;
+                xb[(3 * g + 1) * per + rem] = aA;
+                xb[(3 * g + 2) * per + rem] = aW;
             } else {
-                const CR* src = (g < 3) ? Y1 : Y2;
-                const int comp = g % 3;
-                Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
-                Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
+                const int comp = g - NG3;
+                const CR* Ap;
+                if constexpr (ST)
+                    Ap = st + (2 * NG3 + comp) * nm + kz;
+                else
+                    Ap = Y2 + ((size_t)comp * N + j) * nmB + mo + kz;
+                CR acc = mkc(zero, zero);
+                const int step = x % Nx;
+                int idx = 0;
+                for (int ikx = 0; ikx < nkx; ++ikx) {
+                    if (ikx == Kx + 1) idx = (Nx - (Kx * x) % Nx) % Nx;
+                    acc = cadd(acc, cmul(Ap[(size_t)ikx * nkz], twx[idx]));
+                    idx += step;
+                    if (idx >= Nx) idx -= Nx;
+                }
+                xb[(3 * NG3 + comp) * per + rem] = acc;
             }
-            CR aV = mkc(zero, zero), aA = mkc(zero, zero), aW = mkc(zero, zero);
-            const int step = x % Nx;
-            int idx = 0;                                   // (kx * x) mod Nx, kx = 0, 1, ..
-            for (int ikx = 0; ikx < nkx; ++ikx) {
-                if (ikx == Kx + 1) idx = (Nx - (Kx * x) % Nx) % Nx;   // kx = -Kx
-                const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
-                const CR tw = twx[idx];
-                const CR vt = cmul(Vp[(size_t)ikx * nkz], tw);
-                aV = cadd(aV, vt);
-                aA = cadd(aA, imul(alpha * (R)kx, vt));
-                aW = cadd(aW, cmul(Wp[(size_t)ikx * nkz], tw));
-                idx += step;
-                if (idx >= Nx) idx -= Nx;
-            }
-            xb[(3 * g) * per + rem] = aV;
-            xb[(3 * g + 1) * per + rem] = aA;
-            xb[(3 * g + 2) * per + rem] = aW;
-        } else {
-            const int comp = g - NG3;
-            const CR* Ap;
-            if constexpr (STAGE)
-                Ap = st + (2 * NG3 + comp) * nm + kz;
-            else
-                Ap = Y2 + ((size_t)comp * N + j) * nmB + mo + kz;
-            CR acc = mkc(zero, zero);
-            const int step = x % Nx;
-            int idx = 0;
-            for (int ikx = 0; ikx < nkx; ++ikx) {
-                if (ikx == Kx + 1) idx = (Nx - (Kx * x) % Nx) % Nx;
-                acc = cadd(acc, cmul(Ap[(size_t)ikx * nkz], twx[idx]));
-                idx += step;
-                if (idx >= Nx) idx -= Nx;
-            }
-            xb[(3 * NG3 + comp) * per + rem] = acc;
         }
-    }
+    };
+    if (stage)
+        inverse_x(std::true_type{});
+    else
+        inverse_x(std::false_type{});
     __syncthreads();
 
     // inverse (complex-to-real) transform in z at each point, then the products
@@ -1392,7 +1403,7 @@ size_t plane_lds_bytes(const KP& p, int mode) {
     const int npf = (mode == PLANE_ADJ) ? 12 : 3;
     const size_t nxf = 3 * ng3 + ng1, r = p.prec == PREC_FP32 ? 4 : 8;
     const size_t products = (size_t)npf * p.XS * p.Nz * r;
-    const size_t staged = (mode == PLANE_JVP) ? 0 : (size_t)(2 * ng3 + ng1) * p.nm * 2 * r;   // aliases products
+    const size_t staged = (mode == PLANE_JVP || !p.stage) ? 0 : (size_t)(2 * ng3 + ng1) * p.nm * 2 * r;   // aliases products
     return (size_t)(p.Nx + p.Nz) * 2 * r + nxf * p.XS * p.nkz * 2 * r + std::max(products, staged);
 }
 

@@ -15,6 +15,7 @@ struct KP {
     int prec;                // PREC_FP64, or PREC_FP32 for the physical-space transforms and products
     int pthreads;            // threads per work group of the physical-space kernels (256 or 512)
     int mthreads;            // threads per work group of the per-mode kernels (256 or 512)
+    int stage;               // physical-space kernels stage the plane's y-values in LDS (0/1)
     double lam, nu, alpha, beta;
     const double* M;         // M_COUNT fixed matrices, N x N slots, transposed
     const double* minfo;     // per-mode scalars (MI_STRIDE each)
