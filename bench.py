@@ -128,9 +128,11 @@ def run_copy_calibration():
 
 def extra_legs(torch, inputs, steps):
     """Context figures beside the FP64 metric: the same workload with FP32
-    transforms and products (FP64 solves), and a group of 64 guesses on
-    uneven grids (32 at 32x33x32, 32 at 48x49x48, Re ~ U[350, 450], energy
-    ~ U[0.01, 0.05]) advanced by one launch per stage."""
+    transforms and products (FP64 solves), a group of 64 guesses on uneven
+    grids (32 at 32x33x32, 32 at 48x49x48, Re ~ U[350, 450], energy
+    ~ U[0.01, 0.05]) advanced by one launch per stage, and the largest
+    single-GPU instance (96x65x96, wide box, 8 guesses) with its algorithmic
+    HBM bytes per second."""
     import numpy as np
     from paper_2306_00165_amd.pcfv import Context, Group, MIXED
     out = {}
@@ -170,6 +172,26 @@ def extra_legs(torch, inputs, steps):
                                                "one launch per stage", "unit": "guess-steps/s"})
         out["group64"][name] = round(64 * k / dt, 1)
         del grp, ctxs, fields
+    # the largest single-GPU instance: 96 x 65 x 96 in the wide box, 8 guesses
+    Lx, Lz = 4 * np.pi, 2 * np.pi
+    wide = {"workload": "96x65x96, Lx=4pi, Lz=2pi, batch 8, k^-5/3 guesses E=0.03", "unit": "guess-steps/s"}
+    model = kernel_model(96, 65, 96)
+    step_bytes = 8 * sum(model[k][1] for k in ("plane_fwd", "mode_res", "plane_adj", "mode_grad"))
+    for prec, name in [(0, "f64"), (MIXED, "mixed")]:
+        c = Context(96, 65, 96, Lx=Lx, Lz=Lz, batch=8, precision=prec)
+        U = torch.as_tensor(np.stack([inputs.kolmogorov_guess(96, 65, 96, 0.03, 200 + b, Lx=Lx, Lz=Lz)
+                                      for b in range(8)])).to("cuda:0").contiguous()
+        c.descend(U, max_steps=10, dtau=0.01)
+        torch.cuda.synchronize()
+        k = 100
+        t0 = time.perf_counter()
+        c.descend(U, max_steps=k, dtau=0.01, check_every=k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        wide[name] = round(8 * k / dt, 1)
+        wide[name + "_algorithmic_GBps"] = round(step_bytes * k / dt / 1e9, 1)
+        del c, U
+    out["wide96"] = wide
     return out
 
 
