@@ -80,12 +80,15 @@ KP base_kp(const pcfv_config& c) {
     p.nm = p.nkx * p.nkz;
     p.B = c.batch > 0 ? c.batch : 1;
     p.nmB = p.B * p.nm;
+    p.np = padded_ny(p.N);
     // widest x slab (a divisor of Nx) whose physical-space kernels fit the LDS
-    // budget, at most 12 when a launch holds few modes (fewer slabs, less
-    // partial traffic for the latency-bound case) and at most 8 otherwise
-    p.stage = (p.nmB <= 1024) ? 1 : 0;
+    // budget, at most 12 when a launch holds few modes (the latency-bound
+    // case: more work groups) and at most 16 otherwise (fewer slabs, less
+    // partial traffic); the 1024-thread physical-space groups of both cases
+    // waste the fewest partial passes over the slab's work items
+    p.stage = (p.nmB <= 1024) ? 1 : 0;   // LDS staging pays when occupancy is not the limit
     p.XS = 1;
-    const int xs_max = (p.nmB <= 1024) ? 12 : 8;
+    const int xs_max = (p.nmB <= 1024) ? 12 : 16;
     for (int xs = xs_max; xs >= 1; --xs) {
         if (c.Nx % xs) continue;
         p.XS = xs;
@@ -94,11 +97,22 @@ KP base_kp(const pcfv_config& c) {
     }
     p.NS = c.Nx / p.XS;
     p.prec = c.precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
-    p.pthreads = 512;
-    // few modes per launch: latency-bound, the wider per-mode work groups win
-    p.mthreads = (p.nmB <= 1024) ? 512 : 256;
-    p.stage = (p.nmB <= 1024) ? 1 : 0;   // LDS staging pays when occupancy is not the limit
+    p.pthreads = 1024;
+    // per-mode groups of 256 threads (4 lanes per contraction row): their
+    // contractions have no idle waves for Ny up to 64 and several groups share a CU
+    p.mthreads = 256;
     return p;
+}
+
+// The fixed matrices as the per-mode kernels read them: every N x N slot
+// zero-padded to np rows of mat_ld(np) entries, same transposed layout.
+std::vector<double> padded_mats(const std::vector<double>& mats, int N, int np) {
+    const int ld = mat_ld(np);
+    std::vector<double> out((size_t)M_COUNT * np * ld, 0.0);
+    for (int id = 0; id < M_COUNT; ++id)
+        for (int k = 0; k < N; ++k)
+            std::copy_n(mats.data() + ((size_t)id * N + k) * N, N, out.data() + ((size_t)id * np + k) * ld);
+    return out;
 }
 
 // x-slab widths the autotuner may choose: divisors of Nx up to 16 whose
@@ -125,7 +139,7 @@ WsLayout layout(const pcfv_config& c) {
     const size_t N = p.N, nm = p.nm, NS = c.Nx / *std::min_element(xsc.begin(), xsc.end()), nmB = p.nmB,
                  B = p.B;
     size_t sz[W_COUNT];
-    sz[W_MATS] = (size_t)M_COUNT * N * N * 8;
+    sz[W_MATS] = (size_t)M_COUNT * p.np * mat_ld(p.np) * 8;
     sz[W_MINFO] = nm * MI_STRIDE * 8;
     sz[W_DH] = sz[W_DP] = sz[W_DPROJ] = nm * N * 8;
     sz[W_VK] = sz[W_DVK] = nm * 4 * N * 8;
@@ -487,12 +501,13 @@ pcfv_status pcfv_create(const pcfv_config* cfg, void* hip_stream, void* workspac
     ctx->dmdG = ctx->at<double>(W_DMDG);
     ctx->dmdC = ctx->at<double>(W_DMDC);
     ctx->dmdPsi = ctx->at<double>(W_DMDPSI);
+    const std::vector<double> pm = padded_mats(t.mats, p.N, p.np);
     struct Up {
         int slot;
         const void* src;
         size_t bytes;
     } ups[] = {
-        {W_MATS, t.mats.data(), t.mats.size() * 8},   {W_MINFO, t.minfo.data(), t.minfo.size() * 8},
+        {W_MATS, pm.data(), pm.size() * 8},           {W_MINFO, t.minfo.data(), t.minfo.size() * 8},
         {W_DH, t.dH.data(), t.dH.size() * 8},         {W_DP, t.dP.data(), t.dP.size() * 8},
         {W_DPROJ, t.dproj.data(), t.dproj.size() * 8}, {W_VK, t.Vk.data(), t.Vk.size() * 8},
         {W_DVK, t.DVk.data(), t.DVk.size() * 8},      {W_AINV, t.Ainv.data(), t.Ainv.size() * 8},
@@ -919,8 +934,8 @@ pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_e
     KP best_kp = saved;
     pcfv_status st = PCFV_OK;
     for (int xs : xs_candidates(ctx->cfg)) {
-        for (int cand = 0; cand < 4; ++cand) {
-            const int nt = (cand & 1) ? 512 : 256, mt = (cand & 2) ? 512 : 256;
+        for (int cand = 0; cand < 8; ++cand) {
+            const int nt = 256 * (1 + (cand & 3)), mt = (cand & 4) ? 512 : 256;
             ctx->kp.XS = xs;
             ctx->kp.NS = ctx->cfg.Nx / xs;
             ctx->kp.pthreads = nt;
@@ -956,6 +971,21 @@ pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_e
     return PCFV_OK;
 }
 
+pcfv_status pcfv_set_tuning(pcfv_ctx* ctx, int xs, int plane_threads, int mode_threads) {
+    if (!ctx) return PCFV_EINVAL;
+    const std::vector<int> xsc = xs_candidates(ctx->cfg);
+    if (std::find(xsc.begin(), xsc.end(), xs) == xsc.end())
+        return fail(ctx, PCFV_EINVAL, "slab width is not one of the candidates");
+    if (plane_threads != 256 && plane_threads != 512 && plane_threads != 768 && plane_threads != 1024)
+        return fail(ctx, PCFV_EINVAL, "plane_threads must be 256, 512, 768 or 1024");
+    if (mode_threads != 256 && mode_threads != 512) return fail(ctx, PCFV_EINVAL, "mode_threads must be 256 or 512");
+    ctx->kp.XS = xs;
+    ctx->kp.NS = ctx->cfg.Nx / xs;
+    ctx->kp.pthreads = plane_threads;
+    ctx->kp.mthreads = mode_threads;
+    return PCFV_OK;
+}
+
 pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads, int* mode_threads) {
     if (!ctx) return PCFV_EINVAL;
     if (xs) *xs = ctx->kp.XS;
@@ -976,6 +1006,7 @@ struct pcfv_group {
     hipStream_t stream = nullptr;
     int graph_steps = 0;             // steps captured in `exec` (0: none)
     hipGraphExec_t exec = nullptr;
+    std::vector<double*> mats;       // members' fixed matrices re-padded to the group's np
     std::string err;
 };
 
@@ -1046,7 +1077,8 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out)
     gl.pthreads = members[0]->kp.pthreads;
     long long group_modes = 0;
     for (int k = 0; k < n; ++k) group_modes += members[k]->kp.nmB;
-    gl.mthreads = (group_modes <= 1024) ? 512 : 256;   // the single-context rule, over the whole group
+    gl.mthreads = members[0]->kp.mthreads;
+    for (int k = 0; k < n; ++k) gl.np = std::max(gl.np, members[k]->kp.np);
     long long items[2] = {0, 0};
     for (int k = 0; k < n; ++k) {
         pcfv_ctx* c = members[k];
@@ -1054,17 +1086,27 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out)
         m.kp = c->kp;
         m.kp.pthreads = gl.pthreads;
         m.kp.mthreads = gl.mthreads;
+        if (c->kp.np != gl.np) {   // the per-mode kernels read the tables at the group's stride
+            const std::vector<double> pm = padded_mats(c->t.mats, c->kp.N, gl.np);
+            double* d = nullptr;
+            hipError_t he = hipMalloc(&d, pm.size() * 8);
+            if (he == hipSuccess) g->mats.push_back(d);
+            if (he == hipSuccess) he = hipMemcpy(d, pm.data(), pm.size() * 8, hipMemcpyHostToDevice);
+            if (he != hipSuccess) {
+                g_create_err = std::string("group setup: ") + hipGetErrorString(he);
+                pcfv_group_destroy(g);
+                return PCFV_EDEVICE;
+            }
+            m.kp.M = d;
+        }
+        m.kp.np = gl.np;
         if (group_modes > 1024) {
-            // a throughput launch: no LDS staging, slabs of at most 8 (the
-            // single-context defaults for many modes), from the member's
-            // candidates so that its partial buffers fit
+            // a throughput launch: no LDS staging and the widest slab of the
+            // member's candidates (the single-context defaults for many modes;
+            // every candidate's partial buffers fit)
             m.kp.stage = 0;
-            for (int xs : xs_candidates(c->cfg))   // descending
-                if (xs <= 8) {
-                    m.kp.XS = xs;
-                    m.kp.NS = c->cfg.Nx / xs;
-                    break;
-                }
+            m.kp.XS = xs_candidates(c->cfg).front();   // descending
+            m.kp.NS = c->cfg.Nx / m.kp.XS;
         }
         m.item0[GPH_PLANE] = (int)items[GPH_PLANE];
         m.item0[GPH_MODE] = (int)items[GPH_MODE];
@@ -1078,7 +1120,6 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out)
         m.Atil = c->Atil;
         m.a = c->a;
         m.part = c->part;
-        gl.np = std::max(gl.np, padded_ny(c->kp.N));
         for (int md : {PLANE_FWD, PLANE_JVP, PLANE_ADJ})
             gl.plane_lds[md] = std::max(gl.plane_lds[md], plane_lds_bytes(m.kp, md));
         gl.mode_lds = std::max(gl.mode_lds, mode_lds_bytes(m.kp));
@@ -1109,6 +1150,7 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out)
 void pcfv_group_destroy(pcfv_group* g) {
     if (!g) return;
     drop_graph(g);
+    for (double* d : g->mats) (void)hipFree(d);
     if (g->dev) (void)hipFree(g->dev);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;

@@ -104,8 +104,11 @@ __device__ __forceinline__ MS mscal(const KP& p, int m) {
     return {mi[MI_A], mi[MI_B], mi[MI_K2], mi[MI_INVK2], mi[MI_SIG], mi[MI_WGT]};
 }
 
+// Fixed matrix id: an NP x mat_ld(NP) slot, transposed
+// (slot[k * mat_ld(NP) + n] = A[n][k]), zero outside the matrix.
+template <int NP>
 __device__ __forceinline__ const double* mat(const KP& p, int id) {
-    return p.M + (size_t)id * p.N * p.N;
+    return p.M + (size_t)id * NP * mat_ld(NP);
 }
 
 // Block reduction of NV values per thread (deterministic order): every thread
@@ -150,80 +153,132 @@ __device__ void bmax(double (&v)[NV], double* red) {
     __syncthreads();
 }
 
-// y = A x for one complex vector; A (nout x nin) stored transposed (slot[k*N+n]).
-// Each output row is computed by MC<MT>::KS lanes of one wave, each summing every
-// MC<MT>::KS-th term, then combined with cross-lane shuffles; rows are dealt out
-// in groups of 16 per wave.  x and y live in LDS and must not alias.  Caller
-// synchronises afterwards.
+// Sums over the lanes that share one output row of a contraction: lanes
+// MC<MT>::ROWS apart within the wave (8, 16, 32 apart for ROWS = 8; 16, 32 for
+// ROWS = 16).  The exchanges run on the VALU: a DPP rotation by 8 within each
+// 16-lane row and the gfx950 permlane16/permlane32 swaps, which exchange the
+// odd and even 16-lane rows and the two 32-lane halves.  Every lane of a row
+// group receives the same bits (the partners add the same two numbers).
+__device__ __forceinline__ double ror8_add(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x128, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x128, 0xf, 0xf, false);
+    return v + __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double swap16_add(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ __forceinline__ double swap32_add(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+template <int MT> __device__ __forceinline__ double row_sum(double v) {
+    static_assert(MC<MT>::ROWS == 8 || MC<MT>::ROWS == 16, "row groups of 8 or 16 lanes");
+    if constexpr (MC<MT>::ROWS == 8) v = ror8_add(v);
+    v = swap16_add(v);
+    return swap32_add(v);
+}
+
+// Raw buffer view of the fixed-matrix block: every matrix element is fetched
+// with one buffer load whose per-lane offset is fixed for the whole kernel
+// and whose matrix and step offsets are wave-uniform (scalar operand), so a
+// contraction issues no address arithmetic.  Offsets past the block read 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mat_rsrc(const KP& p, int NP) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p.M), 0, M_COUNT * NP * mat_ld(NP) * 8, 0x00020000);
+}
+__device__ __forceinline__ double mat_load(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+    return __hiloint2double((int)v[1], (int)v[0]);
+}
+
+// y = A x for one complex vector, A = fixed matrix id (nout x nin, zero-padded
+// to NP x NP).  Each output row is computed by MC<MT>::KS lanes of one wave,
+// each summing every MC<MT>::KS-th term over the padded length NP, then
+// combined across lanes; rows are dealt out MC<MT>::ROWS per wave.  The
+// padding terms multiply exact zeros of A by finite entries of x (the LDS
+// vectors start zeroed), so no step is predicated and every matrix load of the
+// contraction is in flight at once.  x and y live in LDS and must not alias;
+// entries [nout, NP) of y are left untouched.  Caller synchronises afterwards.
 template <int NP, int MT>
-__device__ void mv(const KP& p, int id, int nin, int nout, const double2* x, double2* y) {
-    const double* __restrict__ A = mat(p, id);
-    const int N = p.N, lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    const int r = lane % MC<MT>::ROWS, q = lane / MC<MT>::ROWS;
+__device__ void mv(const KP& p, int id, int nout, const double2* x, double2* y) {
+    typedef MC<MT> S;
+    const __amdgpu_buffer_rsrc_t rs = mat_rsrc(p, NP);
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int r = lane % S::ROWS, q = lane / S::ROWS;
 #pragma unroll
-    for (int n0 = 0; n0 < NP; n0 += MC<MT>::WAVES * MC<MT>::ROWS) {
-        const int n = n0 + wave * MC<MT>::ROWS + r;
+    for (int n0 = 0; n0 < NP; n0 += S::WAVES * S::ROWS) {
+        if (n0 + wave * S::ROWS >= nout) break;   // wave-uniform: no rows of this wave are left
+        const int n = n0 + wave * S::ROWS + r;
+        constexpr int LD = mat_ld(NP);
+        const int voff = (q * LD + min(n, NP - 1)) * 8;
+        double a[NP / S::KS];
+#pragma unroll
+        for (int i = 0; i < NP / S::KS; ++i) a[i] = mat_load(rs, voff, (id * NP + S::KS * i) * LD * 8);
         double re = 0.0, im = 0.0;
-        if (n < nout) {
 #pragma unroll
-            for (int i = 0; i < NP / MC<MT>::KS; ++i) {   // fully unrolled: all loads in flight
-                const int k = q + MC<MT>::KS * i;
-                if (k < nin) {
-                    const double a = A[k * N + n];
-                    const double2 v = x[k];
-                    re = fma(a, v.x, re);
-                    im = fma(a, v.y, im);
-                }
-            }
+        for (int i = 0; i < NP / S::KS; ++i) {
+            const double2 v = x[q + S::KS * i];
+            re = fma(a[i], v.x, re);
+            im = fma(a[i], v.y, im);
         }
-#pragma unroll
-        for (int o = MC<MT>::ROWS; o < WAVE; o <<= 1) {   // lanes of one row are MC<MT>::ROWS apart
-            re += __shfl_xor(re, o, WAVE);
-            im += __shfl_xor(im, o, WAVE);
-        }
+        re = row_sum<MT>(re);
+        im = row_sum<MT>(im);
         if (q == 0 && n < nout) y[n] = c2(re, im);
     }
 }
 
 // The same matrix applied to three vectors.
 template <int NP, int MT>
-__device__ void mv3(const KP& p, int id, int nin, int nout, const double2* x0,
-                    const double2* x1, const double2* x2, double2* y0, double2* y1,
-                    double2* y2) {
-    const double* __restrict__ A = mat(p, id);
-    const int N = p.N, lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    const int r = lane % MC<MT>::ROWS, q = lane / MC<MT>::ROWS;
+__device__ void mv3(const KP& p, int id, int nout, const double2* x0, const double2* x1,
+                    const double2* x2, double2* y0, double2* y1, double2* y2) {
+    typedef MC<MT> S;
+    const __amdgpu_buffer_rsrc_t rs = mat_rsrc(p, NP);
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int r = lane % S::ROWS, q = lane / S::ROWS;
 #pragma unroll
-    for (int n0 = 0; n0 < NP; n0 += MC<MT>::WAVES * MC<MT>::ROWS) {
-        const int n = n0 + wave * MC<MT>::ROWS + r;
+    for (int n0 = 0; n0 < NP; n0 += S::WAVES * S::ROWS) {
+        if (n0 + wave * S::ROWS >= nout) break;   // wave-uniform: no rows of this wave are left
+        const int n = n0 + wave * S::ROWS + r;
+        constexpr int LD = mat_ld(NP);
+        const int voff = (q * LD + min(n, NP - 1)) * 8;
+        double a[NP / S::KS];
+#pragma unroll
+        for (int i = 0; i < NP / S::KS; ++i) a[i] = mat_load(rs, voff, (id * NP + S::KS * i) * LD * 8);
         double acc[6] = {0, 0, 0, 0, 0, 0};
-        if (n < nout) {
 #pragma unroll
-            for (int i = 0; i < NP / MC<MT>::KS; ++i) {
-                const int k = q + MC<MT>::KS * i;
-                if (k < nin) {
-                    const double a = A[k * N + n];
-                    const double2 v0 = x0[k], v1 = x1[k], v2 = x2[k];
-                    acc[0] = fma(a, v0.x, acc[0]);
-                    acc[1] = fma(a, v0.y, acc[1]);
-                    acc[2] = fma(a, v1.x, acc[2]);
-                    acc[3] = fma(a, v1.y, acc[3]);
-                    acc[4] = fma(a, v2.x, acc[4]);
-                    acc[5] = fma(a, v2.y, acc[5]);
-                }
-            }
+        for (int i = 0; i < NP / S::KS; ++i) {
+            const int k = q + S::KS * i;
+            const double2 v0 = x0[k], v1 = x1[k], v2 = x2[k];
+            acc[0] = fma(a[i], v0.x, acc[0]);
+            acc[1] = fma(a[i], v0.y, acc[1]);
+            acc[2] = fma(a[i], v1.x, acc[2]);
+            acc[3] = fma(a[i], v1.y, acc[3]);
+            acc[4] = fma(a[i], v2.x, acc[4]);
+            acc[5] = fma(a[i], v2.y, acc[5]);
         }
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-#pragma unroll
-            for (int o = MC<MT>::ROWS; o < WAVE; o <<= 1) acc[i] += __shfl_xor(acc[i], o, WAVE);
-        }
+        for (int i = 0; i < 6; ++i) acc[i] = row_sum<MT>(acc[i]);
         if (q == 0 && n < nout) {
             y0[n] = c2(acc[0], acc[1]);
             y1[n] = c2(acc[2], acc[3]);
             y2[n] = c2(acc[4], acc[5]);
         }
     }
+}
+
+// LDS of the per-mode kernels: MODE_VECS complex vectors at stride NP, then
+// the block-reduction scratch.  The vectors start zeroed, so the padded tail
+// [Ny, NP) and every entry not yet written hold finite values.
+template <int NP, int MT>
+__device__ __forceinline__ double2* mode_vectors() {
+    extern __shared__ double2 sm[];
+    for (int i = threadIdx.x; i < MODE_VECS * NP; i += MT) sm[i] = c2(0.0, 0.0);
+    __syncthreads();
+    return sm;
 }
 
 // ---------------------------------------------------------------------------
@@ -252,8 +307,8 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
                        const double2* Fz, double2* ox, double2* oy, double2* oz, double2* w,
                        double* red) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
-    double2 *Fh = w, *Fe = w + N, *s1 = w + 2 * N, *s2 = w + 3 * N, *s3 = w + 4 * N,
-            *s4 = w + 5 * N, *t2 = w + 6 * N, *v0 = w + 7 * N, *Dv0 = w + 8 * N, *eta = w + 9 * N;
+    double2 *Fh = w, *Fe = w + NP, *s1 = w + 2 * NP, *s2 = w + 3 * NP, *s3 = w + 4 * NP,
+            *s4 = w + 5 * NP, *t2 = w + 6 * NP, *v0 = w + 7 * NP, *Dv0 = w + 8 * NP, *eta = w + 9 * NP;
     const double* dH = p.dH + (size_t)m * N;
     const double* dP = p.dP + (size_t)m * N;
     for (int n = t; n < N; n += MT) {
@@ -262,23 +317,23 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
         Fe[n] = csub(imul(c.b, fx), imul(c.a, fz));
     }
     __syncthreads();
-    mv3<NP, MT>(p, M_PR, M, M, Fh, Fe, Fy, s1, s2, s3);
-    mv<NP, MT>(p, M_PRD, N, M, Fy, s4);
+    mv3<NP, MT>(p, M_PR, M, Fh, Fe, Fy, s1, s2, s3);
+    mv<NP, MT>(p, M_PRD, M, Fy, s4);
     __syncthreads();
     for (int n = t; n < M; n += MT) {
         s1[n] = cscl(-dP[n], cadd(s4[n], s1[n]));   // t1
         s2[n] = cscl(dH[n], s2[n]);                 // te
     }
     __syncthreads();
-    mv<NP, MT>(p, M_PRDPL, M, M, s1, t2);
+    mv<NP, MT>(p, M_PRDPL, M, s1, t2);
     __syncthreads();
     for (int n = t; n < M; n += MT) t2[n] = cscl(dH[n], csub(s3[n], t2[n]));
     __syncthreads();
-    mv<NP, MT>(p, M_PL, M, N, t2, v0);
-    mv<NP, MT>(p, M_DPL, M, N, t2, Dv0);
-    mv<NP, MT>(p, M_PL, M, N, s2, eta);
+    mv<NP, MT>(p, M_PL, N, t2, v0);
+    mv<NP, MT>(p, M_DPL, N, t2, Dv0);
+    mv<NP, MT>(p, M_PL, N, s2, eta);
     __syncthreads();
-    const double* PLlast = mat(p, M_PL) + (N - 1);      // row N-1 of Pl: PLlast[k * N]
+    const double* PLlast = mat<NP>(p, M_PL) + (N - 1);  // row N-1 of Pl: PLlast[k * mat_ld(NP)]
     double sums[6] = {0, 0, 0, 0, 0, 0};
     for (int n = t; n < N; n += MT) {
         const double2 d = Dv0[n];
@@ -287,8 +342,8 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
         sums[2] += (n & 1) ? -d.x : d.x;
         sums[3] += (n & 1) ? -d.y : d.y;
         if (n < M) {
-            sums[4] += PLlast[(size_t)n * N] * s1[n].x;
-            sums[5] += PLlast[(size_t)n * N] * s1[n].y;
+            sums[4] += PLlast[(size_t)n * mat_ld(NP)] * s1[n].x;
+            sums[5] += PLlast[(size_t)n * mat_ld(NP)] * s1[n].y;
         }
     }
     bsum<MT>(sums, red);
@@ -329,9 +384,9 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
                          const double2* xw, double2* yx, double2* yy, double2* yz,
                          double2* w, double* red) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
-    double2 *bDv = w, *beta = w + N, *bv0 = w + 2 * N, *bDv0 = w + 3 * N, *bt2 = w + 4 * N,
-            *tmp = w + 5 * N, *bte = w + 6 * N, *bFh = w + 7 * N, *bFe = w + 8 * N,
-            *bFy = w + 9 * N, *bFy2 = w + 10 * N;
+    double2 *bDv = w, *beta = w + NP, *bv0 = w + 2 * NP, *bDv0 = w + 3 * NP, *bt2 = w + 4 * NP,
+            *tmp = w + 5 * NP, *bte = w + 6 * NP, *bFh = w + 7 * NP, *bFe = w + 8 * NP,
+            *bFy = w + 9 * NP, *bFy2 = w + 10 * NP;
     const double* dH = p.dH + (size_t)m * N;
     const double* dP = p.dP + (size_t)m * N;
     const double* Vk = p.Vk + (size_t)m * 4 * N;
@@ -366,26 +421,26 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
         bDv0[n] = cadd(bDv[n], (n & 1) ? csub(be[0], be[1]) : cadd(be[0], be[1]));
     }
     __syncthreads();
-    mv<NP, MT>(p, M_PLT, N, M, bv0, bt2);
-    mv<NP, MT>(p, M_DPLT, N, M, bDv0, tmp);
-    mv<NP, MT>(p, M_PLT, N, M, beta, bte);
+    mv<NP, MT>(p, M_PLT, M, bv0, bt2);
+    mv<NP, MT>(p, M_DPLT, M, bDv0, tmp);
+    mv<NP, MT>(p, M_PLT, M, beta, bte);
     __syncthreads();
     for (int n = t; n < M; n += MT) {
         bt2[n] = cscl(dH[n], cadd(bt2[n], tmp[n]));   // u2 = dH (PL^T bv0 + DPL^T bDv0)
         bte[n] = cscl(dH[n], bte[n]);                 // bs2
     }
     __syncthreads();
-    mv<NP, MT>(p, M_PRDPLT, M, M, bt2, tmp);
+    mv<NP, MT>(p, M_PRDPLT, M, bt2, tmp);
     __syncthreads();
     const double2 bp0last = cscl(2.0 * (N - 1), be[2]);
-    const double* PLlast = mat(p, M_PL) + (N - 1);
+    const double* PLlast = mat<NP>(p, M_PL) + (N - 1);
     for (int n = t; n < M; n += MT)   // bs1 = -dP (Pl[N-1,:] bp0last - PRDPL^T u2)
-        tmp[n] = cscl(-dP[n], csub(cscl(PLlast[(size_t)n * N], bp0last), tmp[n]));
+        tmp[n] = cscl(-dP[n], csub(cscl(PLlast[(size_t)n * mat_ld(NP)], bp0last), tmp[n]));
     __syncthreads();
-    mv<NP, MT>(p, M_PRT, M, M, tmp, bFh);
-    mv<NP, MT>(p, M_PRT, M, M, bte, bFe);
-    mv<NP, MT>(p, M_PRT, M, M, bt2, bFy);
-    mv<NP, MT>(p, M_PRDT, M, N, tmp, bFy2);
+    mv<NP, MT>(p, M_PRT, M, tmp, bFh);
+    mv<NP, MT>(p, M_PRT, M, bte, bFe);
+    mv<NP, MT>(p, M_PRT, M, bt2, bFy);
+    mv<NP, MT>(p, M_PRDT, N, tmp, bFy2);
     __syncthreads();
     for (int n = t; n < N; n += MT) {
         const double2 h = (n < M) ? bFh[n] : c2(0, 0), e = (n < M) ? bFe[n] : c2(0, 0);
@@ -403,18 +458,18 @@ template <int NP, int MT>
 __device__ void stokes0(const KP& p, const double2* Fx, const double2* Fz, double2* ox,
                         double2* oy, double2* oz, double2* w) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
-    double2 *t1 = w, *t2 = w + N;
+    double2 *t1 = w, *t2 = w + NP;
     const double* dH = p.dH;
-    mv<NP, MT>(p, M_PR, M, M, Fx, t1);
-    mv<NP, MT>(p, M_PR, M, M, Fz, t2);
+    mv<NP, MT>(p, M_PR, M, Fx, t1);
+    mv<NP, MT>(p, M_PR, M, Fz, t2);
     __syncthreads();
     for (int n = t; n < M; n += MT) {
         t1[n] = cscl(dH[n], t1[n]);
         t2[n] = cscl(dH[n], t2[n]);
     }
     __syncthreads();
-    mv<NP, MT>(p, M_PL, M, N, t1, ox);
-    mv<NP, MT>(p, M_PL, M, N, t2, oz);
+    mv<NP, MT>(p, M_PL, N, t1, ox);
+    mv<NP, MT>(p, M_PL, N, t2, oz);
     for (int n = t; n < N; n += MT) oy[n] = c2(0, 0);
     __syncthreads();
 }
@@ -423,18 +478,18 @@ template <int NP, int MT>
 __device__ void stokes0_h(const KP& p, const double2* xu, const double2* xw, double2* yx,
                           double2* yy, double2* yz, double2* w) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
-    double2 *t1 = w, *t2 = w + N;
+    double2 *t1 = w, *t2 = w + NP;
     const double* dH = p.dH;
-    mv<NP, MT>(p, M_PLT, N, M, xu, t1);
-    mv<NP, MT>(p, M_PLT, N, M, xw, t2);
+    mv<NP, MT>(p, M_PLT, M, xu, t1);
+    mv<NP, MT>(p, M_PLT, M, xw, t2);
     __syncthreads();
     for (int n = t; n < M; n += MT) {
         t1[n] = cscl(dH[n], t1[n]);
         t2[n] = cscl(dH[n], t2[n]);
     }
     __syncthreads();
-    mv<NP, MT>(p, M_PRT, M, M, t1, yx);
-    mv<NP, MT>(p, M_PRT, M, M, t2, yz);
+    mv<NP, MT>(p, M_PRT, M, t1, yx);
+    mv<NP, MT>(p, M_PRT, M, t2, yz);
     for (int n = t; n < N; n += MT) {
         yy[n] = c2(0, 0);
         if (n >= M) {
@@ -454,8 +509,8 @@ template <int NP, int MT>
 __device__ void project(const KP& p, int m, const MS& c, const double2* gx, const double2* gy,
                         const double2* gz, double2* ox, double2* oy, double2* oz, double2* w) {
     const int N = p.N, t = threadIdx.x;
-    double2 *gh = w, *ge = w + N, *t1 = w + 2 * N, *t2 = w + 3 * N, *t4 = w + 4 * N,
-            *v = w + 5 * N, *eta = w + 6 * N, *Dv = w + 7 * N;
+    double2 *gh = w, *ge = w + NP, *t1 = w + 2 * NP, *t2 = w + 3 * NP, *t4 = w + 4 * NP,
+            *v = w + 5 * NP, *eta = w + 6 * NP, *Dv = w + 7 * NP;
     const double* dq = p.dproj + (size_t)m * N;
     for (int n = t; n < N; n += MT) {
         const double2 x = gx[n], z = gz[n];
@@ -463,18 +518,18 @@ __device__ void project(const KP& p, int m, const MS& c, const double2* gx, cons
         ge[n] = csub(imul(c.b, x), imul(c.a, z));
     }
     __syncthreads();
-    mv<NP, MT>(p, M_DTG, N, N, gh, t1);
-    mv<NP, MT>(p, M_G, N, N, gy, t2);
-    mv<NP, MT>(p, M_PID, N, N, ge, eta);
+    mv<NP, MT>(p, M_DTG, N, gh, t1);
+    mv<NP, MT>(p, M_G, N, gy, t2);
+    mv<NP, MT>(p, M_PID, N, ge, eta);
     __syncthreads();
     for (int n = t; n < N; n += MT) t2[n] = csub(t2[n], cscl(c.ik2, t1[n]));
     __syncthreads();
-    mv<NP, MT>(p, M_PVLT, N, N - 4, t2, t4);
+    mv<NP, MT>(p, M_PVLT, N - 4, t2, t4);
     __syncthreads();
     for (int n = t; n < N - 4; n += MT) t4[n] = cscl(dq[n], t4[n]);
     __syncthreads();
-    mv<NP, MT>(p, M_PVL, N - 4, N, t4, v);
-    mv<NP, MT>(p, M_DPVL, N - 4, N, t4, Dv);
+    mv<NP, MT>(p, M_PVL, N, t4, v);
+    mv<NP, MT>(p, M_DPVL, N, t4, Dv);
     __syncthreads();
     for (int n = t; n < N; n += MT) {
         const double2 d = Dv[n], e = eta[n];
@@ -489,8 +544,8 @@ template <int NP, int MT>
 __device__ void project0(const KP& p, const double2* gx, const double2* gz, double2* ox,
                          double2* oy, double2* oz) {
     const int N = p.N;
-    mv<NP, MT>(p, M_PID, N, N, gx, ox);
-    mv<NP, MT>(p, M_PID, N, N, gz, oz);
+    mv<NP, MT>(p, M_PID, N, gx, ox);
+    mv<NP, MT>(p, M_PID, N, gz, oz);
     for (int n = threadIdx.x; n < N; n += MT) oy[n] = c2(0, 0);
     __syncthreads();
 }
@@ -504,21 +559,20 @@ __device__ void project0(const KP& p, const double2* gx, const double2* gz, doub
 template <int NP, int MT, class YT>
 __device__ __forceinline__ void synth_body(const KP& p, int mB, const double2* __restrict__ u,
                                            YT* __restrict__ Y) {
-    extern __shared__ double2 sm[];
     const int N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
-    double2* V = sm;
+    double2* V = mode_vectors<NP, MT>();
     for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MT) V[i * N + n] = u[so + ((size_t)i * nm + m) * N + n];
+        for (int n = t; n < N; n += MT) V[i * NP + n] = u[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
-    mv3<NP, MT>(p, M_C, N, N, V, V + N, V + 2 * N, V + 3 * N, V + 4 * N, V + 5 * N);
-    mv3<NP, MT>(p, M_CD, N, N, V, V + N, V + 2 * N, V + 6 * N, V + 7 * N, V + 8 * N);
+    mv3<NP, MT>(p, M_C, N, V, V + NP, V + 2 * NP, V + 3 * NP, V + 4 * NP, V + 5 * NP);
+    mv3<NP, MT>(p, M_CD, N, V, V + NP, V + 2 * NP, V + 6 * NP, V + 7 * NP, V + 8 * NP);
     __syncthreads();
     for (int f = 0; f < 6; ++f)
         for (int j = t; j < N; j += MT)
-            Y[((size_t)f * N + j) * nmB + mB] = narrow<YT>(V[(3 + f) * N + j]);
+            Y[((size_t)f * N + j) * nmB + mB] = narrow<YT>(V[(3 + f) * NP + j]);
 }
 
 template <int MODE, class R, int PLANE_THREADS>
@@ -539,13 +593,23 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     const int nmB = p.nmB, mo = b * nm;                // y-value arrays are [f][j][b * nm + m]
     const int Kx = p.Kx;
     const int x0 = s * XS, tid = threadIdx.x;
-    const int per = XS * nkz, pz = XS * Nz;
-    CR* twx = sm;
-    CR* twz = twx + Nx;
-    CR* xb = twz + Nz;
+    const int per = XS * nkz, pz = XS * Nz, tzs = nkz + 1;
+    // Twiddle tables: TX[xl][ikx] = exp(2 pi i kx x / Nx) for the slab's x and
+    // every retained kx, TZ[z][kz] = exp(2 pi i kz z / Nz) with rows padded to
+    // nkz + 1 entries, so that lanes running over kz (forward z transform) and
+    // lanes running over z (inverse z transform) both read distinct LDS banks.
+    CR* TX = sm;
+    CR* TZ = TX + XS * nkx;
+    CR* xb = TZ + Nz * tzs;
     R* pb = reinterpret_cast<R*>(xb + NXF * per);
-    for (int i = tid; i < Nx; i += PLANE_THREADS) twx[i] = narrow<CR>(p.twx[i]);
-    for (int i = tid; i < Nz; i += PLANE_THREADS) twz[i] = narrow<CR>(p.twz[i]);
+    for (int i = tid; i < XS * nkx; i += PLANE_THREADS) {
+        const int xl = i / nkx, ikx = i - xl * nkx, kx = (ikx <= Kx) ? ikx : ikx - nkx;
+        TX[i] = narrow<CR>(p.twx[(int)((long long)(kx + Nx) * (x0 + xl) % Nx)]);
+    }
+    for (int i = tid; i < Nz * nkz; i += PLANE_THREADS) {
+        const int z = i / nkz, kz = i - z * nkz;
+        TZ[z * tzs + kz] = narrow<CR>(p.twz[(kz * z) % Nz]);
+    }
     // With p.stage the plane's y-values are staged in LDS with one coalesced
     // pass (they are read nkx times each by the inverse x transform); the
     // staging area is the products buffer, which is not live yet.  Staging
@@ -571,7 +635,6 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
         constexpr bool ST = decltype(staged)::value;
         for (int it = tid; it < (NG3 + NG1) * per; it += PLANE_THREADS) {
             const int g = it / per, rem = it - g * per, xl = rem / nkz, kz = rem - xl * nkz;
-            const int x = x0 + xl;
             if (g < NG3) {
                 const CR* Vp;
                 const CR* Wp;
@@ -585,18 +648,14 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
                     Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
                 }
                 CR aV = mkc(zero, zero), aA = mkc(zero, zero), aW = mkc(zero, zero);
-                const int step = x % Nx;
-                int idx = 0;                                   // (kx * x) mod Nx, kx = 0, 1, ..
+                const CR* tx = TX + xl * nkx;
                 for (int ikx = 0; ikx < nkx; ++ikx) {
-                    if (ikx == Kx + 1) idx = (Nx - (Kx * x) % Nx) % Nx;   // kx = -Kx
                     const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
-                    const CR tw = twx[idx];
+                    const CR tw = tx[ikx];
                     const CR vt = cmul(Vp[(size_t)ikx * nkz], tw);
                     aV = cadd(aV, vt);
                     aA = cadd(aA, imul(alpha * (R)kx, vt));
                     aW = cadd(aW, cmul(Wp[(size_t)ikx * nkz], tw));
-                    idx += step;
-                    if (idx >= Nx) idx -= Nx;
                 }
                 xb[(3 * g) * per + rem] = aV;
                 xb[(3 * g + 1) * per + rem] = aA;
@@ -609,14 +668,8 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
                 else
                     Ap = Y2 + ((size_t)comp * N + j) * nmB + mo + kz;
                 CR acc = mkc(zero, zero);
-                const int step = x % Nx;
-                int idx = 0;
-                for (int ikx = 0; ikx < nkx; ++ikx) {
-                    if (ikx == Kx + 1) idx = (Nx - (Kx * x) % Nx) % Nx;
-                    acc = cadd(acc, cmul(Ap[(size_t)ikx * nkz], twx[idx]));
-                    idx += step;
-                    if (idx >= Nx) idx -= Nx;
-                }
+                const CR* tx = TX + xl * nkx;
+                for (int ikx = 0; ikx < nkx; ++ikx) acc = cadd(acc, cmul(Ap[(size_t)ikx * nkz], tx[ikx]));
                 xb[(3 * NG3 + comp) * per + rem] = acc;
             }
         }
@@ -638,11 +691,9 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             const CR* cA = xb + (3 * g + 1) * per + xl * nkz;
             const CR* cW = xb + (3 * g + 2) * per + xl * nkz;
             R sV = 0, sZ = 0, sA = 0, sW = 0;
-            int idx = 0;                                   // (kz * z) mod Nz
+            const CR* tz = TZ + z * tzs;
             for (int kz = 1; kz < nkz; ++kz) {
-                idx += z;
-                if (idx >= Nz) idx -= Nz;
-                const CR tw = twz[idx];
+                const CR tw = tz[kz];
                 const CR t = cmul(cV[kz], tw);
                 sV += t.x;
                 sZ += beta * (R)kz * t.y;
@@ -675,12 +726,8 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             for (int i = 0; i < 3; ++i) {
                 const CR* cc = xb + (3 * NG3 + i) * per + xl * nkz;
                 R sr = 0;
-                int idx = 0;
-                for (int kz = 1; kz < nkz; ++kz) {
-                    idx += z;
-                    if (idx >= Nz) idx -= Nz;
-                    sr += cmul(cc[kz], twz[idx]).x;
-                }
+                const CR* tz = TZ + z * tzs;
+                for (int kz = 1; kz < nkz; ++kz) sr += cmul(cc[kz], tz[kz]).x;
                 at[i] = cc[0].x + two * sr;
             }
 #pragma unroll
@@ -699,11 +746,12 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     const R invNz = (R)1 / (R)Nz, invNx = (R)1 / (R)Nx;
     for (int it = tid; it < NZF * per; it += PLANE_THREADS) {
         const int o = it / per, rem = it - o * per, xl = rem / nkz, kz = rem - xl * nkz;
+        const CR* tzk = TZ + kz;   // tzk[z * tzs] = exp(2 pi i kz z / Nz)
         if (MODE != PLANE_ADJ) {
             const R* q = pb + o * pz + xl * Nz;
             R ar = 0, ai = 0;
-            for (int z = 0, idx = 0; z < Nz; ++z, idx = (idx + kz >= Nz) ? idx + kz - Nz : idx + kz) {
-                const CR tw = twz[idx];
+            for (int z = 0; z < Nz; ++z) {
+                const CR tw = tzk[z * tzs];
                 ar += q[z] * tw.x;
                 ai -= q[z] * tw.y;
             }
@@ -714,8 +762,8 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
                 const R* q1 = pb + (9 + i) * pz + xl * Nz;
                 const R* q2 = pb + (3 * i + 2) * pz + xl * Nz;
                 R ar = 0, ai = 0, br = 0, bi = 0;
-                for (int z = 0, idx = 0; z < Nz; ++z, idx = (idx + kz >= Nz) ? idx + kz - Nz : idx + kz) {
-                    const CR tw = twz[idx];
+                for (int z = 0; z < Nz; ++z) {
+                    const CR tw = tzk[z * tzs];
                     ar += q1[z] * tw.x;
                     ai -= q1[z] * tw.y;
                     br += q2[z] * tw.x;
@@ -726,8 +774,8 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             } else {  // P_{i,x} (kind 1) or P_{i,y} (kind 2)
                 const R* q = pb + (3 * i + (kind - 1)) * pz + xl * Nz;
                 R ar = 0, ai = 0;
-                for (int z = 0, idx = 0; z < Nz; ++z, idx = (idx + kz >= Nz) ? idx + kz - Nz : idx + kz) {
-                    const CR tw = twz[idx];
+                for (int z = 0; z < Nz; ++z) {
+                    const CR tw = tzk[z * tzs];
                     ar += q[z] * tw.x;
                     ai -= q[z] * tw.y;
                 }
@@ -742,21 +790,20 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     for (int it = tid; it < NOUT * nm; it += PLANE_THREADS) {
         const int o = it / nm, mm = it - o * nm, ikx = mm / nkz, kz = mm - ikx * nkz;
         const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
-        const int kstep = ((kx % Nx) + Nx) % Nx;            // kx mod Nx
-        const int idx0 = (int)(((long long)kstep * x0) % Nx);  // (kx * x0) mod Nx
+        const CR* tx = TX + ikx;   // tx[xl * nkx] = exp(2 pi i kx (x0 + xl) / Nx)
         CR res;
         if (MODE != PLANE_ADJ) {
             R ar = 0, ai = 0;
-            for (int xl = 0, idx = idx0; xl < XS; ++xl, idx = (idx + kstep >= Nx) ? idx + kstep - Nx : idx + kstep) {
-                const CR tw = twx[idx], v = xb[o * per + xl * nkz + kz];
+            for (int xl = 0; xl < XS; ++xl) {
+                const CR tw = tx[xl * nkx], v = xb[o * per + xl * nkz + kz];
                 ar += v.x * tw.x + v.y * tw.y;
                 ai += v.y * tw.x - v.x * tw.y;
             }
             res = mkc(ar * invNx, ai * invNx);
         } else if (o < 3) {  // X_i = F(A_i) - i a F(B_i)
             R ar = 0, ai = 0, br = 0, bi = 0;
-            for (int xl = 0, idx = idx0; xl < XS; ++xl, idx = (idx + kstep >= Nx) ? idx + kstep - Nx : idx + kstep) {
-                const CR tw = twx[idx];
+            for (int xl = 0; xl < XS; ++xl) {
+                const CR tw = tx[xl * nkx];
                 const CR va = xb[(3 * o) * per + xl * nkz + kz];
                 const CR vb = xb[(3 * o + 1) * per + xl * nkz + kz];
                 ar += va.x * tw.x + va.y * tw.y;
@@ -768,8 +815,8 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
         } else {  // Y_i = F(C_i)
             const int i = o - 3;
             R ar = 0, ai = 0;
-            for (int xl = 0, idx = idx0; xl < XS; ++xl, idx = (idx + kstep >= Nx) ? idx + kstep - Nx : idx + kstep) {
-                const CR tw = twx[idx], v = xb[(3 * i + 2) * per + xl * nkz + kz];
+            for (int xl = 0; xl < XS; ++xl) {
+                const CR tw = tx[xl * nkx], v = xb[(3 * i + 2) * per + xl * nkz + kz];
                 ar += v.x * tw.x + v.y * tw.y;
                 ai += v.y * tw.x - v.x * tw.y;
             }
@@ -784,13 +831,13 @@ __device__ __forceinline__ void mode_res_body(
     const KP& p, int mB, int flags, const YT* __restrict__ P3, const double2* __restrict__ u,
     double2* __restrict__ r, double* __restrict__ cost_part, double2* __restrict__ a,
     YT* __restrict__ Atil) {
-    extern __shared__ double2 sm[];
     const int N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
-    auto vec = [&](int k) { return sm + (size_t)k * N; };
-    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
+    double2* const vs = mode_vectors<NP, MT>();
+    auto vec = [&](int k) { return vs + (size_t)k * NP; };
+    double* red = reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP);
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
     double2 *R0 = vec(9), *R1 = vec(10), *R2 = vec(11);
@@ -807,8 +854,8 @@ __device__ __forceinline__ void mode_res_body(
                 vec(3 + i)[n] = u[so + ((size_t)i * nm + m) * N + n];
             }
         __syncthreads();
-        mv3<NP, MT>(p, M_CINV, N, N, vec(0), vec(1), vec(2), vec(6), vec(7), vec(8));
-        mv3<NP, MT>(p, M_D2, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
+        mv3<NP, MT>(p, M_CINV, N, vec(0), vec(1), vec(2), vec(6), vec(7), vec(8));
+        mv3<NP, MT>(p, M_D2, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
         __syncthreads();
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MT) {
@@ -829,7 +876,7 @@ __device__ __forceinline__ void mode_res_body(
         __syncthreads();
     }
     if (!(flags & (RES_COST | RES_ADJ))) return;
-    mv3<NP, MT>(p, M_G, N, N, R0, R1, R2, vec(3), vec(4), vec(5));
+    mv3<NP, MT>(p, M_G, N, R0, R1, R2, vec(3), vec(4), vec(5));
     __syncthreads();
     if (flags & RES_COST) {
         double s = 0;
@@ -847,8 +894,8 @@ __device__ __forceinline__ void mode_res_body(
         stokes0_h<NP, MT>(p, vec(3), vec(5), vec(6), vec(7), vec(8), vec(12));
     else
         stokes_h<NP, MT>(p, m, c, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8), vec(12), red);
-    mv3<NP, MT>(p, M_GINV, N, N, vec(6), vec(7), vec(8), vec(0), vec(1), vec(2));
-    mv3<NP, MT>(p, M_CINVT, N, N, vec(6), vec(7), vec(8), vec(12), vec(13), vec(14));
+    mv3<NP, MT>(p, M_GINV, N, vec(6), vec(7), vec(8), vec(0), vec(1), vec(2));
+    mv3<NP, MT>(p, M_CINVT, N, vec(6), vec(7), vec(8), vec(12), vec(13), vec(14));
     __syncthreads();
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MT) {
@@ -861,13 +908,12 @@ template <int NP, int MT, class YT>
 __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, const YT* __restrict__ P6,
                                                const double2* __restrict__ a, double dtau,
                                                double2* __restrict__ uo, YT* __restrict__ Y) {
-    extern __shared__ double2 sm[];
     const int N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
-    auto vec = [&](int k) { return sm + (size_t)k * N; };
-    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
+    double2* const vs = mode_vectors<NP, MT>();
+    auto vec = [&](int k) { return vs + (size_t)k * NP; };
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
     for (int i = 0; i < 3; ++i)
@@ -882,9 +928,9 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
             vec(6 + i)[n] = a[so + ((size_t)i * nm + m) * N + n];
         }
     __syncthreads();
-    mv3<NP, MT>(p, M_MA, N, N, vec(0), vec(1), vec(2), vec(9), vec(10), vec(11));
-    mv3<NP, MT>(p, M_MB, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
-    mv3<NP, MT>(p, M_ML, N, N, vec(6), vec(7), vec(8), vec(15), vec(16), vec(17));
+    mv3<NP, MT>(p, M_MA, N, vec(0), vec(1), vec(2), vec(9), vec(10), vec(11));
+    mv3<NP, MT>(p, M_MB, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
+    mv3<NP, MT>(p, M_ML, N, vec(6), vec(7), vec(8), vec(15), vec(16), vec(17));
     __syncthreads();
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MT) {
@@ -916,8 +962,8 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
                 vec(3 + i)[n] = un;
             }
         __syncthreads();
-        mv3<NP, MT>(p, M_C, N, N, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8));
-        mv3<NP, MT>(p, M_CD, N, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
+        mv3<NP, MT>(p, M_C, N, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8));
+        mv3<NP, MT>(p, M_CD, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
         __syncthreads();
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MT) {
@@ -1017,13 +1063,12 @@ __global__ __launch_bounds__(MT) void kg_mode_grad(const GroupMember* __restrict
 template <int NP, int MT>
 __global__ __launch_bounds__(MT) void k_project(KP p, const double2* __restrict__ g,
                                                           double2* __restrict__ out) {
-    extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
-    auto vec = [&](int k) { return sm + (size_t)k * N; };
-    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
+    double2* const vs = mode_vectors<NP, MT>();
+    auto vec = [&](int k) { return vs + (size_t)k * NP; };
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MT) vec(i)[n] = g[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
@@ -1066,18 +1111,18 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
 template <int NP, int MT>
 __global__ __launch_bounds__(MT) void k_norms(KP p, const double2* __restrict__ u,
                                                         double* __restrict__ part) {
-    extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
-    auto vec = [&](int k) { return sm + (size_t)k * N; };
-    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
+    double2* const vs = mode_vectors<NP, MT>();
+    auto vec = [&](int k) { return vs + (size_t)k * NP; };
+    double* red = reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP);
     const MS c = mscal(p, m);
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MT) vec(i)[n] = u[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
-    mv3<NP, MT>(p, M_G, N, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
+    mv3<NP, MT>(p, M_G, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
     __syncthreads();
     double s0 = 0;
     for (int i = 0; i < 3; ++i)
@@ -1089,9 +1134,9 @@ __global__ __launch_bounds__(MT) void k_norms(KP p, const double2* __restrict__ 
     }
     if (m == 0 && t == 0) vec(0)[1] = cadd(vec(0)[1], c2(1.0, 0.0));  // + u_b = T_1(y) e_x
     __syncthreads();
-    mv3<NP, MT>(p, M_G, N, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
-    mv<NP, MT>(p, M_D, N, N, vec(0), vec(6));
-    mv<NP, MT>(p, M_D, N, N, vec(2), vec(7));
+    mv3<NP, MT>(p, M_G, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
+    mv<NP, MT>(p, M_D, N, vec(0), vec(6));
+    mv<NP, MT>(p, M_D, N, vec(2), vec(7));
     __syncthreads();
     double s1 = 0;
     for (int i = 0; i < 3; ++i)
@@ -1109,7 +1154,7 @@ __global__ __launch_bounds__(MT) void k_norms(KP p, const double2* __restrict__ 
         vec(10)[n] = csub(imul(c.a, uy), vec(6)[n]);
     }
     __syncthreads();
-    mv3<NP, MT>(p, M_G, N, N, vec(8), vec(9), vec(10), vec(11), vec(12), vec(13));
+    mv3<NP, MT>(p, M_G, N, vec(8), vec(9), vec(10), vec(11), vec(12), vec(13));
     __syncthreads();
     double s2 = 0;
     for (int i = 0; i < 3; ++i)
@@ -1131,18 +1176,18 @@ __global__ __launch_bounds__(MT) void k_norms(KP p, const double2* __restrict__ 
 template <int NP, int MT>
 __global__ __launch_bounds__(MT) void k_check(KP p, const double2* __restrict__ u,
                                                         double* __restrict__ part) {
-    extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
-    auto vec = [&](int k) { return sm + (size_t)k * N; };
-    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
+    double2* const vs = mode_vectors<NP, MT>();
+    auto vec = [&](int k) { return vs + (size_t)k * NP; };
+    double* red = reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP);
     const MS c = mscal(p, m);
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MT) vec(i)[n] = u[so + ((size_t)i * nm + m) * N + n];
     __syncthreads();
-    mv<NP, MT>(p, M_D, N, N, vec(1), vec(3));
+    mv<NP, MT>(p, M_D, N, vec(1), vec(3));
     __syncthreads();
     double dv = 0, herm = 0;
     double wr[6] = {0, 0, 0, 0, 0, 0}, wi[6] = {0, 0, 0, 0, 0, 0};
@@ -1233,15 +1278,15 @@ __device__ double2 par_sum(const double2* x, int lim, int par, bool sq, double* 
 template <int NP, int MT>
 __global__ __launch_bounds__(MT) void k_unpack(KP p, const double* __restrict__ psi,
                                                          double2* __restrict__ u) {
-    extern __shared__ double2 sm[];
     const int mB = xcd_item(blockIdx.x, gridDim.x), N = p.N, nm = p.nm, nmB = p.nmB, t = threadIdx.x;
     if (mB >= nmB) return;
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     const int idx = p.indep[m];
     if (idx < 0) return;
-    auto vec = [&](int k) { return sm + (size_t)k * N; };
-    double* red = reinterpret_cast<double*>(sm + (size_t)MODE_VECS * N);
+    double2* const vs = mode_vectors<NP, MT>();
+    auto vec = [&](int k) { return vs + (size_t)k * NP; };
+    double* red = reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP);
     if (m == 0) {
         for (int n = t; n < N; n += MT) {
             vec(0)[n] = c2(n < N - 2 ? psi[(size_t)b * p.nstate + n] : 0.0, 0);
@@ -1295,7 +1340,7 @@ __global__ __launch_bounds__(MT) void k_unpack(KP p, const double* __restrict__ 
         }
         __syncthreads();
     }
-    mv<NP, MT>(p, M_D, N, N, v, Dv);
+    mv<NP, MT>(p, M_D, N, v, Dv);
     __syncthreads();
     const int ikx = m / p.nkz, kz = m - ikx * p.nkz;
     const int mp = ((p.nkx - ikx) % p.nkx) * p.nkz;
@@ -1404,26 +1449,34 @@ size_t plane_lds_bytes(const KP& p, int mode) {
     const size_t nxf = 3 * ng3 + ng1, r = p.prec == PREC_FP32 ? 4 : 8;
     const size_t products = (size_t)npf * p.XS * p.Nz * r;
     const size_t staged = (mode == PLANE_JVP || !p.stage) ? 0 : (size_t)(2 * ng3 + ng1) * p.nm * 2 * r;   // aliases products
-    return (size_t)(p.Nx + p.Nz) * 2 * r + nxf * p.XS * p.nkz * 2 * r + std::max(products, staged);
+    const size_t twiddles = (size_t)p.XS * p.nkx + (size_t)p.Nz * (p.nkz + 1);
+    return twiddles * 2 * r + nxf * p.XS * p.nkz * 2 * r + std::max(products, staged);
 }
 
 size_t mode_lds_bytes(const KP& p) {
-    return (size_t)MODE_VECS * p.N * 16 + (size_t)(p.mthreads / WAVE) * RED_SLOTS * 8;
+    return (size_t)MODE_VECS * p.np * 16 + (size_t)(p.mthreads / WAVE) * RED_SLOTS * 8;
 }
 
 static dim3 mode_grid(const KP& p) { return dim3((unsigned)((p.nmB + NXCD - 1) / NXCD * NXCD)); }
 
-// The per-mode kernels are compiled for Ny padded to a multiple of 16 so that
-// every contraction loop is fully unrolled.
-int padded_ny(int N) { return (N + 15) / 16 * 16; }
-static int padded_ny(const KP& p) { return padded_ny(p.N); }
+// The per-mode kernels are compiled for a fixed set of padded Ny (KP::np, a
+// multiple of 8 so that every split of a contraction is whole) and every
+// contraction loop is fully unrolled; Ny takes the smallest that holds it.
+static const int kPaddedNy[] = {16, 32, 48, 56, 64, 72, 80, 96, 112, 128};
+int padded_ny(int N) {
+    for (int np : kPaddedNy)
+        if (N <= np) return np;
+    return 0;
+}
 
 #define PCFV_DISPATCH_NP(np, ...)                                 \
     switch (np) {                                                 \
         case 16: { constexpr int NP = 16; __VA_ARGS__; } break;   \
         case 32: { constexpr int NP = 32; __VA_ARGS__; } break;   \
         case 48: { constexpr int NP = 48; __VA_ARGS__; } break;   \
+        case 56: { constexpr int NP = 56; __VA_ARGS__; } break;   \
         case 64: { constexpr int NP = 64; __VA_ARGS__; } break;   \
+        case 72: { constexpr int NP = 72; __VA_ARGS__; } break;   \
         case 80: { constexpr int NP = 80; __VA_ARGS__; } break;   \
         case 96: { constexpr int NP = 96; __VA_ARGS__; } break;   \
         case 112: { constexpr int NP = 112; __VA_ARGS__; } break; \
@@ -1443,7 +1496,7 @@ static int padded_ny(const KP& p) { return padded_ny(p.N); }
 // FP32 complex (half the bytes, same buffers) for PREC_FP32.
 template <class YT>
 static hipError_t synth_t(const KP& p, hipStream_t s, const double2* u, void* Y) {
-    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_synth<NP, MT, YT>), mode_grid(p), dim3(MT),
+    PCFV_DISPATCH_MODE(p.np, p.mthreads, hipLaunchKernelGGL((k_synth<NP, MT, YT>), mode_grid(p), dim3(MT),
                                                       mode_lds_bytes(p), s, p, u, static_cast<YT*>(Y)));
     return hipGetLastError();
 }
@@ -1460,29 +1513,46 @@ static hipError_t plane_t(const KP& p, hipStream_t s, int mode, const void* Y1, 
     const CR* y1 = static_cast<const CR*>(Y1);
     const CR* y2 = static_cast<const CR*>(Y2);
     CR* o = static_cast<CR*>(out);
-    if (mode == PLANE_FWD)
+    if (mode == PLANE_FWD) {
         hipLaunchKernelGGL((k_plane<PLANE_FWD, R, NT>), grid, block, lds, s, p, y1, y2, o);
-    else if (mode == PLANE_JVP)
-        hipLaunchKernelGGL((k_plane<PLANE_JVP, R, NT>), grid, block, lds, s, p, y1, y2, o);
-    else
+    } else if (mode == PLANE_JVP) {
+        if constexpr (NT <= 512)
+            hipLaunchKernelGGL((k_plane<PLANE_JVP, R, NT>), grid, block, lds, s, p, y1, y2, o);
+        else
+            return hipErrorInvalidValue;
+    } else {
         hipLaunchKernelGGL((k_plane<PLANE_ADJ, R, NT>), grid, block, lds, s, p, y1, y2, o);
+    }
     return hipGetLastError();
 }
 
+// Work-group sizes of the physical-space kernels.  Their four stages hand out
+// (fields x slab points) work items to the threads, so the size that wastes
+// the fewest partial passes depends on the slab; the JVP variant carries twice
+// the fields (more registers) and runs with at most 512 threads.
+#define PCFV_DISPATCH_PT(nt, ...)                                   \
+    switch (nt) {                                                   \
+        case 256: { constexpr int NT = 256; __VA_ARGS__; } break;   \
+        case 512: { constexpr int NT = 512; __VA_ARGS__; } break;   \
+        case 768: { constexpr int NT = 768; __VA_ARGS__; } break;   \
+        case 1024: { constexpr int NT = 1024; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;                       \
+    }
+
 hipError_t launch_plane(const KP& p, hipStream_t s, int mode, const void* Y1, const void* Y2, void* out) {
-    if (p.pthreads == 256)
-        return p.prec == PREC_FP32 ? plane_t<float, 256>(p, s, mode, Y1, Y2, out)
-                                   : plane_t<double, 256>(p, s, mode, Y1, Y2, out);
-    if (p.pthreads == 512)
-        return p.prec == PREC_FP32 ? plane_t<float, 512>(p, s, mode, Y1, Y2, out)
-                                   : plane_t<double, 512>(p, s, mode, Y1, Y2, out);
+    const int nt = (mode == PLANE_JVP) ? std::min(p.pthreads, 512) : p.pthreads;
+    if (p.prec == PREC_FP32) {
+        PCFV_DISPATCH_PT(nt, return plane_t<float, NT>(p, s, mode, Y1, Y2, out));
+    } else {
+        PCFV_DISPATCH_PT(nt, return plane_t<double, NT>(p, s, mode, Y1, Y2, out));
+    }
     return hipErrorInvalidValue;
 }
 
 template <class YT>
 static hipError_t mode_res_t(const KP& p, hipStream_t s, int flags, const void* P3, const double2* u,
                              double2* r, double* cost_part, double2* a, void* Atil) {
-    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_mode_res<NP, MT, YT>), mode_grid(p), dim3(MT),
+    PCFV_DISPATCH_MODE(p.np, p.mthreads, hipLaunchKernelGGL((k_mode_res<NP, MT, YT>), mode_grid(p), dim3(MT),
                                                       mode_lds_bytes(p), s, p, flags, static_cast<const YT*>(P3),
                                                       u, r, cost_part, a, static_cast<YT*>(Atil)));
     return hipGetLastError();
@@ -1497,7 +1567,7 @@ hipError_t launch_mode_res(const KP& p, hipStream_t s, int flags, const void* P3
 template <class YT>
 static hipError_t mode_grad_t(const KP& p, hipStream_t s, int flags, const void* P6, const double2* a,
                               double dtau, double2* u_or_out, void* Y) {
-    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_mode_grad<NP, MT, YT>), mode_grid(p), dim3(MT),
+    PCFV_DISPATCH_MODE(p.np, p.mthreads, hipLaunchKernelGGL((k_mode_grad<NP, MT, YT>), mode_grid(p), dim3(MT),
                                                       mode_lds_bytes(p), s, p, flags, static_cast<const YT*>(P6),
                                                       a, dtau, u_or_out, static_cast<YT*>(Y)));
     return hipGetLastError();
@@ -1540,15 +1610,16 @@ static hipError_t group_t(const GroupLaunch& g, hipStream_t s, int which) {
 }
 
 hipError_t launch_group(const GroupLaunch& g, hipStream_t s, int which) {
-    if (g.pthreads == 256)
-        return g.prec == PREC_FP32 ? group_t<float, 256, float2>(g, s, which) : group_t<double, 256, double2>(g, s, which);
-    if (g.pthreads == 512)
-        return g.prec == PREC_FP32 ? group_t<float, 512, float2>(g, s, which) : group_t<double, 512, double2>(g, s, which);
+    if (g.prec == PREC_FP32) {
+        PCFV_DISPATCH_PT(g.pthreads, return group_t<float, NT, float2>(g, s, which));
+    } else {
+        PCFV_DISPATCH_PT(g.pthreads, return group_t<double, NT, double2>(g, s, which));
+    }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_project(const KP& p, hipStream_t s, const double2* g, double2* out) {
-    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_project<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, g, out));
+    PCFV_DISPATCH_MODE(p.np, p.mthreads, hipLaunchKernelGGL((k_project<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, g, out));
     return hipGetLastError();
 }
 
@@ -1559,12 +1630,12 @@ hipError_t launch_reduce(hipStream_t s, const double* part, int ngroups, int n, 
 }
 
 hipError_t launch_norms(const KP& p, hipStream_t s, const double2* u, double* part) {
-    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_norms<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, u, part));
+    PCFV_DISPATCH_MODE(p.np, p.mthreads, hipLaunchKernelGGL((k_norms<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, u, part));
     return hipGetLastError();
 }
 
 hipError_t launch_check(const KP& p, hipStream_t s, const double2* u, double* part) {
-    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_check<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, u, part));
+    PCFV_DISPATCH_MODE(p.np, p.mthreads, hipLaunchKernelGGL((k_check<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, u, part));
     return hipGetLastError();
 }
 
@@ -1577,7 +1648,7 @@ hipError_t launch_pack(const KP& p, hipStream_t s, const double2* u, double* psi
 }
 
 hipError_t launch_unpack(const KP& p, hipStream_t s, const double* psi, double2* u) {
-    PCFV_DISPATCH_MODE(padded_ny(p), p.mthreads, hipLaunchKernelGGL((k_unpack<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, psi, u));
+    PCFV_DISPATCH_MODE(p.np, p.mthreads, hipLaunchKernelGGL((k_unpack<NP, MT>), mode_grid(p), dim3(MT), mode_lds_bytes(p), s, p, psi, u));
     return hipGetLastError();
 }
 

@@ -13,11 +13,12 @@ struct KP {
     long long nstate;        // state-vector length of one guess
     int XS, NS;              // x-slab width of the physical-space kernels, number of slabs
     int prec;                // PREC_FP64, or PREC_FP32 for the physical-space transforms and products
-    int pthreads;            // threads per work group of the physical-space kernels (256 or 512)
+    int pthreads;            // threads per work group of the physical-space kernels (256, 512, 768, 1024)
     int mthreads;            // threads per work group of the per-mode kernels (256 or 512)
     int stage;               // physical-space kernels stage the plane's y-values in LDS (0/1)
+    int np;                  // padded Ny of the per-mode kernels: stride of M and of their LDS vectors
     double lam, nu, alpha, beta;
-    const double* M;         // M_COUNT fixed matrices, N x N slots, transposed
+    const double* M;         // M_COUNT fixed matrices, np x mat_ld(np) zero-padded slots, transposed
     const double* minfo;     // per-mode scalars (MI_STRIDE each)
     const double* dH;        // per-mode 1/(sigma - nu mu_k)
     const double* dP;        // per-mode 1/(kappa^2 - mu_k)
@@ -85,6 +86,9 @@ struct GroupLaunch {
 enum GroupKernel { GK_SYNTH = 0, GK_PLANE_FWD = 1, GK_MODE_RES = 2, GK_PLANE_ADJ = 3, GK_MODE_GRAD = 4 };
 hipError_t launch_group(const GroupLaunch& g, hipStream_t s, int which);
 int padded_ny(int N);
+// Row stride (doubles) of the fixed-matrix slots for padded Ny np: a multiple
+// of 16 so that every aligned 8-row chunk a wave loads lies in one 128-byte line.
+constexpr int mat_ld(int np) { return (np + 15) / 16 * 16; }
 
 size_t plane_lds_bytes(const KP& p, int mode);
 size_t mode_lds_bytes(const KP& p);

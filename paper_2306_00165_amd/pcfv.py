@@ -29,7 +29,8 @@ EXPORTS = [
     "pcfv_residual", "pcfv_cost", "pcfv_jvp", "pcfv_adjoint", "pcfv_project", "pcfv_descend",
     "pcfv_norms", "pcfv_pack_state", "pcfv_unpack_state", "pcfv_check_state",
     "pcfv_time_kernels", "pcfv_last_error", "pcfv_host_table", "pcfv_dmd_extrapolate",
-    "pcfv_host_dmd", "pcfv_set_precision", "pcfv_autotune", "pcfv_get_tuning", "pcfv_group_create",
+    "pcfv_host_dmd", "pcfv_set_precision", "pcfv_autotune", "pcfv_get_tuning", "pcfv_set_tuning",
+    "pcfv_group_create",
     "pcfv_group_destroy", "pcfv_group_descend", "pcfv_group_last_error",
     "pcfv_mlp_param_count", "pcfv_mlp_workspace_bytes", "pcfv_mlp_create", "pcfv_mlp_destroy",
     "pcfv_mlp_last_error", "pcfv_mlp_set_params", "pcfv_mlp_get_params", "pcfv_mlp_forward", "pcfv_mlp_grad",
@@ -143,6 +144,8 @@ def load_library(path=_LIB_PATH):
     lib.pcfv_autotune.argtypes = [vp, vp, i, ctypes.POINTER(TuneEntry), i, ctypes.POINTER(i)]
     lib.pcfv_get_tuning.restype = i
     lib.pcfv_get_tuning.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.pcfv_set_tuning.restype = i
+    lib.pcfv_set_tuning.argtypes = [vp, i, i, i]
     lib.pcfv_group_create.restype = i
     lib.pcfv_group_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp)]
     lib.pcfv_group_destroy.restype = None
@@ -439,7 +442,7 @@ class Context:
         """Time every launch-shape candidate on a copy of u and keep the
         fastest; returns the list of (xs, plane_threads, mode_threads, ms_per_step)."""
         u = self._field(u)
-        cap = 64
+        cap = 256
         ent = (TuneEntry * cap)()
         n = ctypes.c_int(0)
         self._check(_lib.pcfv_autotune(self._h, _ptr(u), int(steps), ent, cap, ctypes.byref(n)))
@@ -449,6 +452,10 @@ class Context:
         xs, nt, mt = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
         self._check(_lib.pcfv_get_tuning(self._h, ctypes.byref(xs), ctypes.byref(nt), ctypes.byref(mt)))
         return xs.value, nt.value, mt.value
+
+    def set_tuning(self, xs, plane_threads, mode_threads):
+        """Pin the launch shape (x-slab width, work-group sizes)."""
+        self._check(_lib.pcfv_set_tuning(self._h, int(xs), int(plane_threads), int(mode_threads)))
 
 
 class Group:

@@ -537,7 +537,7 @@ def test_autotune_keeps_parity(ctxs):
     c = Context(32, 33, 32)
     u = guess(g, 9)
     ent = c.autotune(u, steps=5)
-    assert ent and all(32 % xs == 0 and nt in (256, 512) and mt in (256, 512) for xs, nt, mt, _ in ent)
+    assert ent and all(32 % xs == 0 and nt in (256, 512, 768, 1024) and mt in (256, 512) for xs, nt, mt, _ in ent)
     best = min(ent, key=lambda e: e[3])
     assert c.tuning() == best[:3]
     print(f"[gpu] autotune 32x33x32: {ent}")
@@ -547,6 +547,40 @@ def test_autotune_keeps_parity(ctxs):
     for _ in range(3):
         u, _ = m.descent_step(u, 0.02)
     assert rel(to_np(U), u) < TOL
+
+
+@pytest.fixture(scope="module")
+def shape_ctx():
+    from paper_2306_00165_amd.pcfv import Context
+    g = Grid(48, 49, 48)
+    return g, Method(g), Context(48, 49, 48)
+
+
+@pytest.mark.parametrize("xs,nt,mt", [(12, 256, 512), (12, 512, 256), (12, 768, 512), (12, 1024, 512),
+                                      (8, 768, 256), (6, 1024, 256), (16, 1024, 512)])
+def test_every_launch_shape_matches_oracle(shape_ctx, xs, nt, mt):
+    """Residual, adjoint and one descent step at 48x49x48 with each pinned
+    launch shape (slab width, physical-space and per-mode work-group sizes)."""
+    import torch
+    g, m, c = shape_ctx
+    c.set_tuning(xs, nt, mt)
+    assert c.tuning() == (xs, nt, mt)
+    u, w = guess(g, 11), guess(g, 12)
+    assert rel(to_np(c.residual(u)), m.residual(u)) < TOL
+    assert rel(to_np(c.adjoint(u, w)), m.adjoint(u, w)) < TOL_ADJ49
+    U = torch.as_tensor(u).to("cuda:0").contiguous()
+    c.descend(U, max_steps=1, dtau=0.02)
+    assert rel(to_np(U), m.descent_step(u, 0.02)[0]) < TOL
+
+
+def test_set_tuning_rejects_invalid_shapes(shape_ctx):
+    from paper_2306_00165_amd.pcfv import PcfvError
+    _, _, c = shape_ctx
+    before = c.tuning()
+    for bad in [(5, 512, 512), (12, 384, 512), (12, 512, 1024), (0, 512, 256)]:
+        with pytest.raises(PcfvError):
+            c.set_tuning(*bad)
+        assert c.tuning() == before
 
 
 # -- the largest single-GPU instance: 96 x 65 x 96 in the wide box, 8 guesses --------
