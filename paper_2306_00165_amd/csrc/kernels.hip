@@ -195,35 +195,64 @@ __device__ __forceinline__ double mat_load(__amdgpu_buffer_rsrc_t rs, int voff, 
     return __hiloint2double((int)v[1], (int)v[0]);
 }
 
-// y = A x for one complex vector, A = fixed matrix id (nout x nin, zero-padded
-// to NP x NP).  Each output row is computed by MC<MT>::KS lanes of one wave,
-// each summing every MC<MT>::KS-th term over the padded length NP, then
-// combined across lanes; rows are dealt out MC<MT>::ROWS per wave.  The
-// padding terms multiply exact zeros of A by finite entries of x (the LDS
-// vectors start zeroed), so no step is predicated and every matrix load of the
-// contraction is in flight at once.  x and y live in LDS and must not alias;
-// entries [nout, NP) of y are left untouched.  Caller synchronises afterwards.
-template <int NP, int MT>
-__device__ void mv(const KP& p, int id, int nout, const double2* x, double2* y) {
+// One contraction's matrix elements as the lanes hold them.  y = A x for
+// A = fixed matrix id (nout x nin, zero-padded to NP rows): each output row is
+// computed by MC<MT>::KS lanes of one wave, each summing every MC<MT>::KS-th
+// term over the padded length NP, then combined across lanes; rows are dealt
+// out MC<MT>::ROWS per wave in PASSES passes.  The padding terms multiply
+// exact zeros of A by finite entries of x (the LDS vectors start zeroed), so
+// no step is predicated, and the loads of every pass are issued before any
+// arithmetic, so one contraction waits for memory once.  A wave whose rows
+// all lie at or past nout neither loads nor computes.
+template <int NP, int MT> struct MatRegs {
     typedef MC<MT> S;
+    static constexpr int ROWS_PER_PASS = S::WAVES * S::ROWS;
+    static constexpr int PASSES = (NP + ROWS_PER_PASS - 1) / ROWS_PER_PASS;
+    static constexpr int PER = NP / S::KS;
+    double a[PASSES][PER];
+};
+
+template <int NP, int MT>
+__device__ __forceinline__ MatRegs<NP, MT> mat_fetch(const KP& p, int id, int nout) {
+    typedef MC<MT> S;
+    typedef MatRegs<NP, MT> A;
+    constexpr int LD = mat_ld(NP);
     const __amdgpu_buffer_rsrc_t rs = mat_rsrc(p, NP);
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     const int r = lane % S::ROWS, q = lane / S::ROWS;
+    A m;
 #pragma unroll
-    for (int n0 = 0; n0 < NP; n0 += S::WAVES * S::ROWS) {
+    for (int ps = 0; ps < A::PASSES; ++ps) {
+        const int n0 = ps * A::ROWS_PER_PASS;
         if (n0 + wave * S::ROWS >= nout) break;   // wave-uniform: no rows of this wave are left
-        const int n = n0 + wave * S::ROWS + r;
-        constexpr int LD = mat_ld(NP);
-        const int voff = (q * LD + min(n, NP - 1)) * 8;
-        double a[NP / S::KS];
+        const int voff = (q * LD + min(n0 + wave * S::ROWS + r, NP - 1)) * 8;
 #pragma unroll
-        for (int i = 0; i < NP / S::KS; ++i) a[i] = mat_load(rs, voff, (id * NP + S::KS * i) * LD * 8);
+        for (int i = 0; i < A::PER; ++i) m.a[ps][i] = mat_load(rs, voff, (id * NP + S::KS * i) * LD * 8);
+    }
+    return m;
+}
+
+// y = A x for one complex vector, A = fixed matrix id.  x and y live in LDS
+// and must not alias; entries [nout, NP) of y are left untouched.  Caller
+// synchronises afterwards.
+template <int NP, int MT>
+__device__ __forceinline__ void mv(const KP& p, int id, int nout, const double2* x, double2* y) {
+    typedef MC<MT> S;
+    typedef MatRegs<NP, MT> A;
+    const A m = mat_fetch<NP, MT>(p, id, nout);
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int r = lane % S::ROWS, q = lane / S::ROWS;
+#pragma unroll
+    for (int ps = 0; ps < A::PASSES; ++ps) {
+        const int n0 = ps * A::ROWS_PER_PASS;
+        if (n0 + wave * S::ROWS >= nout) break;
+        const int n = n0 + wave * S::ROWS + r;
         double re = 0.0, im = 0.0;
 #pragma unroll
-        for (int i = 0; i < NP / S::KS; ++i) {
+        for (int i = 0; i < A::PER; ++i) {
             const double2 v = x[q + S::KS * i];
-            re = fma(a[i], v.x, re);
-            im = fma(a[i], v.y, im);
+            re = fma(m.a[ps][i], v.x, re);
+            im = fma(m.a[ps][i], v.y, im);
         }
         re = row_sum<MT>(re);
         im = row_sum<MT>(im);
@@ -233,32 +262,29 @@ __device__ void mv(const KP& p, int id, int nout, const double2* x, double2* y) 
 
 // The same matrix applied to three vectors.
 template <int NP, int MT>
-__device__ void mv3(const KP& p, int id, int nout, const double2* x0, const double2* x1,
-                    const double2* x2, double2* y0, double2* y1, double2* y2) {
+__device__ __forceinline__ void mv3(const KP& p, int id, int nout, const double2* x0, const double2* x1,
+                                    const double2* x2, double2* y0, double2* y1, double2* y2) {
     typedef MC<MT> S;
-    const __amdgpu_buffer_rsrc_t rs = mat_rsrc(p, NP);
+    typedef MatRegs<NP, MT> A;
+    const A m = mat_fetch<NP, MT>(p, id, nout);
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     const int r = lane % S::ROWS, q = lane / S::ROWS;
 #pragma unroll
-    for (int n0 = 0; n0 < NP; n0 += S::WAVES * S::ROWS) {
-        if (n0 + wave * S::ROWS >= nout) break;   // wave-uniform: no rows of this wave are left
+    for (int ps = 0; ps < A::PASSES; ++ps) {
+        const int n0 = ps * A::ROWS_PER_PASS;
+        if (n0 + wave * S::ROWS >= nout) break;
         const int n = n0 + wave * S::ROWS + r;
-        constexpr int LD = mat_ld(NP);
-        const int voff = (q * LD + min(n, NP - 1)) * 8;
-        double a[NP / S::KS];
-#pragma unroll
-        for (int i = 0; i < NP / S::KS; ++i) a[i] = mat_load(rs, voff, (id * NP + S::KS * i) * LD * 8);
         double acc[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < NP / S::KS; ++i) {
+        for (int i = 0; i < A::PER; ++i) {
             const int k = q + S::KS * i;
             const double2 v0 = x0[k], v1 = x1[k], v2 = x2[k];
-            acc[0] = fma(a[i], v0.x, acc[0]);
-            acc[1] = fma(a[i], v0.y, acc[1]);
-            acc[2] = fma(a[i], v1.x, acc[2]);
-            acc[3] = fma(a[i], v1.y, acc[3]);
-            acc[4] = fma(a[i], v2.x, acc[4]);
-            acc[5] = fma(a[i], v2.y, acc[5]);
+            acc[0] = fma(m.a[ps][i], v0.x, acc[0]);
+            acc[1] = fma(m.a[ps][i], v0.y, acc[1]);
+            acc[2] = fma(m.a[ps][i], v1.x, acc[2]);
+            acc[3] = fma(m.a[ps][i], v1.y, acc[3]);
+            acc[4] = fma(m.a[ps][i], v2.x, acc[4]);
+            acc[5] = fma(m.a[ps][i], v2.y, acc[5]);
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) acc[i] = row_sum<MT>(acc[i]);
@@ -437,9 +463,7 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
     for (int n = t; n < M; n += MT)   // bs1 = -dP (Pl[N-1,:] bp0last - PRDPL^T u2)
         tmp[n] = cscl(-dP[n], csub(cscl(PLlast[(size_t)n * mat_ld(NP)], bp0last), tmp[n]));
     __syncthreads();
-    mv<NP, MT>(p, M_PRT, M, tmp, bFh);
-    mv<NP, MT>(p, M_PRT, M, bte, bFe);
-    mv<NP, MT>(p, M_PRT, M, bt2, bFy);
+    mv3<NP, MT>(p, M_PRT, M, tmp, bte, bt2, bFh, bFe, bFy);
     mv<NP, MT>(p, M_PRDT, N, tmp, bFy2);
     __syncthreads();
     for (int n = t; n < N; n += MT) {
