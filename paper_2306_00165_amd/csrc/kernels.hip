@@ -307,6 +307,55 @@ __device__ __forceinline__ double2* mode_vectors() {
     return sm;
 }
 
+// The per-mode kernels read a few values per thread from global memory before
+// their first contraction.  The helpers below issue all of a thread's loads
+// before the first use, so their latencies overlap instead of adding up.
+
+// The three components of spectral field f at mode m of the guess at offset
+// so, into LDS vectors d0, d1, d2.
+template <int MT>
+__device__ __forceinline__ void read_field3(const KP& p, const double2* __restrict__ f, size_t so, int m,
+                                            double2* d0, double2* d1, double2* d2) {
+    const int N = p.N;
+    const size_t nm = p.nm;
+    for (int n = threadIdx.x; n < N; n += MT) {
+        const double2 a = f[so + (size_t)m * N + n], b = f[so + (nm + m) * N + n], c = f[so + (2 * nm + m) * N + n];
+        d0[n] = a;
+        d1[n] = b;
+        d2[n] = c;
+    }
+}
+
+// The x-slab partials P[s][f][j][mode] (NF fields per slab) of work item mB,
+// summed over the slabs in slab order, into the LDS vectors dst + f * NP.
+// Four slabs' loads are issued before any of them is added.
+template <int NP, int MT, int NF, class YT>
+__device__ __forceinline__ void sum_partials(const KP& p, const YT* __restrict__ P, int mB, double2* dst) {
+    const int N = p.N, NS = p.NS;
+    const size_t nmB = p.nmB;
+    for (int n = threadIdx.x; n < N; n += MT) {
+        double2 acc[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f] = c2(0.0, 0.0);
+        for (int s0 = 0; s0 < NS; s0 += 4) {
+            YT v[4][NF];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const size_t sl = (size_t)min(s0 + k, NS - 1);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) v[k][f] = P[((sl * NF + f) * N + n) * nmB + mB];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (s0 + k < NS)
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) acc[f] = cadd(acc[f], widen(v[k][f]));
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) dst[f * NP + n] = acc[f];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Stokes solve S (kappa > 0) by the influence-matrix method in the fixed
 // tau eigenbasis.  Writes (ox, oy, oz) = velocity of the Chebyshev-tau
@@ -588,8 +637,7 @@ __device__ __forceinline__ void synth_body(const KP& p, int mB, const double2* _
     const int b = mB / nm, m = mB - b * nm;   // guess, Fourier mode
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     double2* V = mode_vectors<NP, MT>();
-    for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MT) V[i * NP + n] = u[so + ((size_t)i * nm + m) * N + n];
+    read_field3<MT>(p, u, so, m, V, V + NP, V + 2 * NP);
     __syncthreads();
     mv3<NP, MT>(p, M_C, N, V, V + NP, V + 2 * NP, V + 3 * NP, V + 4 * NP, V + 5 * NP);
     mv3<NP, MT>(p, M_CD, N, V, V + NP, V + 2 * NP, V + 6 * NP, V + 7 * NP, V + 8 * NP);
@@ -626,28 +674,43 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     CR* TZ = TX + XS * nkx;
     CR* xb = TZ + Nz * tzs;
     R* pb = reinterpret_cast<R*>(xb + NXF * per);
-    for (int i = tid; i < XS * nkx; i += PLANE_THREADS) {
-        const int xl = i / nkx, ikx = i - xl * nkx, kx = (ikx <= Kx) ? ikx : ikx - nkx;
-        TX[i] = narrow<CR>(p.twx[(int)((long long)(kx + Nx) * (x0 + xl) % Nx)]);
-    }
-    for (int i = tid; i < Nz * nkz; i += PLANE_THREADS) {
-        const int z = i / nkz, kz = i - z * nkz;
-        TZ[z * tzs + kz] = narrow<CR>(p.twz[(kz * z) % Nz]);
-    }
     // With p.stage the plane's y-values are staged in LDS with one coalesced
     // pass (they are read nkx times each by the inverse x transform); the
     // staging area is the products buffer, which is not live yet.  Staging
-    // costs LDS (occupancy), so it is used for launches with few modes.  Staged fields: V and W of each
-    // velocity group (2 g, 2 g + 1), then the adjoint fields.
+    // costs LDS (occupancy), so it is used for launches with few modes.  Staged
+    // fields: V and W of each velocity group (2 g, 2 g + 1), then the adjoint
+    // fields.  Setup pass q covers entry i = q * PLANE_THREADS + tid of both
+    // twiddle tables and mode i of every staged field; a thread issues all of
+    // a pass's global loads before it stores any of them.
     const bool stage = (MODE != PLANE_JVP) && p.stage;
     constexpr int NSF = 2 * NG3 + NG1;
     CR* st = reinterpret_cast<CR*>(pb);
-    if (stage) {
-        for (int e = tid; e < NSF * nm; e += PLANE_THREADS) {
-            const int f = e / nm, m = e - f * nm;
-            const CR* src = (f < 2 * NG3) ? Y1 : Y2;
-            const int comp = (f < 2 * NG3) ? ((f & 1) ? 3 + (f >> 1) : (f >> 1)) : f - 2 * NG3;
-            st[e] = src[((size_t)comp * N + j) * nmB + mo + m];
+    {
+        const int ntx = XS * nkx, ntz = Nz * nkz, nsm = stage ? nm : 0;
+        const int nset = max(max(ntx, ntz), nsm);
+#pragma unroll 1
+        for (int i = tid; i < nset; i += PLANE_THREADS) {
+            double2 vx = make_double2(0.0, 0.0), vz = make_double2(0.0, 0.0);
+            const int xl = i / nkx, ikx = i - xl * nkx, kx = (ikx <= Kx) ? ikx : ikx - nkx;
+            const int z = i / nkz, kz = i - z * nkz;
+            if (i < ntx) vx = p.twx[(int)((long long)(kx + Nx) * (x0 + xl) % Nx)];
+            if (i < ntz) vz = p.twz[(kz * z) % Nz];
+            R svx[NSF], svy[NSF];   // two real arrays: kept in registers
+            if (i < nsm) {
+#pragma unroll
+                for (int f = 0; f < NSF; ++f) {
+                    const CR* src = (f < 2 * NG3) ? Y1 : Y2;
+                    const int comp = (f < 2 * NG3) ? ((f & 1) ? 3 + (f >> 1) : (f >> 1)) : f - 2 * NG3;
+                    const CR v = src[((size_t)comp * N + j) * nmB + mo + i];
+                    svx[f] = v.x;
+                    svy[f] = v.y;
+                }
+            }
+            if (i < ntx) TX[i] = narrow<CR>(vx);
+            if (i < ntz) TZ[z * tzs + kz] = narrow<CR>(vz);
+            if (i < nsm)
+#pragma unroll
+                for (int f = 0; f < NSF; ++f) st[f * nm + i] = mkc(svx[f], svy[f]);
         }
     }
     __syncthreads();
@@ -866,17 +929,11 @@ __device__ __forceinline__ void mode_res_body(
     const bool zero = (m == 0);
     double2 *R0 = vec(9), *R1 = vec(10), *R2 = vec(11);
     if (flags & RES_INPUT_W) {
-        for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MT) vec(9 + i)[n] = u[so + ((size_t)i * nm + m) * N + n];
+        read_field3<MT>(p, u, so, m, vec(9), vec(10), vec(11));
         __syncthreads();
     } else {
-        for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MT) {
-                double2 acc = c2(0, 0);
-                for (int s = 0; s < p.NS; ++s) acc = cadd(acc, widen(P3[(((size_t)s * 3 + i) * N + n) * nmB + mB]));
-                vec(i)[n] = acc;
-                vec(3 + i)[n] = u[so + ((size_t)i * nm + m) * N + n];
-            }
+        read_field3<MT>(p, u, so, m, vec(3), vec(4), vec(5));
+        sum_partials<NP, MT, 3>(p, P3, mB, vec(0));
         __syncthreads();
         mv3<NP, MT>(p, M_CINV, N, vec(0), vec(1), vec(2), vec(6), vec(7), vec(8));
         mv3<NP, MT>(p, M_D2, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
@@ -940,17 +997,8 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
-    for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MT) {
-            double2 sx = c2(0, 0), sy = c2(0, 0);
-            for (int s = 0; s < p.NS; ++s) {
-                sx = cadd(sx, widen(P6[(((size_t)s * 6 + i) * N + n) * nmB + mB]));
-                sy = cadd(sy, widen(P6[(((size_t)s * 6 + 3 + i) * N + n) * nmB + mB]));
-            }
-            vec(i)[n] = sx;
-            vec(3 + i)[n] = sy;
-            vec(6 + i)[n] = a[so + ((size_t)i * nm + m) * N + n];
-        }
+    read_field3<MT>(p, a, so, m, vec(6), vec(7), vec(8));
+    sum_partials<NP, MT, 6>(p, P6, mB, vec(0));
     __syncthreads();
     mv3<NP, MT>(p, M_MA, N, vec(0), vec(1), vec(2), vec(9), vec(10), vec(11));
     mv3<NP, MT>(p, M_MB, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
@@ -978,13 +1026,21 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
     }
     double2* Fs[3] = {F0, F1, F2};
     if (flags & GRAD_UPDATE) {
-        for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MT) {
-                const size_t gi = so + ((size_t)i * nm + m) * N + n;
-                const double2 un = cadd(uo[gi], cscl(dtau, Fs[i][n]));
-                uo[gi] = un;
+        for (int n = t; n < N; n += MT) {
+            size_t gi[3];
+            double2 uv[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                gi[i] = so + ((size_t)i * nm + m) * N + n;
+                uv[i] = uo[gi[i]];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double2 un = cadd(uv[i], cscl(dtau, Fs[i][n]));
+                uo[gi[i]] = un;
                 vec(3 + i)[n] = un;
             }
+        }
         __syncthreads();
         mv3<NP, MT>(p, M_C, N, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8));
         mv3<NP, MT>(p, M_CD, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
@@ -1093,8 +1149,7 @@ __global__ __launch_bounds__(MT) void k_project(KP p, const double2* __restrict_
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     double2* const vs = mode_vectors<NP, MT>();
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
-    for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MT) vec(i)[n] = g[so + ((size_t)i * nm + m) * N + n];
+    read_field3<MT>(p, g, so, m, vec(0), vec(1), vec(2));
     __syncthreads();
     if (m == 0)
         project0<NP, MT>(p, vec(0), vec(2), vec(3), vec(4), vec(5));
@@ -1143,8 +1198,7 @@ __global__ __launch_bounds__(MT) void k_norms(KP p, const double2* __restrict__ 
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
     double* red = reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP);
     const MS c = mscal(p, m);
-    for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MT) vec(i)[n] = u[so + ((size_t)i * nm + m) * N + n];
+    read_field3<MT>(p, u, so, m, vec(0), vec(1), vec(2));
     __syncthreads();
     mv3<NP, MT>(p, M_G, N, vec(0), vec(1), vec(2), vec(3), vec(4), vec(5));
     __syncthreads();
@@ -1208,8 +1262,7 @@ __global__ __launch_bounds__(MT) void k_check(KP p, const double2* __restrict__ 
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
     double* red = reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP);
     const MS c = mscal(p, m);
-    for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MT) vec(i)[n] = u[so + ((size_t)i * nm + m) * N + n];
+    read_field3<MT>(p, u, so, m, vec(0), vec(1), vec(2));
     __syncthreads();
     mv<NP, MT>(p, M_D, N, vec(1), vec(3));
     __syncthreads();
