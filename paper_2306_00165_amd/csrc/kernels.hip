@@ -658,6 +658,7 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     constexpr int NG1 = (MODE == PLANE_ADJ) ? 3 : 0;  // adjoint fields: single outputs
     constexpr int NXF = 3 * NG3 + NG1;
     constexpr int NZF = (MODE == PLANE_ADJ) ? 9 : 3;  // after the forward z stage
+    static_assert(NG1 == 0 || NG1 == NG3, "adjoint fields pair with the velocity groups");
     if (item >= p.B * p.NS * p.N) return;
     const int jb = item / p.NS, s = item - jb * p.NS;   // the slabs of a plane run on one XCD
     const int b = jb / p.N, j = jb - b * p.N;          // guess, Gauss-Lobatto plane
@@ -718,47 +719,41 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     // inverse transform in x for the slab's x positions, all retained kz; the
     // y-values come from LDS (staged) or straight from global memory, as two
     // instantiations so that each pointer has one address space
+    // Work item (g, xl, kz): velocity group g and, in the adjoint variant, the
+    // adjoint field g too (NG1 == NG3 there), sharing the twiddles.
     auto inverse_x = [&](auto staged) {
         constexpr bool ST = decltype(staged)::value;
-        for (int it = tid; it < (NG3 + NG1) * per; it += PLANE_THREADS) {
+        for (int it = tid; it < NG3 * per; it += PLANE_THREADS) {
             const int g = it / per, rem = it - g * per, xl = rem / nkz, kz = rem - xl * nkz;
-            if (g < NG3) {
-                const CR* Vp;
-                const CR* Wp;
-                if constexpr (ST) {
-                    Vp = st + (2 * g) * nm + kz;
-                    Wp = st + (2 * g + 1) * nm + kz;
-                } else {
-                    const CR* src = (g < 3) ? Y1 : Y2;
-                    const int comp = g % 3;
-                    Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
-                    Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
-                }
-                CR aV = mkc(zero, zero), aA = mkc(zero, zero), aW = mkc(zero, zero);
-                const CR* tx = TX + xl * nkx;
-                for (int ikx = 0; ikx < nkx; ++ikx) {
-                    const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
-                    const CR tw = tx[ikx];
-                    const CR vt = cmul(Vp[(size_t)ikx * nkz], tw);
-                    aV = cadd(aV, vt);
-                    aA = cadd(aA, imul(alpha * (R)kx, vt));
-                    aW = cadd(aW, cmul(Wp[(size_t)ikx * nkz], tw));
-                }
-                xb[(3 * g) * per + rem] = aV;
-                xb[(3 * g + 1) * per + rem] = aA;
-                xb[(3 * g + 2) * per + rem] = aW;
+            const CR* Vp;
+            const CR* Wp;
+            const CR* Ap = nullptr;
+            if constexpr (ST) {
+                Vp = st + (2 * g) * nm + kz;
+                Wp = st + (2 * g + 1) * nm + kz;
+                if constexpr (NG1 > 0) Ap = st + (2 * NG3 + g) * nm + kz;
             } else {
-                const int comp = g - NG3;
-                const CR* Ap;
-                if constexpr (ST)
-                    Ap = st + (2 * NG3 + comp) * nm + kz;
-                else
-                    Ap = Y2 + ((size_t)comp * N + j) * nmB + mo + kz;
-                CR acc = mkc(zero, zero);
-                const CR* tx = TX + xl * nkx;
-                for (int ikx = 0; ikx < nkx; ++ikx) acc = cadd(acc, cmul(Ap[(size_t)ikx * nkz], tx[ikx]));
-                xb[(3 * NG3 + comp) * per + rem] = acc;
+                const CR* src = (g < 3) ? Y1 : Y2;
+                const int comp = g % 3;
+                Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
+                Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
+                if constexpr (NG1 > 0) Ap = Y2 + ((size_t)g * N + j) * nmB + mo + kz;
             }
+            CR aV = mkc(zero, zero), aA = mkc(zero, zero), aW = mkc(zero, zero), aT = mkc(zero, zero);
+            const CR* tx = TX + xl * nkx;
+            for (int ikx = 0; ikx < nkx; ++ikx) {
+                const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
+                const CR tw = tx[ikx];
+                const CR vt = cmul(Vp[(size_t)ikx * nkz], tw);
+                aV = cadd(aV, vt);
+                aA = cadd(aA, imul(alpha * (R)kx, vt));
+                aW = cadd(aW, cmul(Wp[(size_t)ikx * nkz], tw));
+                if constexpr (NG1 > 0) aT = cadd(aT, cmul(Ap[(size_t)ikx * nkz], tw));
+            }
+            xb[(3 * g) * per + rem] = aV;
+            xb[(3 * g + 1) * per + rem] = aA;
+            xb[(3 * g + 2) * per + rem] = aW;
+            if constexpr (NG1 > 0) xb[(3 * NG3 + g) * per + rem] = aT;
         }
     };
     if (stage)
@@ -829,9 +824,11 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     }
     __syncthreads();
 
-    // forward transform in z (normalised), into xb
+    // forward transform in z (normalised), into xb.  Adjoint variant: work item
+    // (i, xl, kz) forms the three outputs of component i, sharing the twiddles.
     const R invNz = (R)1 / (R)Nz, invNx = (R)1 / (R)Nx;
-    for (int it = tid; it < NZF * per; it += PLANE_THREADS) {
+    constexpr int NZI = (MODE == PLANE_ADJ) ? 3 : NZF;
+    for (int it = tid; it < NZI * per; it += PLANE_THREADS) {
         const int o = it / per, rem = it - o * per, xl = rem / nkz, kz = rem - xl * nkz;
         const CR* tzk = TZ + kz;   // tzk[z * tzs] = exp(2 pi i kz z / Nz)
         if (MODE != PLANE_ADJ) {
@@ -844,72 +841,64 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             }
             xb[o * per + rem] = mkc(ar * invNz, ai * invNz);
         } else {
-            const int i = o / 3, kind = o - 3 * i;
-            if (kind == 0) {  // Q_i - i b P_{i,z}
-                const R* q1 = pb + (9 + i) * pz + xl * Nz;
-                const R* q2 = pb + (3 * i + 2) * pz + xl * Nz;
-                R ar = 0, ai = 0, br = 0, bi = 0;
-                for (int z = 0; z < Nz; ++z) {
-                    const CR tw = tzk[z * tzs];
-                    ar += q1[z] * tw.x;
-                    ai -= q1[z] * tw.y;
-                    br += q2[z] * tw.x;
-                    bi -= q2[z] * tw.y;
-                }
-                const CR r = csub(mkc(ar, ai), imul(beta * (R)kz, mkc(br, bi)));
-                xb[o * per + rem] = cscl(invNz, r);
-            } else {  // P_{i,x} (kind 1) or P_{i,y} (kind 2)
-                const R* q = pb + (3 * i + (kind - 1)) * pz + xl * Nz;
-                R ar = 0, ai = 0;
-                for (int z = 0; z < Nz; ++z) {
-                    const CR tw = tzk[z * tzs];
-                    ar += q[z] * tw.x;
-                    ai -= q[z] * tw.y;
-                }
-                xb[o * per + rem] = mkc(ar * invNz, ai * invNz);
+            const int i = o;
+            const R* q1 = pb + (9 + i) * pz + xl * Nz;      // Q_i
+            const R* q2 = pb + (3 * i + 2) * pz + xl * Nz;  // P_{i,z}
+            const R* qx = pb + (3 * i) * pz + xl * Nz;      // P_{i,x}
+            const R* qy = pb + (3 * i + 1) * pz + xl * Nz;  // P_{i,y}
+            R ar = 0, ai = 0, br = 0, bi = 0, xr = 0, xi = 0, yr = 0, yi = 0;
+            for (int z = 0; z < Nz; ++z) {
+                const CR tw = tzk[z * tzs];
+                ar += q1[z] * tw.x;
+                ai -= q1[z] * tw.y;
+                br += q2[z] * tw.x;
+                bi -= q2[z] * tw.y;
+                xr += qx[z] * tw.x;
+                xi -= qx[z] * tw.y;
+                yr += qy[z] * tw.x;
+                yi -= qy[z] * tw.y;
             }
+            xb[(3 * i) * per + rem] = cscl(invNz, csub(mkc(ar, ai), imul(beta * (R)kz, mkc(br, bi))));  // Q_i - i b P_{i,z}
+            xb[(3 * i + 1) * per + rem] = mkc(xr * invNz, xi * invNz);
+            xb[(3 * i + 2) * per + rem] = mkc(yr * invNz, yi * invNz);
         }
     }
     __syncthreads();
 
-    // forward transform in x over this slab (partial sum), retained modes only
+    // forward transform in x over this slab (partial sum), retained modes only;
+    // work item mm forms every output of mode mm, sharing the twiddles.  The
+    // adjoint outputs are X_i = F(A_i) - i a F(B_i) and Y_i = F(C_i) from the
+    // fields (A_i, B_i, C_i) = xb fields (3 i, 3 i + 1, 3 i + 2).
     constexpr int NOUT = (MODE == PLANE_ADJ) ? 6 : 3;
-    for (int it = tid; it < NOUT * nm; it += PLANE_THREADS) {
-        const int o = it / nm, mm = it - o * nm, ikx = mm / nkz, kz = mm - ikx * nkz;
+    constexpr int NIN = (MODE == PLANE_ADJ) ? 9 : 3;
+    for (int mm = tid; mm < nm; mm += PLANE_THREADS) {
+        const int ikx = mm / nkz, kz = mm - ikx * nkz;
         const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
         const CR* tx = TX + ikx;   // tx[xl * nkx] = exp(2 pi i kx (x0 + xl) / Nx)
-        CR res;
-        if (MODE != PLANE_ADJ) {
-            R ar = 0, ai = 0;
-            for (int xl = 0; xl < XS; ++xl) {
-                const CR tw = tx[xl * nkx], v = xb[o * per + xl * nkz + kz];
-                ar += v.x * tw.x + v.y * tw.y;
-                ai += v.y * tw.x - v.x * tw.y;
+        R ar[NIN], ai[NIN];
+#pragma unroll
+        for (int f = 0; f < NIN; ++f) ar[f] = ai[f] = 0;
+        for (int xl = 0; xl < XS; ++xl) {
+            const CR tw = tx[xl * nkx];
+#pragma unroll
+            for (int f = 0; f < NIN; ++f) {
+                const CR v = xb[f * per + xl * nkz + kz];
+                ar[f] += v.x * tw.x + v.y * tw.y;
+                ai[f] += v.y * tw.x - v.x * tw.y;
             }
-            res = mkc(ar * invNx, ai * invNx);
-        } else if (o < 3) {  // X_i = F(A_i) - i a F(B_i)
-            R ar = 0, ai = 0, br = 0, bi = 0;
-            for (int xl = 0; xl < XS; ++xl) {
-                const CR tw = tx[xl * nkx];
-                const CR va = xb[(3 * o) * per + xl * nkz + kz];
-                const CR vb = xb[(3 * o + 1) * per + xl * nkz + kz];
-                ar += va.x * tw.x + va.y * tw.y;
-                ai += va.y * tw.x - va.x * tw.y;
-                br += vb.x * tw.x + vb.y * tw.y;
-                bi += vb.y * tw.x - vb.x * tw.y;
-            }
-            res = cscl(invNx, csub(mkc(ar, ai), imul(alpha * (R)kx, mkc(br, bi))));
-        } else {  // Y_i = F(C_i)
-            const int i = o - 3;
-            R ar = 0, ai = 0;
-            for (int xl = 0; xl < XS; ++xl) {
-                const CR tw = tx[xl * nkx], v = xb[(3 * i + 2) * per + xl * nkz + kz];
-                ar += v.x * tw.x + v.y * tw.y;
-                ai += v.y * tw.x - v.x * tw.y;
-            }
-            res = mkc(ar * invNx, ai * invNx);
         }
-        out[(((size_t)s * NOUT + o) * N + j) * nmB + mo + mm] = res;
+        CR* o0 = out + ((size_t)s * NOUT * N + j) * nmB + mo + mm;   // output o at o0[o * N * nmB]
+        const size_t os = (size_t)N * nmB;
+        if (MODE != PLANE_ADJ) {
+#pragma unroll
+            for (int o = 0; o < 3; ++o) o0[o * os] = mkc(ar[o] * invNx, ai[o] * invNx);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                o0[i * os] = cscl(invNx, csub(mkc(ar[3 * i], ai[3 * i]), imul(alpha * (R)kx, mkc(ar[3 * i + 1], ai[3 * i + 1]))));
+                o0[(3 + i) * os] = mkc(ar[3 * i + 2] * invNx, ai[3 * i + 2] * invNx);
+            }
+        }
     }
 }
 
