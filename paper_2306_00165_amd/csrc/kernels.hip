@@ -69,6 +69,18 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 imul(float s, float2 z) { return mkc(-s * z.y, s * z.x); }
 
+// Fused multiply-add in the precision of its arguments.
+__device__ __forceinline__ double fmar(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmar(float a, float b, float c) { return fmaf(a, b, c); }
+
+// acc + a b for complex a, b as four fused multiply-adds.
+__device__ __forceinline__ double2 cmac(double2 acc, double2 a, double2 b) {
+    return c2(fmar(-a.y, b.y, fmar(a.x, b.x, acc.x)), fmar(a.y, b.x, fmar(a.x, b.y, acc.y)));
+}
+__device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 b) {
+    return mkc(fmar(-a.y, b.y, fmar(a.x, b.x, acc.x)), fmar(a.y, b.x, fmar(a.x, b.y, acc.y)));
+}
+
 __device__ __forceinline__ double2 widen(double2 v) { return v; }
 __device__ __forceinline__ double2 widen(float2 v) { return make_double2(v.x, v.y); }
 template <class T> __device__ __forceinline__ T narrow(double2 v);
@@ -739,19 +751,20 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
                 Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
                 if constexpr (NG1 > 0) Ap = Y2 + ((size_t)g * N + j) * nmB + mo + kz;
             }
-            CR aV = mkc(zero, zero), aA = mkc(zero, zero), aW = mkc(zero, zero), aT = mkc(zero, zero);
+            // aV = sum V tw, aK = sum kx V tw (then aA = i alpha aK), aW, aT = sum W tw, A tw
+            CR aV = mkc(zero, zero), aK = mkc(zero, zero), aW = mkc(zero, zero), aT = mkc(zero, zero);
             const CR* tx = TX + xl * nkx;
             for (int ikx = 0; ikx < nkx; ++ikx) {
-                const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
+                const R kx = (R)((ikx <= Kx) ? ikx : ikx - nkx);
                 const CR tw = tx[ikx];
                 const CR vt = cmul(Vp[(size_t)ikx * nkz], tw);
                 aV = cadd(aV, vt);
-                aA = cadd(aA, imul(alpha * (R)kx, vt));
-                aW = cadd(aW, cmul(Wp[(size_t)ikx * nkz], tw));
-                if constexpr (NG1 > 0) aT = cadd(aT, cmul(Ap[(size_t)ikx * nkz], tw));
+                aK = mkc(fmar(kx, vt.x, aK.x), fmar(kx, vt.y, aK.y));
+                aW = cmac(aW, Wp[(size_t)ikx * nkz], tw);
+                if constexpr (NG1 > 0) aT = cmac(aT, Ap[(size_t)ikx * nkz], tw);
             }
             xb[(3 * g) * per + rem] = aV;
-            xb[(3 * g + 1) * per + rem] = aA;
+            xb[(3 * g + 1) * per + rem] = imul(alpha, aK);
             xb[(3 * g + 2) * per + rem] = aW;
             if constexpr (NG1 > 0) xb[(3 * NG3 + g) * per + rem] = aT;
         }
@@ -766,27 +779,44 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     const R yj = (R)p.ygl[j];
     for (int pt = tid; pt < pz; pt += PLANE_THREADS) {
         const int xl = pt / Nz, z = pt - xl * Nz;
-        R val[NG3][4];  // U, dU/dx, dU/dy, dU/dz of each velocity field
+        // U, dU/dx, dU/dy, dU/dz of each velocity field: Re of the kz sums, the
+        // kz > 0 terms doubled (real field), kz weights applied in the loop,
+        // beta once at the end; one twiddle load per kz serves every field
+        R val[NG3][4];
+        R at[NG1 > 0 ? NG1 : 1];
+        const CR* c0 = xb + xl * nkz;   // field f at c0[f * per + kz]
+        const CR* tz = TZ + z * tzs;
+#pragma unroll
+        for (int g = 0; g < NG3; ++g) val[g][0] = val[g][1] = val[g][2] = val[g][3] = 0;
+#pragma unroll
+        for (int i = 0; i < NG1; ++i) at[i] = 0;
+        R kzr = 0;
+        for (int kz = 1; kz < nkz; ++kz) {
+            const CR tw = tz[kz];
+            kzr += (R)1;
+#pragma unroll
+            for (int g = 0; g < NG3; ++g) {
+                const CR cV = c0[(3 * g) * per + kz], cA = c0[(3 * g + 1) * per + kz], cW = c0[(3 * g + 2) * per + kz];
+                val[g][0] = fmar(-cV.y, tw.y, fmar(cV.x, tw.x, val[g][0]));
+                val[g][3] = fmar(kzr, fmar(cV.y, tw.x, cV.x * tw.y), val[g][3]);
+                val[g][1] = fmar(-cA.y, tw.y, fmar(cA.x, tw.x, val[g][1]));
+                val[g][2] = fmar(-cW.y, tw.y, fmar(cW.x, tw.x, val[g][2]));
+            }
+#pragma unroll
+            for (int i = 0; i < NG1; ++i) {
+                const CR cc = c0[(3 * NG3 + i) * per + kz];
+                at[i] = fmar(-cc.y, tw.y, fmar(cc.x, tw.x, at[i]));
+            }
+        }
 #pragma unroll
         for (int g = 0; g < NG3; ++g) {
-            const CR* cV = xb + (3 * g) * per + xl * nkz;
-            const CR* cA = xb + (3 * g + 1) * per + xl * nkz;
-            const CR* cW = xb + (3 * g + 2) * per + xl * nkz;
-            R sV = 0, sZ = 0, sA = 0, sW = 0;
-            const CR* tz = TZ + z * tzs;
-            for (int kz = 1; kz < nkz; ++kz) {
-                const CR tw = tz[kz];
-                const CR t = cmul(cV[kz], tw);
-                sV += t.x;
-                sZ += beta * (R)kz * t.y;
-                sA += cmul(cA[kz], tw).x;
-                sW += cmul(cW[kz], tw).x;
-            }
-            val[g][0] = cV[0].x + two * sV;
-            val[g][1] = cA[0].x + two * sA;
-            val[g][2] = cW[0].x + two * sW;
-            val[g][3] = -two * sZ;
+            val[g][0] = c0[(3 * g) * per].x + two * val[g][0];
+            val[g][1] = c0[(3 * g + 1) * per].x + two * val[g][1];
+            val[g][2] = c0[(3 * g + 2) * per].x + two * val[g][2];
+            val[g][3] = -two * beta * val[g][3];
         }
+#pragma unroll
+        for (int i = 0; i < NG1; ++i) at[i] = c0[(3 * NG3 + i) * per].x + two * at[i];
         val[0][0] += yj;   // base flow u_b = y e_x
         val[0][2] += (R)1; // d(u_b)_x / dy = 1
         if (MODE == PLANE_FWD) {
@@ -803,15 +833,6 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
                 pb[i * pz + pt] = q;
             }
         } else {
-            R at[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const CR* cc = xb + (3 * NG3 + i) * per + xl * nkz;
-                R sr = 0;
-                const CR* tz = TZ + z * tzs;
-                for (int kz = 1; kz < nkz; ++kz) sr += cmul(cc[kz], tz[kz]).x;
-                at[i] = cc[0].x + two * sr;
-            }
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -881,10 +902,10 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
         for (int xl = 0; xl < XS; ++xl) {
             const CR tw = tx[xl * nkx];
 #pragma unroll
-            for (int f = 0; f < NIN; ++f) {
+            for (int f = 0; f < NIN; ++f) {   // (ar, ai) += v conj(tw)
                 const CR v = xb[f * per + xl * nkz + kz];
-                ar[f] += v.x * tw.x + v.y * tw.y;
-                ai[f] += v.y * tw.x - v.x * tw.y;
+                ar[f] = fmar(v.y, tw.y, fmar(v.x, tw.x, ar[f]));
+                ai[f] = fmar(-v.x, tw.y, fmar(v.y, tw.x, ai[f]));
             }
         }
         CR* o0 = out + ((size_t)s * NOUT * N + j) * nmB + mo + mm;   // output o at o0[o * N * nmB]
