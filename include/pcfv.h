@@ -169,7 +169,9 @@ typedef struct {
     double* dmd_buffer;
     /* Mixed precision: on a PCFV_MIXED context, once every guess has
      * ||r||/||u_b+u|| < fp64_below at a check, the rest of the call runs in
-     * FP64 (the refinement phase); <= 0 keeps the context's precision. */
+     * FP64 (the refinement phase); <= 0 keeps the context's precision.  The
+     * refinement steps equal those of a PCFV_FP64 context with the same launch
+     * shape (pcfv_get_tuning) bit for bit. */
     double fp64_below;
     /* Learned extrapolator (may be NULL): at the end of every DMD window its
      * proposal from the window's last model->window snapshots competes with
@@ -271,7 +273,8 @@ pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_e
 /* The launch shape in use (x-slab width, physical-space and per-mode work-group
  * sizes; any pointer may be NULL).  Without pcfv_autotune: the widest slab
  * that fits, up to 12 (16 when the context holds more than 1024 modes over all
- * guesses), 1024-thread physical-space groups and 256-thread per-mode groups. */
+ * guesses), 1024-thread physical-space groups (512 for FP64 contexts of at
+ * most 1024 modes) and 256-thread per-mode groups. */
 pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads, int* mode_threads);
 /* Sets the launch shape explicitly: xs must be one of the slab widths the
  * autotuner considers, plane_threads one of 256, 512, 768, 1024 and

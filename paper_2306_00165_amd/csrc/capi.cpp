@@ -97,7 +97,10 @@ KP base_kp(const pcfv_config& c) {
     }
     p.NS = c.Nx / p.XS;
     p.prec = c.precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
-    p.pthreads = 1024;
+    // 1024-thread physical-space groups, except FP64 launches with few modes:
+    // there 512 threads leave the registers for the inverse z transform to
+    // take two points per work item
+    p.pthreads = (p.prec == PREC_FP64 && p.nmB <= 1024) ? 512 : 1024;
     // per-mode groups of 256 threads (4 lanes per contraction row): their
     // contractions have no idle waves for Ny up to 64 and several groups share a CU
     p.mthreads = 256;
@@ -1077,6 +1080,7 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out)
     gl.pthreads = members[0]->kp.pthreads;
     long long group_modes = 0;
     for (int k = 0; k < n; ++k) group_modes += members[k]->kp.nmB;
+    if (group_modes > 1024) gl.pthreads = 1024;   // the single-context default for many modes
     gl.mthreads = members[0]->kp.mthreads;
     for (int k = 0; k < n; ++k) gl.np = std::max(gl.np, members[k]->kp.np);
     long long items[2] = {0, 0};

@@ -89,16 +89,6 @@ template <> __device__ __forceinline__ float2 narrow<float2>(double2 v) {
     return make_float2((float)v.x, (float)v.y);
 }
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-__device__ __forceinline__ double wmax(double v) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
-    return v;
-}
 
 // Work groups are dispatched to the 8 XCDs of the chip round-robin.  Launchers
 // pad the grid to a multiple of 8 and kernels map their work-group index w to
@@ -121,6 +111,70 @@ __device__ __forceinline__ MS mscal(const KP& p, int m) {
 template <int NP>
 __device__ __forceinline__ const double* mat(const KP& p, int id) {
     return p.M + (size_t)id * NP * mat_ld(NP);
+}
+
+
+// Sums over the lanes that share one output row of a contraction: lanes
+// MC<MT>::ROWS apart within the wave (8, 16, 32 apart for ROWS = 8; 16, 32 for
+// ROWS = 16).  The exchanges run on the VALU: a DPP rotation by 8 within each
+// 16-lane row and the gfx950 permlane16/permlane32 swaps, which exchange the
+// odd and even 16-lane rows and the two 32-lane halves.  Every lane of a row
+// group receives the same bits (the partners add the same two numbers).
+__device__ __forceinline__ double ror8_add(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x128, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x128, 0xf, 0xf, false);
+    return v + __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double swap16_add(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ __forceinline__ double swap32_add(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+// A double moved across lanes by a DPP pattern (both halves).
+template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double swap16_max(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return fmax(__hiloint2double((int)h[0], (int)l[0]), __hiloint2double((int)h[1], (int)l[1]));
+}
+__device__ __forceinline__ double swap32_max(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return fmax(__hiloint2double((int)h[0], (int)l[0]), __hiloint2double((int)h[1], (int)l[1]));
+}
+
+// Sum (maximum) over the 64 lanes of a wave, on the VALU: quad permutes
+// (lane xor 1, xor 2), rotations by 4 and 8 within each 16-lane row, then the
+// row swaps.  Every lane of the wave must be active; lane 0 holds the total
+// (every lane holds a total, summed in an order that may differ by lane).
+__device__ __forceinline__ double wsum(double v) {
+    v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x124>(v);   // row_ror:4
+    v += dpp_d<0x128>(v);   // row_ror:8
+    v = swap16_add(v);
+    return swap32_add(v);
+}
+__device__ __forceinline__ double wmax(double v) {
+    v = fmax(v, dpp_d<0xB1>(v));
+    v = fmax(v, dpp_d<0x4E>(v));
+    v = fmax(v, dpp_d<0x124>(v));
+    v = fmax(v, dpp_d<0x128>(v));
+    v = swap16_max(v);
+    return swap32_max(v);
 }
 
 // Block reduction of NV values per thread (deterministic order): every thread
@@ -165,29 +219,6 @@ __device__ void bmax(double (&v)[NV], double* red) {
     __syncthreads();
 }
 
-// Sums over the lanes that share one output row of a contraction: lanes
-// MC<MT>::ROWS apart within the wave (8, 16, 32 apart for ROWS = 8; 16, 32 for
-// ROWS = 16).  The exchanges run on the VALU: a DPP rotation by 8 within each
-// 16-lane row and the gfx950 permlane16/permlane32 swaps, which exchange the
-// odd and even 16-lane rows and the two 32-lane halves.  Every lane of a row
-// group receives the same bits (the partners add the same two numbers).
-__device__ __forceinline__ double ror8_add(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x128, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x128, 0xf, 0xf, false);
-    return v + __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double swap16_add(double v) {
-    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
-}
-__device__ __forceinline__ double swap32_add(double v) {
-    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
-}
 template <int MT> __device__ __forceinline__ double row_sum(double v) {
     static_assert(MC<MT>::ROWS == 8 || MC<MT>::ROWS == 16, "row groups of 8 or 16 lanes");
     if constexpr (MC<MT>::ROWS == 8) v = ror8_add(v);
@@ -775,72 +806,97 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
         inverse_x(std::false_type{});
     __syncthreads();
 
-    // inverse (complex-to-real) transform in z at each point, then the products
+    // inverse (complex-to-real) transform in z, then the products.  With Nz
+    // even a work item takes the points z and z + Nz/2 of one x: their
+    // twiddles differ by (-1)^kz, so sums over the odd and the even kz give
+    // both points from one pass over the coefficients.  Per velocity field the
+    // sums give U, dU/dx, dU/dy, dU/dz: Re of the kz sums, the kz > 0 terms
+    // doubled (real field), kz weights applied in the loop, beta at the end;
+    // one twiddle load per kz serves every field.
+    // The pairing needs a second set of sums: it is compiled where the
+    // registers allow it without spilling (FP32, or at most 512 threads).
     const R yj = (R)p.ygl[j];
-    for (int pt = tid; pt < pz; pt += PLANE_THREADS) {
-        const int xl = pt / Nz, z = pt - xl * Nz;
-        // U, dU/dx, dU/dy, dU/dz of each velocity field: Re of the kz sums, the
-        // kz > 0 terms doubled (real field), kz weights applied in the loop,
-        // beta once at the end; one twiddle load per kz serves every field
-        R val[NG3][4];
-        R at[NG1 > 0 ? NG1 : 1];
+    constexpr int NA = NG1 > 0 ? NG1 : 1;
+    constexpr bool PAIRABLE = sizeof(R) == 4 || PLANE_THREADS <= 512;
+    const bool pair = PAIRABLE && !(Nz & 1);
+    const int hz = pair ? Nz / 2 : Nz, npt = pair ? 2 : 1;
+    for (int it = tid; it < XS * hz; it += PLANE_THREADS) {
+        const int xl = it / hz, z = it - xl * hz;
         const CR* c0 = xb + xl * nkz;   // field f at c0[f * per + kz]
         const CR* tz = TZ + z * tzs;
+        R ve[NG3][4], vo[NG3][4], ae[NA], ao[NA];   // even- and odd-kz sums
 #pragma unroll
-        for (int g = 0; g < NG3; ++g) val[g][0] = val[g][1] = val[g][2] = val[g][3] = 0;
+        for (int g = 0; g < NG3; ++g)
 #pragma unroll
-        for (int i = 0; i < NG1; ++i) at[i] = 0;
-        R kzr = 0;
-        for (int kz = 1; kz < nkz; ++kz) {
+            for (int q = 0; q < 4; ++q) ve[g][q] = vo[g][q] = 0;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) ae[i] = ao[i] = 0;
+        auto term = [&](int kz, R (&v)[NG3][4], R (&a)[NA]) {
             const CR tw = tz[kz];
-            kzr += (R)1;
+            const R kzr = (R)kz;
 #pragma unroll
             for (int g = 0; g < NG3; ++g) {
                 const CR cV = c0[(3 * g) * per + kz], cA = c0[(3 * g + 1) * per + kz], cW = c0[(3 * g + 2) * per + kz];
-                val[g][0] = fmar(-cV.y, tw.y, fmar(cV.x, tw.x, val[g][0]));
-                val[g][3] = fmar(kzr, fmar(cV.y, tw.x, cV.x * tw.y), val[g][3]);
-                val[g][1] = fmar(-cA.y, tw.y, fmar(cA.x, tw.x, val[g][1]));
-                val[g][2] = fmar(-cW.y, tw.y, fmar(cW.x, tw.x, val[g][2]));
+                v[g][0] = fmar(-cV.y, tw.y, fmar(cV.x, tw.x, v[g][0]));
+                v[g][3] = fmar(kzr, fmar(cV.y, tw.x, cV.x * tw.y), v[g][3]);
+                v[g][1] = fmar(-cA.y, tw.y, fmar(cA.x, tw.x, v[g][1]));
+                v[g][2] = fmar(-cW.y, tw.y, fmar(cW.x, tw.x, v[g][2]));
             }
 #pragma unroll
             for (int i = 0; i < NG1; ++i) {
                 const CR cc = c0[(3 * NG3 + i) * per + kz];
-                at[i] = fmar(-cc.y, tw.y, fmar(cc.x, tw.x, at[i]));
+                a[i] = fmar(-cc.y, tw.y, fmar(cc.x, tw.x, a[i]));
+            }
+        };
+        for (int kz = 1; kz < nkz; kz += 2) {
+            term(kz, vo, ao);
+            if (kz + 1 < nkz) {
+                if constexpr (PAIRABLE)
+                    term(kz + 1, ve, ae);
+                else
+                    term(kz + 1, vo, ao);   // one point per item: a single set of sums
             }
         }
 #pragma unroll
-        for (int g = 0; g < NG3; ++g) {
-            val[g][0] = c0[(3 * g) * per].x + two * val[g][0];
-            val[g][1] = c0[(3 * g + 1) * per].x + two * val[g][1];
-            val[g][2] = c0[(3 * g + 2) * per].x + two * val[g][2];
-            val[g][3] = -two * beta * val[g][3];
-        }
+        for (int h = 0; h < 2; ++h) {   // h = 0: point z, h = 1: point z + Nz/2
+            if (h >= npt) break;
+            const R sg = h ? (R)-1 : (R)1;
+            const int pt = xl * Nz + z + h * hz;
+            R val[NG3][4], at[NA];
 #pragma unroll
-        for (int i = 0; i < NG1; ++i) at[i] = c0[(3 * NG3 + i) * per].x + two * at[i];
-        val[0][0] += yj;   // base flow u_b = y e_x
-        val[0][2] += (R)1; // d(u_b)_x / dy = 1
-        if (MODE == PLANE_FWD) {
+            for (int g = 0; g < NG3; ++g) {
+                val[g][0] = c0[(3 * g) * per].x + two * (ve[g][0] + sg * vo[g][0]);
+                val[g][1] = c0[(3 * g + 1) * per].x + two * (ve[g][1] + sg * vo[g][1]);
+                val[g][2] = c0[(3 * g + 2) * per].x + two * (ve[g][2] + sg * vo[g][2]);
+                val[g][3] = -two * beta * (ve[g][3] + sg * vo[g][3]);
+            }
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
-                pb[i * pz + pt] = val[0][0] * val[i][1] + val[1][0] * val[i][2] + val[2][0] * val[i][3];
-        } else if (MODE == PLANE_JVP) {
+            for (int i = 0; i < NG1; ++i) at[i] = c0[(3 * NG3 + i) * per].x + two * (ae[i] + sg * ao[i]);
+            val[0][0] += yj;   // base flow u_b = y e_x
+            val[0][2] += (R)1; // d(u_b)_x / dy = 1
+            if (MODE == PLANE_FWD) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                R q = 0;
+                for (int i = 0; i < 3; ++i)
+                    pb[i * pz + pt] = val[0][0] * val[i][1] + val[1][0] * val[i][2] + val[2][0] * val[i][3];
+            } else if (MODE == PLANE_JVP) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    R q = 0;
+#pragma unroll
+                    for (int jj = 0; jj < 3; ++jj)
+                        q += val[jj][0] * val[3 + i][1 + jj] + val[3 + jj][0] * val[i][1 + jj];
+                    pb[i * pz + pt] = q;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < 3; ++jj) pb[(3 * i + jj) * pz + pt] = val[jj][0] * at[i];
 #pragma unroll
                 for (int jj = 0; jj < 3; ++jj)
-                    q += val[jj][0] * val[3 + i][1 + jj] + val[3 + jj][0] * val[i][1 + jj];
-                pb[i * pz + pt] = q;
+                    pb[(9 + jj) * pz + pt] =
+                        val[0][1 + jj] * at[0] + val[1][1 + jj] * at[1] + val[2][1 + jj] * at[2];
             }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int jj = 0; jj < 3; ++jj) pb[(3 * i + jj) * pz + pt] = val[jj][0] * at[i];
-#pragma unroll
-            for (int jj = 0; jj < 3; ++jj)
-                pb[(9 + jj) * pz + pt] =
-                    val[0][1 + jj] * at[0] + val[1][1 + jj] * at[1] + val[2][1 + jj] * at[2];
         }
     }
     __syncthreads();

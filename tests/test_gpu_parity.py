@@ -430,14 +430,20 @@ def test_mixed_residual_adjoint_and_step(mixed_ctxs, name):
 
 def test_mixed_descent_refines_in_fp64(ctxs, mixed_ctxs):
     """fp64_below switches the rest of a call to FP64: always-below gives the
-    FP64 trajectory bit for bit, never-below stays FP32 throughout, and a
-    threshold met mid-run gives both phases; the context keeps its precision."""
+    trajectory of an FP64 context with the same launch shape bit for bit,
+    never-below stays FP32 throughout, and a threshold met mid-run gives both
+    phases; the context keeps its precision."""
     import torch
     g, m, c64 = ctxs("cfg1")
     _, _, c32 = mixed_ctxs("cfg1")
     u0 = torch.as_tensor(inputs.config1_guess()).to("cuda:0").contiguous()
     ref = u0.clone()
-    c64.descend(ref, max_steps=300, dtau=0.02, check_every=50)
+    shape64 = c64.tuning()
+    c64.set_tuning(*c32.tuning())
+    try:
+        c64.descend(ref, max_steps=300, dtau=0.02, check_every=50)
+    finally:
+        c64.set_tuning(*shape64)
     a = u0.clone()
     st, rep = c32.descend(a, max_steps=300, dtau=0.02, check_every=50, fp64_below=1e30)
     assert rep["steps_fp32"] == 0 and torch.equal(a, ref)
