@@ -275,11 +275,14 @@ __device__ __forceinline__ MatRegs<NP, MT> mat_fetch(const KP& p, int id, int no
     return m;
 }
 
-// y = A x for one complex vector, A = fixed matrix id.  x and y live in LDS
-// and must not alias; entries [nout, NP) of y are left untouched.  Caller
-// synchronises afterwards.
-template <int NP, int MT>
-__device__ __forceinline__ void mv(const KP& p, int id, int nout, const double2* x, double2* y) {
+// y = A x for one complex vector, A = fixed matrix id, x in LDS.  Row n of
+// the result goes to ep(n, y_n), called by one lane for every n < nout; the
+// row-to-thread map depends only on NP and MT, so an epilogue may read
+// entries [n] that the same thread stored in an earlier contraction's
+// epilogue without a barrier.  Caller synchronises before other threads read
+// what the epilogue stores.
+template <int NP, int MT, class EP>
+__device__ __forceinline__ void mv_ep(const KP& p, int id, int nout, const double2* x, EP&& ep) {
     typedef MC<MT> S;
     typedef MatRegs<NP, MT> A;
     const A m = mat_fetch<NP, MT>(p, id, nout);
@@ -299,14 +302,14 @@ __device__ __forceinline__ void mv(const KP& p, int id, int nout, const double2*
         }
         re = row_sum<MT>(re);
         im = row_sum<MT>(im);
-        if (q == 0 && n < nout) y[n] = c2(re, im);
+        if (q == 0 && n < nout) ep(n, c2(re, im));
     }
 }
 
-// The same matrix applied to three vectors.
-template <int NP, int MT>
-__device__ __forceinline__ void mv3(const KP& p, int id, int nout, const double2* x0, const double2* x1,
-                                    const double2* x2, double2* y0, double2* y1, double2* y2) {
+// The same matrix applied to three vectors; ep(n, y0_n, y1_n, y2_n).
+template <int NP, int MT, class EP>
+__device__ __forceinline__ void mv3_ep(const KP& p, int id, int nout, const double2* x0, const double2* x1,
+                                       const double2* x2, EP&& ep) {
     typedef MC<MT> S;
     typedef MatRegs<NP, MT> A;
     const A m = mat_fetch<NP, MT>(p, id, nout);
@@ -331,12 +334,23 @@ __device__ __forceinline__ void mv3(const KP& p, int id, int nout, const double2
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) acc[i] = row_sum<MT>(acc[i]);
-        if (q == 0 && n < nout) {
-            y0[n] = c2(acc[0], acc[1]);
-            y1[n] = c2(acc[2], acc[3]);
-            y2[n] = c2(acc[4], acc[5]);
-        }
+        if (q == 0 && n < nout) ep(n, c2(acc[0], acc[1]), c2(acc[2], acc[3]), c2(acc[4], acc[5]));
     }
+}
+
+// y = A x into LDS (x and y must not alias; entries [nout, NP) of y untouched).
+template <int NP, int MT>
+__device__ __forceinline__ void mv(const KP& p, int id, int nout, const double2* x, double2* y) {
+    mv_ep<NP, MT>(p, id, nout, x, [&](int n, double2 v) { y[n] = v; });
+}
+template <int NP, int MT>
+__device__ __forceinline__ void mv3(const KP& p, int id, int nout, const double2* x0, const double2* x1,
+                                    const double2* x2, double2* y0, double2* y1, double2* y2) {
+    mv3_ep<NP, MT>(p, id, nout, x0, x1, x2, [&](int n, double2 a, double2 b, double2 c) {
+        y0[n] = a;
+        y1[n] = b;
+        y2[n] = c;
+    });
 }
 
 // LDS of the per-mode kernels: MODE_VECS complex vectors at stride NP, then
@@ -426,7 +440,7 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
                        double* red) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
     double2 *Fh = w, *Fe = w + NP, *s1 = w + 2 * NP, *s2 = w + 3 * NP, *s3 = w + 4 * NP,
-            *s4 = w + 5 * NP, *t2 = w + 6 * NP, *v0 = w + 7 * NP, *Dv0 = w + 8 * NP, *eta = w + 9 * NP;
+            *t2 = w + 6 * NP, *v0 = w + 7 * NP, *Dv0 = w + 8 * NP, *eta = w + 9 * NP;
     const double* dH = p.dH + (size_t)m * N;
     const double* dP = p.dP + (size_t)m * N;
     for (int n = t; n < N; n += MT) {
@@ -435,17 +449,15 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
         Fe[n] = csub(imul(c.b, fx), imul(c.a, fz));
     }
     __syncthreads();
+    // the diagonal steps run in the epilogues: row n of each contraction is
+    // stored by the thread that stored row n of the earlier ones
     mv3<NP, MT>(p, M_PR, M, Fh, Fe, Fy, s1, s2, s3);
-    mv<NP, MT>(p, M_PRD, M, Fy, s4);
+    mv_ep<NP, MT>(p, M_PRD, M, Fy, [&](int n, double2 s4) {
+        s1[n] = cscl(-dP[n], cadd(s4, s1[n]));   // t1
+        s2[n] = cscl(dH[n], s2[n]);              // te
+    });
     __syncthreads();
-    for (int n = t; n < M; n += MT) {
-        s1[n] = cscl(-dP[n], cadd(s4[n], s1[n]));   // t1
-        s2[n] = cscl(dH[n], s2[n]);                 // te
-    }
-    __syncthreads();
-    mv<NP, MT>(p, M_PRDPL, M, s1, t2);
-    __syncthreads();
-    for (int n = t; n < M; n += MT) t2[n] = cscl(dH[n], csub(s3[n], t2[n]));
+    mv_ep<NP, MT>(p, M_PRDPL, M, s1, [&](int n, double2 v) { t2[n] = cscl(dH[n], csub(s3[n], v)); });
     __syncthreads();
     mv<NP, MT>(p, M_PL, N, t2, v0);
     mv<NP, MT>(p, M_DPL, N, t2, Dv0);
@@ -540,20 +552,16 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
     }
     __syncthreads();
     mv<NP, MT>(p, M_PLT, M, bv0, bt2);
-    mv<NP, MT>(p, M_DPLT, M, bDv0, tmp);
-    mv<NP, MT>(p, M_PLT, M, beta, bte);
-    __syncthreads();
-    for (int n = t; n < M; n += MT) {
-        bt2[n] = cscl(dH[n], cadd(bt2[n], tmp[n]));   // u2 = dH (PL^T bv0 + DPL^T bDv0)
-        bte[n] = cscl(dH[n], bte[n]);                 // bs2
-    }
-    __syncthreads();
-    mv<NP, MT>(p, M_PRDPLT, M, bt2, tmp);
+    mv_ep<NP, MT>(p, M_DPLT, M, bDv0, [&](int n, double2 v) {
+        bt2[n] = cscl(dH[n], cadd(bt2[n], v));   // u2 = dH (PL^T bv0 + DPL^T bDv0)
+    });
+    mv_ep<NP, MT>(p, M_PLT, M, beta, [&](int n, double2 v) { bte[n] = cscl(dH[n], v); });   // bs2
     __syncthreads();
     const double2 bp0last = cscl(2.0 * (N - 1), be[2]);
     const double* PLlast = mat<NP>(p, M_PL) + (N - 1);
-    for (int n = t; n < M; n += MT)   // bs1 = -dP (Pl[N-1,:] bp0last - PRDPL^T u2)
-        tmp[n] = cscl(-dP[n], csub(cscl(PLlast[(size_t)n * mat_ld(NP)], bp0last), tmp[n]));
+    mv_ep<NP, MT>(p, M_PRDPLT, M, bt2, [&](int n, double2 v) {   // bs1 = -dP (Pl[N-1,:] bp0last - PRDPL^T u2)
+        tmp[n] = cscl(-dP[n], csub(cscl(PLlast[(size_t)n * mat_ld(NP)], bp0last), v));
+    });
     __syncthreads();
     mv3<NP, MT>(p, M_PRT, M, tmp, bte, bt2, bFh, bFe, bFy);
     mv<NP, MT>(p, M_PRDT, N, tmp, bFy2);
@@ -635,14 +643,10 @@ __device__ void project(const KP& p, int m, const MS& c, const double2* gx, cons
     }
     __syncthreads();
     mv<NP, MT>(p, M_DTG, N, gh, t1);
-    mv<NP, MT>(p, M_G, N, gy, t2);
+    mv_ep<NP, MT>(p, M_G, N, gy, [&](int n, double2 v) { t2[n] = csub(v, cscl(c.ik2, t1[n])); });
     mv<NP, MT>(p, M_PID, N, ge, eta);
     __syncthreads();
-    for (int n = t; n < N; n += MT) t2[n] = csub(t2[n], cscl(c.ik2, t1[n]));
-    __syncthreads();
-    mv<NP, MT>(p, M_PVLT, N - 4, t2, t4);
-    __syncthreads();
-    for (int n = t; n < N - 4; n += MT) t4[n] = cscl(dq[n], t4[n]);
+    mv_ep<NP, MT>(p, M_PVLT, N - 4, t2, [&](int n, double2 v) { t4[n] = cscl(dq[n], v); });
     __syncthreads();
     mv<NP, MT>(p, M_PVL, N, t4, v);
     mv<NP, MT>(p, M_DPVL, N, t4, Dv);
@@ -1002,13 +1006,14 @@ __device__ __forceinline__ void mode_res_body(
         sum_partials<NP, MT, 3>(p, P3, mB, vec(0));
         __syncthreads();
         mv3<NP, MT>(p, M_CINV, N, vec(0), vec(1), vec(2), vec(6), vec(7), vec(8));
-        mv3<NP, MT>(p, M_D2, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
-        __syncthreads();
-        for (int i = 0; i < 3; ++i)
-            for (int n = t; n < N; n += MT) {
-                const double2 L = csub(vec(12 + i)[n], cscl(c.k2, vec(3 + i)[n]));
+        mv3_ep<NP, MT>(p, M_D2, N, vec(3), vec(4), vec(5), [&](int n, double2 d0, double2 d1, double2 d2) {
+            const double2 d[3] = {d0, d1, d2};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {   // F = -(advection) + nu L u, L = D^2 - k^2
+                const double2 L = csub(d[i], cscl(c.k2, vec(3 + i)[n]));
                 vec(6 + i)[n] = cadd(cscl(-1.0, vec(6 + i)[n]), cscl(p.nu, L));
             }
+        });
         __syncthreads();
         if (zero)
             stokes0<NP, MT>(p, vec(6), vec(8), R0, R1, R2, vec(12));
@@ -1068,14 +1073,15 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
     __syncthreads();
     mv3<NP, MT>(p, M_MA, N, vec(0), vec(1), vec(2), vec(9), vec(10), vec(11));
     mv3<NP, MT>(p, M_MB, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
-    mv3<NP, MT>(p, M_ML, N, vec(6), vec(7), vec(8), vec(15), vec(16), vec(17));
-    __syncthreads();
-    for (int i = 0; i < 3; ++i)
-        for (int n = t; n < N; n += MT) {
+    mv3_ep<NP, MT>(p, M_ML, N, vec(6), vec(7), vec(8), [&](int n, double2 l0, double2 l1, double2 l2) {
+        const double2 l[3] = {l0, l1, l2};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {   // g = lam (nu L* a - M'* a)
             const double2 adv = cadd(vec(9 + i)[n], vec(12 + i)[n]);
-            const double2 lap = csub(vec(15 + i)[n], cscl(c.k2, vec(6 + i)[n]));
+            const double2 lap = csub(l[i], cscl(c.k2, vec(6 + i)[n]));
             vec(9 + i)[n] = cscl(p.lam, csub(cscl(p.nu, lap), adv));
         }
+    });
     __syncthreads();
     double2 *F0 = vec(9), *F1 = vec(10), *F2 = vec(11);
     if (flags & GRAD_PROJECT) {
