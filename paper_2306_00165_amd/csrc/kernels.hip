@@ -364,6 +364,57 @@ __device__ __forceinline__ double2* mode_vectors() {
     return sm;
 }
 
+// Per-mode tables of the solves and the projection, staged in LDS after the
+// mode vectors (then the block-reduction scratch): dH, dP (NP each), the
+// homogeneous responses Vk, DVk (4 rows of NP), the 4 x 4 inverse influence
+// matrix and the projection diagonal dq (NP).  Read from LDS, they cost no
+// global round trip in the middle of a solve, where a barrier would keep the
+// compiler from loading them early.
+constexpr int tab_doubles(int np) { return 11 * np + 16; }
+struct ModeTabs {
+    const double *dH, *dP, *Vk, *DVk, *Ai, *dq;
+};
+template <int NP>
+__device__ __forceinline__ double* mode_tab(double2* vs) { return reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP); }
+template <int NP>
+__device__ __forceinline__ double* mode_red(double2* vs) { return mode_tab<NP>(vs) + tab_doubles(NP); }
+
+// Mode m's tables into LDS (solve: dH, dP, Vk, DVk, Ainv; proj: dq), each
+// thread's loads issued together; the caller's next barrier publishes them.
+template <int NP, int MT>
+__device__ __forceinline__ ModeTabs stage_tabs(const KP& p, int m, double* tab, bool solve, bool proj) {
+    const int N = p.N;
+    double *dH = tab, *dP = tab + NP, *Vk = tab + 2 * NP, *DVk = tab + 6 * NP, *Ai = tab + 10 * NP,
+           *dq = tab + 10 * NP + 16;
+    const size_t mN = (size_t)m * N;
+    for (int n = threadIdx.x; n < max(N, 16); n += MT) {
+        double h = 0, q = 0, r = 0, a = 0, v[4] = {0, 0, 0, 0}, dv[4] = {0, 0, 0, 0};
+        if (solve && n < N) {
+            h = p.dH[mN + n];
+            q = p.dP[mN + n];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[k] = p.Vk[4 * mN + (size_t)k * N + n];
+                dv[k] = p.DVk[4 * mN + (size_t)k * N + n];
+            }
+        }
+        if (solve && n < 16) a = p.Ainv[(size_t)m * 16 + n];
+        if (proj && n < N) r = p.dproj[mN + n];
+        if (solve && n < N) {
+            dH[n] = h;
+            dP[n] = q;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                Vk[k * NP + n] = v[k];
+                DVk[k * NP + n] = dv[k];
+            }
+        }
+        if (solve && n < 16) Ai[n] = a;
+        if (proj && n < N) dq[n] = r;
+    }
+    return {dH, dP, Vk, DVk, Ai, dq};
+}
+
 // The per-mode kernels read a few values per thread from global memory before
 // their first contraction.  The helpers below issue all of a thread's loads
 // before the first use, so their latencies overlap instead of adding up.
@@ -435,14 +486,14 @@ __device__ __forceinline__ void sum_partials(const KP& p, const YT* __restrict__
 // w: 10 scratch vectors.
 // ---------------------------------------------------------------------------
 template <int NP, int MT>
-__device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const double2* Fy,
+__device__ void stokes(const KP& p, const ModeTabs& T, const MS& c, const double2* Fx, const double2* Fy,
                        const double2* Fz, double2* ox, double2* oy, double2* oz, double2* w,
                        double* red) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
     double2 *Fh = w, *Fe = w + NP, *s1 = w + 2 * NP, *s2 = w + 3 * NP, *s3 = w + 4 * NP,
             *t2 = w + 6 * NP, *v0 = w + 7 * NP, *Dv0 = w + 8 * NP, *eta = w + 9 * NP;
-    const double* dH = p.dH + (size_t)m * N;
-    const double* dP = p.dP + (size_t)m * N;
+    const double* dH = T.dH;
+    const double* dP = T.dP;
     for (int n = t; n < N; n += MT) {
         const double2 fx = Fx[n], fz = Fz[n];
         Fh[n] = cadd(imul(c.a, fx), imul(c.b, fz));
@@ -481,7 +532,7 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
     const double tn = 2.0 * (N - 1);
     const double2 e2 = csub(cadd(cscl(c.sig, v0[N - 2]), cscl(tn, p0last)), Fy[N - 2]);
     const double2 e3 = csub(cscl(c.sig, v0[N - 1]), Fy[N - 1]);
-    const double* Ai = p.Ainv + (size_t)m * 16;
+    const double* Ai = T.Ai;
     double2 cc[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -489,14 +540,14 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
                           cadd(cscl(Ai[4 * k + 2], e2), cscl(Ai[4 * k + 3], e3)));
         cc[k] = cscl(-1.0, sk);
     }
-    const double* Vk = p.Vk + (size_t)m * 4 * N;
-    const double* DVk = p.DVk + (size_t)m * 4 * N;
+    const double* Vk = T.Vk;     // row k at Vk[k * NP]
+    const double* DVk = T.DVk;
     for (int n = t; n < N; n += MT) {
         double2 v = v0[n], Dv = Dv0[n];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            v = cadd(v, cscl(Vk[k * N + n], cc[k]));
-            Dv = cadd(Dv, cscl(DVk[k * N + n], cc[k]));
+            v = cadd(v, cscl(Vk[k * NP + n], cc[k]));
+            Dv = cadd(Dv, cscl(DVk[k * NP + n], cc[k]));
         }
         const double2 e = eta[n];
         ox[n] = cscl(c.ik2, csub(imul(c.a, Dv), imul(c.b, e)));
@@ -510,17 +561,17 @@ __device__ void stokes(const KP& p, int m, const MS& c, const double2* Fx, const
 // above run backwards with every matrix transposed (three contraction phases).
 // w: 11 scratch vectors.
 template <int NP, int MT>
-__device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, const double2* xv,
+__device__ void stokes_h(const KP& p, const ModeTabs& T, const MS& c, const double2* xu, const double2* xv,
                          const double2* xw, double2* yx, double2* yy, double2* yz,
                          double2* w, double* red) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
     double2 *bDv = w, *beta = w + NP, *bv0 = w + 2 * NP, *bDv0 = w + 3 * NP, *bt2 = w + 4 * NP,
             *tmp = w + 5 * NP, *bte = w + 6 * NP, *bFh = w + 7 * NP, *bFe = w + 8 * NP,
             *bFy = w + 9 * NP, *bFy2 = w + 10 * NP;
-    const double* dH = p.dH + (size_t)m * N;
-    const double* dP = p.dP + (size_t)m * N;
-    const double* Vk = p.Vk + (size_t)m * 4 * N;
-    const double* DVk = p.DVk + (size_t)m * 4 * N;
+    const double* dH = T.dH;
+    const double* dP = T.dP;
+    const double* Vk = T.Vk;     // row k at Vk[k * NP]
+    const double* DVk = T.DVk;
     double dots[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int n = t; n < N; n += MT) {
         const double2 a0 = xu[n], a2 = xw[n], bv = xv[n];
@@ -529,12 +580,12 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
         beta[n] = cscl(c.ik2, csub(imul(c.b, a0), imul(c.a, a2)));
 #pragma unroll
         for (int k = 0; k < 4; ++k) {   // v = v0 + Vk^T c and Dv = Dv0 + DVk^T c
-            dots[2 * k] += Vk[k * N + n] * bv.x + DVk[k * N + n] * bd.x;
-            dots[2 * k + 1] += Vk[k * N + n] * bv.y + DVk[k * N + n] * bd.y;
+            dots[2 * k] += Vk[k * NP + n] * bv.x + DVk[k * NP + n] * bd.x;
+            dots[2 * k + 1] += Vk[k * NP + n] * bv.y + DVk[k * NP + n] * bd.y;
         }
     }
     bsum<MT>(dots, red);
-    const double* Ai = p.Ainv + (size_t)m * 16;
+    const double* Ai = T.Ai;
     double2 be[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -579,11 +630,11 @@ __device__ void stokes_h(const KP& p, int m, const MS& c, const double2* xu, con
 }
 
 template <int NP, int MT>
-__device__ void stokes0(const KP& p, const double2* Fx, const double2* Fz, double2* ox,
+__device__ void stokes0(const KP& p, const ModeTabs& T, const double2* Fx, const double2* Fz, double2* ox,
                         double2* oy, double2* oz, double2* w) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
     double2 *t1 = w, *t2 = w + NP;
-    const double* dH = p.dH;
+    const double* dH = T.dH;
     mv<NP, MT>(p, M_PR, M, Fx, t1);
     mv<NP, MT>(p, M_PR, M, Fz, t2);
     __syncthreads();
@@ -599,11 +650,11 @@ __device__ void stokes0(const KP& p, const double2* Fx, const double2* Fz, doubl
 }
 
 template <int NP, int MT>
-__device__ void stokes0_h(const KP& p, const double2* xu, const double2* xw, double2* yx,
+__device__ void stokes0_h(const KP& p, const ModeTabs& T, const double2* xu, const double2* xw, double2* yx,
                           double2* yy, double2* yz, double2* w) {
     const int N = p.N, M = N - 2, t = threadIdx.x;
     double2 *t1 = w, *t2 = w + NP;
-    const double* dH = p.dH;
+    const double* dH = T.dH;
     mv<NP, MT>(p, M_PLT, M, xu, t1);
     mv<NP, MT>(p, M_PLT, M, xw, t2);
     __syncthreads();
@@ -630,12 +681,12 @@ __device__ void stokes0_h(const KP& p, const double2* xu, const double2* xw, dou
 // is diagonalised by fixed vectors X with diagonal 1/(1 + Lambda/kappa^2).
 // Three contraction phases.  w: 8 scratch vectors.
 template <int NP, int MT>
-__device__ void project(const KP& p, int m, const MS& c, const double2* gx, const double2* gy,
+__device__ void project(const KP& p, const ModeTabs& T, const MS& c, const double2* gx, const double2* gy,
                         const double2* gz, double2* ox, double2* oy, double2* oz, double2* w) {
     const int N = p.N, t = threadIdx.x;
     double2 *gh = w, *ge = w + NP, *t1 = w + 2 * NP, *t2 = w + 3 * NP, *t4 = w + 4 * NP,
             *v = w + 5 * NP, *eta = w + 6 * NP, *Dv = w + 7 * NP;
-    const double* dq = p.dproj + (size_t)m * N;
+    const double* dq = T.dq;
     for (int n = t; n < N; n += MT) {
         const double2 x = gx[n], z = gz[n];
         gh[n] = cadd(imul(c.a, x), imul(c.b, z));
@@ -994,10 +1045,11 @@ __device__ __forceinline__ void mode_res_body(
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     double2* const vs = mode_vectors<NP, MT>();
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
-    double* red = reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP);
+    double* red = mode_red<NP>(vs);
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
     double2 *R0 = vec(9), *R1 = vec(10), *R2 = vec(11);
+    const ModeTabs T = stage_tabs<NP, MT>(p, m, mode_tab<NP>(vs), true, false);   // published by the next barrier
     if (flags & RES_INPUT_W) {
         read_field3<MT>(p, u, so, m, vec(9), vec(10), vec(11));
         __syncthreads();
@@ -1016,9 +1068,9 @@ __device__ __forceinline__ void mode_res_body(
         });
         __syncthreads();
         if (zero)
-            stokes0<NP, MT>(p, vec(6), vec(8), R0, R1, R2, vec(12));
+            stokes0<NP, MT>(p, T, vec(6), vec(8), R0, R1, R2, vec(12));
         else
-            stokes<NP, MT>(p, m, c, vec(6), vec(7), vec(8), R0, R1, R2, vec(12), red);
+            stokes<NP, MT>(p, T, c, vec(6), vec(7), vec(8), R0, R1, R2, vec(12), red);
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MT) {
                 const double2 v = cscl(p.lam, vec(9 + i)[n]);
@@ -1043,9 +1095,9 @@ __device__ __forceinline__ void mode_res_body(
     }
     if (!(flags & RES_ADJ)) return;
     if (zero)
-        stokes0_h<NP, MT>(p, vec(3), vec(5), vec(6), vec(7), vec(8), vec(12));
+        stokes0_h<NP, MT>(p, T, vec(3), vec(5), vec(6), vec(7), vec(8), vec(12));
     else
-        stokes_h<NP, MT>(p, m, c, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8), vec(12), red);
+        stokes_h<NP, MT>(p, T, c, vec(3), vec(4), vec(5), vec(6), vec(7), vec(8), vec(12), red);
     mv3<NP, MT>(p, M_GINV, N, vec(6), vec(7), vec(8), vec(0), vec(1), vec(2));
     mv3<NP, MT>(p, M_CINVT, N, vec(6), vec(7), vec(8), vec(12), vec(13), vec(14));
     __syncthreads();
@@ -1068,6 +1120,7 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
+    const ModeTabs T = stage_tabs<NP, MT>(p, m, mode_tab<NP>(vs), false, (flags & GRAD_PROJECT) != 0);
     read_field3<MT>(p, a, so, m, vec(6), vec(7), vec(8));
     sum_partials<NP, MT, 6>(p, P6, mB, vec(0));
     __syncthreads();
@@ -1088,7 +1141,7 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
         if (zero)
             project0<NP, MT>(p, vec(9), vec(11), vec(0), vec(1), vec(2));
         else
-            project<NP, MT>(p, m, c, vec(9), vec(10), vec(11), vec(0), vec(1), vec(2), vec(12));
+            project<NP, MT>(p, T, c, vec(9), vec(10), vec(11), vec(0), vec(1), vec(2), vec(12));
         for (int i = 0; i < 3; ++i)
             for (int n = t; n < N; n += MT) vec(i)[n] = cscl(-1.0, vec(i)[n]);
         __syncthreads();
@@ -1221,12 +1274,13 @@ __global__ __launch_bounds__(MT) void k_project(KP p, const double2* __restrict_
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     double2* const vs = mode_vectors<NP, MT>();
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
+    const ModeTabs T = stage_tabs<NP, MT>(p, m, mode_tab<NP>(vs), false, true);
     read_field3<MT>(p, g, so, m, vec(0), vec(1), vec(2));
     __syncthreads();
     if (m == 0)
         project0<NP, MT>(p, vec(0), vec(2), vec(3), vec(4), vec(5));
     else
-        project<NP, MT>(p, m, mscal(p, m), vec(0), vec(1), vec(2), vec(3), vec(4), vec(5), vec(12));
+        project<NP, MT>(p, T, mscal(p, m), vec(0), vec(1), vec(2), vec(3), vec(4), vec(5), vec(12));
     for (int i = 0; i < 3; ++i)
         for (int n = t; n < N; n += MT) out[so + ((size_t)i * nm + m) * N + n] = vec(3 + i)[n];
 }
@@ -1268,7 +1322,7 @@ __global__ __launch_bounds__(MT) void k_norms(KP p, const double2* __restrict__ 
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     double2* const vs = mode_vectors<NP, MT>();
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
-    double* red = reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP);
+    double* red = mode_red<NP>(vs);
     const MS c = mscal(p, m);
     read_field3<MT>(p, u, so, m, vec(0), vec(1), vec(2));
     __syncthreads();
@@ -1332,7 +1386,7 @@ __global__ __launch_bounds__(MT) void k_check(KP p, const double2* __restrict__ 
     const size_t so = (size_t)b * 3 * nm * N; // offset of this guess in spectral arrays
     double2* const vs = mode_vectors<NP, MT>();
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
-    double* red = reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP);
+    double* red = mode_red<NP>(vs);
     const MS c = mscal(p, m);
     read_field3<MT>(p, u, so, m, vec(0), vec(1), vec(2));
     __syncthreads();
@@ -1435,7 +1489,7 @@ __global__ __launch_bounds__(MT) void k_unpack(KP p, const double* __restrict__ 
     if (idx < 0) return;
     double2* const vs = mode_vectors<NP, MT>();
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
-    double* red = reinterpret_cast<double*>(vs + (size_t)MODE_VECS * NP);
+    double* red = mode_red<NP>(vs);
     if (m == 0) {
         for (int n = t; n < N; n += MT) {
             vec(0)[n] = c2(n < N - 2 ? psi[(size_t)b * p.nstate + n] : 0.0, 0);
@@ -1603,7 +1657,7 @@ size_t plane_lds_bytes(const KP& p, int mode) {
 }
 
 size_t mode_lds_bytes(const KP& p) {
-    return (size_t)MODE_VECS * p.np * 16 + (size_t)(p.mthreads / WAVE) * RED_SLOTS * 8;
+    return (size_t)MODE_VECS * p.np * 16 + (size_t)tab_doubles(p.np) * 8 + (size_t)(p.mthreads / WAVE) * RED_SLOTS * 8;
 }
 
 static dim3 mode_grid(const KP& p) { return dim3((unsigned)((p.nmB + NXCD - 1) / NXCD * NXCD)); }
