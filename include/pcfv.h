@@ -254,8 +254,8 @@ const char* pcfv_last_error(const pcfv_ctx* ctx);
 
 /* Autotuner over the launch shapes: for every candidate x-slab width of the
  * physical-space kernels (divisors of Nx up to 16 whose staging fits the
- * 160 KiB of LDS a work group may use, at least half the default), their work-group size (256, 512, 768, 1024
- * threads) and the
+ * 160 KiB of LDS a work group may use, at least half the default), their work-group size (256, 512, 576, 768,
+ * 1024 threads) and the
  * per-mode kernels' work-group size (256 threads with 4 lanes per contraction
  * row, 512 with 8) it times
  * `steps` descent steps (after one untimed step) on a scratch copy of u with
@@ -273,11 +273,11 @@ pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_e
 /* The launch shape in use (x-slab width, physical-space and per-mode work-group
  * sizes; any pointer may be NULL).  Without pcfv_autotune: the widest slab
  * that fits, up to 12 (16 when the context holds more than 1024 modes over all
- * guesses), 1024-thread physical-space groups (512 for FP64 contexts of at
+ * guesses), 1024-thread physical-space groups (576 for FP64 contexts of at
  * most 1024 modes) and 256-thread per-mode groups. */
 pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads, int* mode_threads);
 /* Sets the launch shape explicitly: xs must be one of the slab widths the
- * autotuner considers, plane_threads one of 256, 512, 768, 1024 and
+ * autotuner considers, plane_threads one of 256, 512, 576, 768, 1024 and
  * mode_threads 256 or 512; anything else returns PCFV_EINVAL and leaves the
  * shape unchanged.  Results do not depend on the shape beyond rounding. */
 pcfv_status pcfv_set_tuning(pcfv_ctx* ctx, int xs, int plane_threads, int mode_threads);

@@ -98,9 +98,9 @@ KP base_kp(const pcfv_config& c) {
     p.NS = c.Nx / p.XS;
     p.prec = c.precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
     // 1024-thread physical-space groups, except FP64 launches with few modes:
-    // there 512 threads leave the registers for the inverse z transform to
-    // take two points per work item
-    p.pthreads = (p.prec == PREC_FP64 && p.nmB <= 1024) ? 512 : 1024;
+    // there 576 threads (9 waves) leave the registers for the inverse z
+    // transform to take two points per work item
+    p.pthreads = (p.prec == PREC_FP64 && p.nmB <= 1024) ? 576 : 1024;
     // per-mode groups of 256 threads (4 lanes per contraction row): their
     // contractions have no idle waves for Ny up to 64 and several groups share a CU
     p.mthreads = 256;
@@ -937,8 +937,9 @@ pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_e
     KP best_kp = saved;
     pcfv_status st = PCFV_OK;
     for (int xs : xs_candidates(ctx->cfg)) {
-        for (int cand = 0; cand < 8; ++cand) {
-            const int nt = 256 * (1 + (cand & 3)), mt = (cand & 4) ? 512 : 256;
+        static const int kPlaneThreads[] = {256, 512, 576, 768, 1024};
+        for (int cand = 0; cand < 10; ++cand) {
+            const int nt = kPlaneThreads[cand % 5], mt = (cand < 5) ? 256 : 512;
             ctx->kp.XS = xs;
             ctx->kp.NS = ctx->cfg.Nx / xs;
             ctx->kp.pthreads = nt;
@@ -979,8 +980,9 @@ pcfv_status pcfv_set_tuning(pcfv_ctx* ctx, int xs, int plane_threads, int mode_t
     const std::vector<int> xsc = xs_candidates(ctx->cfg);
     if (std::find(xsc.begin(), xsc.end(), xs) == xsc.end())
         return fail(ctx, PCFV_EINVAL, "slab width is not one of the candidates");
-    if (plane_threads != 256 && plane_threads != 512 && plane_threads != 768 && plane_threads != 1024)
-        return fail(ctx, PCFV_EINVAL, "plane_threads must be 256, 512, 768 or 1024");
+    if (plane_threads != 256 && plane_threads != 512 && plane_threads != 576 && plane_threads != 768 &&
+        plane_threads != 1024)
+        return fail(ctx, PCFV_EINVAL, "plane_threads must be 256, 512, 576, 768 or 1024");
     if (mode_threads != 256 && mode_threads != 512) return fail(ctx, PCFV_EINVAL, "mode_threads must be 256 or 512");
     ctx->kp.XS = xs;
     ctx->kp.NS = ctx->cfg.Nx / xs;

@@ -869,10 +869,10 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     // doubled (real field), kz weights applied in the loop, beta at the end;
     // one twiddle load per kz serves every field.
     // The pairing needs a second set of sums: it is compiled where the
-    // registers allow it without spilling (FP32, or at most 512 threads).
+    // registers allow it without spilling (FP32, or at most 576 threads).
     const R yj = (R)p.ygl[j];
     constexpr int NA = NG1 > 0 ? NG1 : 1;
-    constexpr bool PAIRABLE = sizeof(R) == 4 || PLANE_THREADS <= 512;
+    constexpr bool PAIRABLE = sizeof(R) == 4 || PLANE_THREADS <= 576;
     const bool pair = PAIRABLE && !(Nz & 1);
     const int hz = pair ? Nz / 2 : Nz, npt = pair ? 2 : 1;
     for (int it = tid; it < XS * hz; it += PLANE_THREADS) {
@@ -1737,6 +1737,7 @@ static hipError_t plane_t(const KP& p, hipStream_t s, int mode, const void* Y1, 
     switch (nt) {                                                   \
         case 256: { constexpr int NT = 256; __VA_ARGS__; } break;   \
         case 512: { constexpr int NT = 512; __VA_ARGS__; } break;   \
+        case 576: { constexpr int NT = 576; __VA_ARGS__; } break;   \
         case 768: { constexpr int NT = 768; __VA_ARGS__; } break;   \
         case 1024: { constexpr int NT = 1024; __VA_ARGS__; } break; \
         default: return hipErrorInvalidValue;                       \

@@ -13,7 +13,7 @@ struct KP {
     long long nstate;        // state-vector length of one guess
     int XS, NS;              // x-slab width of the physical-space kernels, number of slabs
     int prec;                // PREC_FP64, or PREC_FP32 for the physical-space transforms and products
-    int pthreads;            // threads per work group of the physical-space kernels (256, 512, 768, 1024)
+    int pthreads;            // threads per work group of the physical-space kernels (256, 512, 576, 768, 1024)
     int mthreads;            // threads per work group of the per-mode kernels (256 or 512)
     int stage;               // physical-space kernels stage the plane's y-values in LDS (0/1)
     int np;                  // padded Ny of the per-mode kernels: stride of M and of their LDS vectors

@@ -543,7 +543,7 @@ def test_autotune_keeps_parity(ctxs):
     c = Context(32, 33, 32)
     u = guess(g, 9)
     ent = c.autotune(u, steps=5)
-    assert ent and all(32 % xs == 0 and nt in (256, 512, 768, 1024) and mt in (256, 512) for xs, nt, mt, _ in ent)
+    assert ent and all(32 % xs == 0 and nt in (256, 512, 576, 768, 1024) and mt in (256, 512) for xs, nt, mt, _ in ent)
     best = min(ent, key=lambda e: e[3])
     assert c.tuning() == best[:3]
     print(f"[gpu] autotune 32x33x32: {ent}")
@@ -562,7 +562,7 @@ def shape_ctx():
     return g, Method(g), Context(48, 49, 48)
 
 
-@pytest.mark.parametrize("xs,nt,mt", [(12, 256, 512), (12, 512, 256), (12, 768, 512), (12, 1024, 512),
+@pytest.mark.parametrize("xs,nt,mt", [(12, 256, 512), (12, 512, 256), (12, 576, 256), (12, 768, 512), (12, 1024, 512),
                                       (8, 768, 256), (6, 1024, 256), (16, 1024, 512)])
 def test_every_launch_shape_matches_oracle(shape_ctx, xs, nt, mt):
     """Residual, adjoint and one descent step at 48x49x48 with each pinned
