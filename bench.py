@@ -253,8 +253,8 @@ def main():
         run_cpu_baseline_only(args.cpu_seconds)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU "
-              "sharding is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the descent "
+              "across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         run_copy_calibration()

@@ -27,14 +27,13 @@ namespace pcfv {
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int MODE_VECS = 24;                  // LDS vectors (length N) used by the mode kernels
+constexpr int MODE_VECS = 24;                  // LDS vectors (stride NP) used by the mode kernels
 constexpr int RED_SLOTS = 16;                  // doubles per wave for block reductions
 
 // Work-group shapes of the per-mode kernels (one Fourier mode per work group):
 // MT threads; every output row of a contraction is summed by KS lanes of a
-// wave, ROWS rows per wave.  256 threads with KS = 4 suit many modes per
-// launch (throughput); 512 threads with KS = 8 halve each lane's serial
-// chain for few modes per launch (latency).
+// wave, ROWS rows per wave.  256 threads with KS = 4 (the default) or 512
+// threads with KS = 8 (half of each lane's serial chain, twice the waves).
 template <int MT> struct MC {
     static constexpr int THREADS = MT, WAVES = MT / WAVE, KS = (MT >= 512) ? 8 : 4, ROWS = WAVE / KS;
 };
