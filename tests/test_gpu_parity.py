@@ -514,6 +514,30 @@ def test_group_of_uneven_grids_matches_each_member(precision):
         assert rel(to_np(plain[1]), u) < TOL
 
 
+def test_group_of_many_modes_matches_oracle():
+    """A group of more than 1024 modes (3 guesses at 48x49x48 + 2 at 32x33x32)
+    runs its throughput shape (1024-thread plane groups, widest slabs, no
+    staging, the smaller member's tables re-padded to the group's Ny); two
+    steps of one guess of each member match the oracle."""
+    import torch
+    from paper_2306_00165_amd.pcfv import Context, Group
+    specs = [((48, 49, 48), 3, 0.012), ((32, 33, 32), 2, 0.02)]
+    ctxs_, fields, refs = [], [], []
+    for i, (dims, B, dt) in enumerate(specs):
+        us = [inputs.random_field(*dims, energy=1e-3, seed=80 + 5 * i + b) for b in range(B)]
+        ctxs_.append(Context(*dims, batch=B))
+        fields.append(torch.as_tensor(np.stack(us)).to("cuda:0").contiguous())
+        refs.append(us[i % B])
+    grp = Group(ctxs_)
+    grp.descend(fields, [dt for _, _, dt in specs], 2)
+    for i, (dims, B, dt) in enumerate(specs):
+        m = Method(Grid(*dims))
+        u = refs[i]
+        for _ in range(2):
+            u, _ = m.descent_step(u, dt)
+        assert rel(to_np(fields[i][i % B]), u) < TOL, dims
+
+
 def test_group_graph_is_reused_across_calls():
     """The captured graph reads fields and steps from device records, so it is
     replayed across calls with new fields and new dtau, with eager work in
