@@ -414,6 +414,100 @@ __device__ __forceinline__ ModeTabs stage_tabs(const KP& p, int m, double* tab, 
     return {dH, dP, Vk, DVk, Ai, dq};
 }
 
+// The opening reads of the residual and gradient kernels in one pass: mode m's
+// tables (as stage_tabs), the three components of spectral field f at the
+// guess offset so (into fd[0..2] at stride NP) and the NS x-slab partials of
+// NF fields of work item mB (summed in slab order into pd[0..NF-1] at stride
+// NP).  Every load of a thread is issued before its first LDS store, so the
+// three groups of reads cost one round trip.  The caller's next barrier
+// publishes the results.
+template <int NP, int MT, int NF, class YT>
+__device__ __forceinline__ ModeTabs open_mode(const KP& p, int m, int mB, size_t so, double* tab, bool solve,
+                                              bool proj, const double2* __restrict__ f, double2* fd,
+                                              const YT* __restrict__ P, double2* pd) {
+    const int N = p.N, NS = p.NS;
+    const size_t nm = p.nm, nmB = p.nmB, mN = (size_t)m * N;
+    double *dH = tab, *dP = tab + NP, *Vk = tab + 2 * NP, *DVk = tab + 6 * NP, *Ai = tab + 10 * NP,
+           *dq = tab + 10 * NP + 16;
+    for (int n = threadIdx.x; n < max(N, 16); n += MT) {
+        // every load is unconditional at a clamped (in-bounds) index, and only the
+        // stores are guarded: a load under a condition would make the compiler
+        // wait for it where the condition ends, before the next loads issue
+        const int nc = min(n, N - 1);
+        const double h = p.dH[mN + nc], q = p.dP[mN + nc], r = p.dproj[mN + nc];
+        const double a = p.Ainv[(size_t)m * 16 + min(n, 15)];
+        double v[4], dv[4], fx[3], fy[3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = p.Vk[4 * mN + (size_t)k * N + nc];
+            dv[k] = p.DVk[4 * mN + (size_t)k * N + nc];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double2 w = f[so + ((size_t)c * nm + m) * N + nc];
+            fx[c] = w.x;
+            fy[c] = w.y;
+        }
+        // slab partials in batches of four, summed in slab order; the first
+        // batch is straight-line code, so its loads issue with the ones above
+        // (a loop entry would wait for them first)
+        double ax[NF], ay[NF];
+        YT pv[4][NF];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const size_t sl = (size_t)min(k, NS - 1);
+#pragma unroll
+            for (int g = 0; g < NF; ++g) pv[k][g] = P[((sl * NF + g) * N + nc) * nmB + mB];
+        }
+#pragma unroll
+        for (int g = 0; g < NF; ++g) ax[g] = ay[g] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < NS)
+#pragma unroll
+                for (int g = 0; g < NF; ++g) {
+                    const double2 w = widen(pv[k][g]);
+                    ax[g] += w.x;
+                    ay[g] += w.y;
+                }
+        for (int s0 = 4; s0 < NS; s0 += 4) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const size_t sl = (size_t)min(s0 + k, NS - 1);
+#pragma unroll
+                for (int g = 0; g < NF; ++g) pv[k][g] = P[((sl * NF + g) * N + nc) * nmB + mB];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (s0 + k < NS)
+#pragma unroll
+                    for (int g = 0; g < NF; ++g) {
+                        const double2 w = widen(pv[k][g]);
+                        ax[g] += w.x;
+                        ay[g] += w.y;
+                    }
+        }
+        if (n < N) {
+#pragma unroll
+            for (int g = 0; g < NF; ++g) pd[g * NP + n] = c2(ax[g], ay[g]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fd[c * NP + n] = c2(fx[c], fy[c]);
+            if (solve) {
+                dH[n] = h;
+                dP[n] = q;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    Vk[k * NP + n] = v[k];
+                    DVk[k * NP + n] = dv[k];
+                }
+            }
+            if (proj) dq[n] = r;
+        }
+        if (solve && n < 16) Ai[n] = a;
+    }
+    return {dH, dP, Vk, DVk, Ai, dq};
+}
+
 // The per-mode kernels read a few values per thread from global memory before
 // their first contraction.  The helpers below issue all of a thread's loads
 // before the first use, so their latencies overlap instead of adding up.
@@ -433,35 +527,6 @@ __device__ __forceinline__ void read_field3(const KP& p, const double2* __restri
     }
 }
 
-// The x-slab partials P[s][f][j][mode] (NF fields per slab) of work item mB,
-// summed over the slabs in slab order, into the LDS vectors dst + f * NP.
-// Four slabs' loads are issued before any of them is added.
-template <int NP, int MT, int NF, class YT>
-__device__ __forceinline__ void sum_partials(const KP& p, const YT* __restrict__ P, int mB, double2* dst) {
-    const int N = p.N, NS = p.NS;
-    const size_t nmB = p.nmB;
-    for (int n = threadIdx.x; n < N; n += MT) {
-        double2 acc[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) acc[f] = c2(0.0, 0.0);
-        for (int s0 = 0; s0 < NS; s0 += 4) {
-            YT v[4][NF];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const size_t sl = (size_t)min(s0 + k, NS - 1);
-#pragma unroll
-                for (int f = 0; f < NF; ++f) v[k][f] = P[((sl * NF + f) * N + n) * nmB + mB];
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (s0 + k < NS)
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) acc[f] = cadd(acc[f], widen(v[k][f]));
-        }
-#pragma unroll
-        for (int f = 0; f < NF; ++f) dst[f * NP + n] = acc[f];
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Stokes solve S (kappa > 0) by the influence-matrix method in the fixed
@@ -1048,13 +1113,13 @@ __device__ __forceinline__ void mode_res_body(
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
     double2 *R0 = vec(9), *R1 = vec(10), *R2 = vec(11);
-    const ModeTabs T = stage_tabs<NP, MT>(p, m, mode_tab<NP>(vs), true, false);   // published by the next barrier
+    ModeTabs T;
     if (flags & RES_INPUT_W) {
+        T = stage_tabs<NP, MT>(p, m, mode_tab<NP>(vs), true, false);
         read_field3<MT>(p, u, so, m, vec(9), vec(10), vec(11));
         __syncthreads();
     } else {
-        read_field3<MT>(p, u, so, m, vec(3), vec(4), vec(5));
-        sum_partials<NP, MT, 3>(p, P3, mB, vec(0));
+        T = open_mode<NP, MT, 3>(p, m, mB, so, mode_tab<NP>(vs), true, false, u, vec(3), P3, vec(0));
         __syncthreads();
         mv3<NP, MT>(p, M_CINV, N, vec(0), vec(1), vec(2), vec(6), vec(7), vec(8));
         mv3_ep<NP, MT>(p, M_D2, N, vec(3), vec(4), vec(5), [&](int n, double2 d0, double2 d1, double2 d2) {
@@ -1119,9 +1184,8 @@ __device__ __forceinline__ void mode_grad_body(const KP& p, int mB, int flags, c
     auto vec = [&](int k) { return vs + (size_t)k * NP; };
     const MS c = mscal(p, m);
     const bool zero = (m == 0);
-    const ModeTabs T = stage_tabs<NP, MT>(p, m, mode_tab<NP>(vs), false, (flags & GRAD_PROJECT) != 0);
-    read_field3<MT>(p, a, so, m, vec(6), vec(7), vec(8));
-    sum_partials<NP, MT, 6>(p, P6, mB, vec(0));
+    const ModeTabs T = open_mode<NP, MT, 6>(p, m, mB, so, mode_tab<NP>(vs), false, (flags & GRAD_PROJECT) != 0, a,
+                                            vec(6), P6, vec(0));
     __syncthreads();
     mv3<NP, MT>(p, M_MA, N, vec(0), vec(1), vec(2), vec(9), vec(10), vec(11));
     mv3<NP, MT>(p, M_MB, N, vec(3), vec(4), vec(5), vec(12), vec(13), vec(14));
