@@ -197,7 +197,10 @@ typedef struct {
  * every guess reached rel_tol (or, with rel_tol = 0, after max_steps),
  * PCFV_ENOTCONV when max_steps ran out above rel_tol, PCFV_ENAN on a
  * non-finite cost, PCFV_EDIVERGED when some guess's cost kept growing after
- * max_halvings halvings (u is then the last checked state).  The report gives
+ * max_halvings halvings.  With grow_tol > 0 the state is checkpointed at every
+ * check; when a guess's cost has grown by more than grow_tol since the last
+ * check, u, the step count and tau go back to that checkpoint and dtau is
+ * halved (u is the checkpointed state on PCFV_EDIVERGED).  The report gives
  * the largest cost and relative residual over the guesses. */
 pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* opts,
                          pcfv_descent_report* report);

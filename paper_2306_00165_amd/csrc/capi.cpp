@@ -682,8 +682,20 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
     bool window = false;
     int nsnap = 0;
     long long next_snap = 0, window_start = 0, since_check = 0;
-    if (o->grow_tol > 0)
-        PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
+    // checkpoint for the divergence rollback: the state, and the step count,
+    // fictitious time and FP32 step count it was taken at
+    long long steps_ck = 0, steps32_ck = 0;
+    double tau_ck = 0;
+    auto checkpoint = [&]() -> pcfv_status {
+        steps_ck = steps;
+        steps32_ck = steps32;
+        tau_ck = tau;
+        if (o->grow_tol > 0)
+            PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
+        return PCFV_OK;
+    };
+    s = checkpoint();
+    if (s != PCFV_OK) return s;
     while (steps < o->max_steps) {
         if (use_dmd && !window && steps >= window_start &&
             (o->dmd_start <= 0 || std::sqrt(std::max(max_cost(), 0.0)) < o->dmd_start)) {
@@ -739,8 +751,8 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
                 cost_prev = cost;
                 s = maybe_refine();
                 if (s != PCFV_OK) return s;
-                if (o->grow_tol > 0)
-                    PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
+                s = checkpoint();
+                if (s != PCFV_OK) return s;
                 window = false;
                 window_start = steps + o->dmd_gap;
                 since_check = 0;
@@ -766,8 +778,12 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
         bool grew = false;
         for (int b = 0; b < B; ++b) grew |= (o->grow_tol > 0 && cost[b] > o->grow_tol * cost_prev[b]);
         if (grew) {
+            // back to the last checkpoint: state, steps, fictitious time
             PCFV_TRY(hipMemcpyAsync(u, ctx->ck, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "restore");
             cost = cost_prev;
+            steps = steps_ck;
+            steps32 = steps32_ck;
+            tau = tau_ck;
             window = false;
             if (halvings >= o->max_halvings) {
                 PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
@@ -781,8 +797,8 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
         cost_prev = cost;
         s = maybe_refine();
         if (s != PCFV_OK) return s;
-        if (o->grow_tol > 0)
-            PCFV_TRY(hipMemcpyAsync(ctx->ck, u, fbytes, hipMemcpyDeviceToDevice, ctx->stream), "checkpoint");
+        s = checkpoint();
+        if (s != PCFV_OK) return s;
         if (converged()) return report(PCFV_OK);
     }
     return report(o->rel_tol > 0 ? fail(ctx, PCFV_ENOTCONV, "max_steps reached above rel_tol") : PCFV_OK);

@@ -61,3 +61,50 @@ def test_extrapolation_of_a_descent_window_lowers_the_cost():
     assert r >= 1 and u_s is not None
     assert max(m.defects(u_s)) < 1e-12
     assert c_s < c_now
+
+
+def test_numerical_rank_counts_singular_values_of_the_first_m_minus_1_snapshots():
+    """The rank is that of [psi_1 .. psi_{M-1}] (the pairs' first members),
+    counting singular values above 1e-7 of the largest."""
+    rng = np.random.default_rng(3)
+    n, M = 50, 6
+    U, _ = np.linalg.qr(rng.standard_normal((n, M - 1)))
+    V, _ = np.linalg.qr(rng.standard_normal((M - 1, M - 1)))
+    s = np.array([1.0, 1e-3, 1e-6, 5e-8, 0.0])
+    X = (U * s) @ V.T                                 # n x (M-1), singular values s
+    last = rng.standard_normal(n)                     # psi_M does not count
+    snaps = np.vstack([X.T, last])
+    assert dmd.numerical_rank(snaps) == 3
+    assert dmd.numerical_rank(snaps, tol=1e-8) == 4
+
+
+def test_rank_is_chosen_by_least_true_cost(monkeypatch):
+    """Sec. 6.2: among r = 1..r*, the rank whose extrapolated state has the
+    smallest cost is taken.  With a stub DMD whose rank-r steady state is
+    marked by its first entry and a stub cost table, the choice must be the
+    argmin over r <= r* (not the largest rank, not beyond r*), returning that
+    candidate, its cost and r."""
+    g = Grid(6, 9, 6)
+    n = g.n_state()
+    table = {1: 3.0, 2: 1.0, 3: 2.0, 4: 0.5, 5: 4.0, 6: 0.1}
+
+    def fake_steady(psis, dtau, r):
+        psi = np.zeros(n)
+        psi[0] = r
+        return psi, 0.0
+
+    class StubMethod:
+        def __init__(self):
+            self.g = g
+
+        def cost(self, u):
+            return table[int(round(state.pack(g, u)[0]))]
+
+    monkeypatch.setattr(dmd, "steady_state", fake_steady)
+    monkeypatch.setattr(dmd, "numerical_rank", lambda psis, tol=dmd.RANK_TOL: 5)
+    fields = [state.unpack(g, np.full(n, float(k))) for k in range(4)]
+    u_s, c_s, r = dmd.extrapolate(StubMethod(), fields, 1.0)
+    assert (r, c_s) == (4, 0.5)
+    assert state.pack(g, u_s)[0] == 4.0
+    monkeypatch.setattr(dmd, "numerical_rank", lambda psis, tol=dmd.RANK_TOL: 0)
+    assert dmd.extrapolate(StubMethod(), fields, 1.0) == (None, np.inf, 0)

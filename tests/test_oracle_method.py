@@ -221,6 +221,28 @@ def test_laminar_diagnostics_match_table2():
     assert abs(m.total_norm(z) ** 2 - 1.0 / 3.0) < 1e-15     # (1/2) int y^2 dy
 
 
+@pytest.mark.parametrize("seed,energy", [(1, 1e-3), (81, 0.05), (82, 0.3)])
+def test_dissipation_equals_gradient_norm(seed, energy):
+    """D = <curl U, curl U>_W equals sum_ij ||d_j U_i||^2_W for U = u_b + u with
+    u divergence-free and no-slip: the difference is the volume integral of
+    d_j(U_i d_i U_j) (using div U = 0), a wall flux of U_i d_i U_y that
+    vanishes because U is constant along each wall (U = (+-1, 0, 0) there, so
+    d_x U_y = d_z U_y = 0 and U_y = 0).  Every integrand is a polynomial of
+    degree < 2 Ny in y, which the Gram matrix integrates exactly, so the
+    identity holds to round-off; a sign or index mistake in any vorticity
+    component breaks it at the 1e-4 level or more."""
+    g = Grid(16, 25, 16)
+    m = Method(g)
+    T = m.T
+    u = rnd(g, seed, energy)
+    U = m.base_flow() + u
+    grad2 = 0.0
+    for i in range(3):
+        dU = np.stack([T.ddx(U[i]), T.ddy(U[i]), T.ddz(U[i])])
+        grad2 += m.inner(dU, dU)
+    assert abs(m.dissipation(u) - grad2) < 1e-13 * grad2
+
+
 def test_state_vector_length_matches_paper():
     sv = GOLDEN["state_vector_length"]
     g = Grid(sv["grid"]["Nx"], sv["grid"]["Ny"], sv["grid"]["Nz"])

@@ -73,6 +73,23 @@ def test_adam_first_step_moves_by_lr_times_sign():
     np.testing.assert_allclose(v, 0.001 * g * g)
 
 
+def test_adam_constant_gradient_moves_by_lr_times_sign_every_step():
+    """With a constant gradient g the moments are m_t = (1 - beta1^t) g and
+    v_t = (1 - beta2^t) g^2, so the bias-corrected ratio is g / |g| at every
+    step t: each step moves by lr g / (|g| + eps).  A bias correction with the
+    wrong power (beta t instead of beta^t, or t - 1) fails from t = 2 on."""
+    rng = np.random.default_rng(17)
+    p0 = rng.standard_normal(64)
+    g = rng.standard_normal(64)
+    p, m, v = p0.copy(), np.zeros(64), np.zeros(64)
+    lr, b1, b2 = 0.003, 0.9, 0.999
+    for t in range(1, 6):
+        p, m, v = mlp.adam(p, g, m, v, t, lr=lr, beta1=b1, beta2=b2)
+        np.testing.assert_allclose(m, (1 - b1 ** t) * g, rtol=1e-14)
+        np.testing.assert_allclose(v, (1 - b2 ** t) * g * g, rtol=1e-13)
+        np.testing.assert_allclose(p, p0 - t * lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-14)
+
+
 def test_pod_recovers_planted_modes():
     """Snapshots mean + sum_i a_si s_i v_i with orthonormal v_i and
     orthonormal zero-mean amplitude columns a_i: the POD returns s_i and +-v_i."""
