@@ -369,6 +369,24 @@ pcfv_status pcfv_pod_build(void* hip_stream, const double* X, int S, long long n
 size_t pcfv_pod_project_scratch_bytes(int m, long long n, int r);
 pcfv_status pcfv_pod_project(void* hip_stream, const double* X, int m, long long n, int r, const double* mean,
                              const double* basis, double* coef, void* scratch);
+/* Allocation-free variant of pcfv_pod_project, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same split of the
+ * sum over n, so coef equals pcfv_pod_project's bit for bit, but the split-K
+ * partials live in a device-resident array of PCFV_NOALLOC_SCRATCH_BYTES
+ * (8 MiB) that the library holds on every GPU it runs on until the process
+ * ends.  The call allocates nothing and calls no allocating routine; its
+ * first call on a device looks up that device's copy of the array (with the
+ * device current: hip_stream must belong to the current device).  Every call
+ * on one GPU shares that array and leaves its contents behind, so calls that
+ * overlap on one GPU (different streams, threads) race; the partials are
+ * written in full before they are read, so nothing needs clearing between
+ * calls.  Errors: PCFV_EINVAL (bad arguments), PCFV_ENOMEM when the partials
+ * (pcfv_pod_project_scratch_bytes(m, n, r) bytes) exceed the array (message
+ * from pcfv_last_error(NULL)), PCFV_EDEVICE.  Asynchronous on hip_stream. */
+#define PCFV_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+pcfv_status pcfv_pod_project_noalloc(void* hip_stream, const double* X, int m, long long n, int r,
+                                     const double* mean, const double* basis, double* coef);
 /* X (m x n) = mean + coef basis.  Asynchronous. */
 pcfv_status pcfv_pod_reconstruct(void* hip_stream, const double* coef, int m, long long n, int r, const double* mean,
                                  const double* basis, double* X);

@@ -194,6 +194,12 @@ namespace {
 
 thread_local std::string g_create_err;  // reason of the last failed pcfv_create on this thread
 
+}  // namespace
+
+void pcfv::set_create_error(const std::string& msg) { g_create_err = msg; }
+
+namespace {
+
 pcfv_status fail(pcfv_ctx* c, pcfv_status s, const std::string& msg) {
     if (c) c->err = msg;
     return s;

@@ -416,6 +416,31 @@ pcfv_status pcfv_pod_project(void* hip_stream, const double* X, int m, long long
                : PCFV_EDEVICE;
 }
 
+pcfv_status pcfv_pod_project_noalloc(void* hip_stream, const double* X, int m, long long n, int r,
+                                     const double* mean, const double* basis, double* coef) {
+    if (!X || !mean || !basis || !coef || m < 1 || n < 1 || r < 1) {
+        set_create_error("pcfv_pod_project_noalloc: NULL pointer or non-positive size");
+        return PCFV_EINVAL;
+    }
+    const int sp = pod_splits(m, r, n);
+    const size_t need = pcfv_pod_project_scratch_bytes(m, n, r);
+    if (sp > 1 && need > kStaticScratchBytes) {
+        set_create_error("pcfv_pod_project_noalloc: the split-K partials need " + std::to_string(need) +
+                         " bytes, more than the " + std::to_string(kStaticScratchBytes) +
+                         "-byte device-resident scratch; use pcfv_pod_project with a workspace");
+        return PCFV_ENOMEM;
+    }
+    double* part = nullptr;
+    if (sp > 1 && static_scratch(&part) != hipSuccess) {
+        set_create_error("pcfv_pod_project_noalloc: hipGetSymbolAddress of the scratch array failed");
+        return PCFV_EDEVICE;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    return launch_gemm_f64(s, m, r, n, X, n, false, basis, n, true, mean, nullptr, coef, r, sp, part) == hipSuccess
+               ? PCFV_OK
+               : PCFV_EDEVICE;
+}
+
 pcfv_status pcfv_pod_reconstruct(void* hip_stream, const double* coef, int m, long long n, int r, const double* mean,
                                  const double* basis, double* X) {
     if (!coef || !mean || !basis || !X || m < 1 || n < 1 || r < 1 || n > (1LL << 30)) return PCFV_EINVAL;

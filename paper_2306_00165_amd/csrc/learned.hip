@@ -9,7 +9,17 @@
 // C[4 (l / 16) + r][l % 16], r = 0..3 (checked on the device by the tests).
 #include "learned.hpp"
 
+#include <mutex>
+
 namespace pcfv {
+
+// Device-resident scratch of the allocation-free POD projection
+// (pcfv_pod_project_noalloc): the split-K partials of its FP64 GEMM.  Every
+// GPU the library runs on holds one copy for the life of the process.  In host
+// code the array's name is only a stand-in for the symbol; its device address
+// comes from hipGetSymbolAddress (static_scratch below).
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
 namespace {
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -396,6 +406,29 @@ hipError_t launch_normalize(hipStream_t s, int B, int n, float* F, const float* 
 hipError_t launch_gather(hipStream_t s, int rows, int n, const int* idx, const float* src, float* dst) {
     hipLaunchKernelGGL(k_gather, dim3(blocks((long long)rows * n, 256)), dim3(256), 0, s, rows, n, idx, src, dst);
     return hipGetLastError();
+}
+
+// Device address of `scratch` on the current device: looked up once per device
+// (with that device current) and kept, since each GPU holds its own copy at
+// its own address.
+hipError_t static_scratch(double** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace pcfv

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "../../include/pcfv.h"
+
 namespace pcfv {
 
 typedef uint16_t bf16_t;   // bfloat16 bit pattern
@@ -83,5 +85,11 @@ hipError_t launch_targets(hipStream_t s, int W, int B, int r, const double* c, c
 hipError_t launch_normalize(hipStream_t s, int B, int n, float* F, const float* mu, const float* isd);
 // dst[i][j] = src[idx[i]][j] (rows x n, FP32).
 hipError_t launch_gather(hipStream_t s, int rows, int n, const int* idx, const float* src, float* dst);
+
+// Size of the device-resident scratch array of the allocation-free entry point.
+constexpr size_t kStaticScratchBytes = PCFV_NOALLOC_SCRATCH_BYTES;
+// Device address of that array on the current device (looked up with
+// hipGetSymbolAddress on the first call per device, then cached).
+hipError_t static_scratch(double** out);
 
 }  // namespace pcfv

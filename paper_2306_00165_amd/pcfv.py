@@ -36,8 +36,10 @@ EXPORTS = [
     "pcfv_mlp_last_error", "pcfv_mlp_set_params", "pcfv_mlp_get_params", "pcfv_mlp_forward", "pcfv_mlp_grad",
     "pcfv_mlp_adam_step", "pcfv_mlp_read", "pcfv_mlp_fit", "pcfv_pod_scratch_bytes", "pcfv_pod_build",
     "pcfv_pod_project_scratch_bytes", "pcfv_pod_project", "pcfv_pod_reconstruct", "pcfv_learned_scratch_bytes",
-    "pcfv_learned_propose", "pcfv_learned_prepare", "pcfv_time_descent_kernels",
+    "pcfv_learned_propose", "pcfv_learned_prepare", "pcfv_time_descent_kernels", "pcfv_pod_project_noalloc",
 ]
+
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 MLP_MAX_LAYERS = 8
 MLP_ACT, MLP_OUT, MLP_DZ, MLP_GRAD = 0, 1, 2, 3
@@ -187,6 +189,8 @@ def load_library(path=_LIB_PATH):
     lib.pcfv_pod_project_scratch_bytes.argtypes = [i, ctypes.c_longlong, i]
     lib.pcfv_pod_project.restype = i
     lib.pcfv_pod_project.argtypes = [vp, vp, i, ctypes.c_longlong, i, vp, vp, vp, vp]
+    lib.pcfv_pod_project_noalloc.restype = i
+    lib.pcfv_pod_project_noalloc.argtypes = [vp, vp, i, ctypes.c_longlong, i, vp, vp, vp]
     lib.pcfv_pod_reconstruct.restype = i
     lib.pcfv_pod_reconstruct.argtypes = [vp, vp, i, ctypes.c_longlong, i, vp, vp, vp]
     lib.pcfv_learned_scratch_bytes.restype = ctypes.c_size_t
@@ -620,6 +624,21 @@ def pod_project(X, mean, basis):
                                _ptr(basis), _ptr(coef), _ptr(scratch))
     if st != OK:
         raise PcfvError(st, "pcfv_pod_project failed")
+    return coef
+
+
+def pod_project_noalloc(X, mean, basis, coef=None):
+    """pcfv_pod_project without a workspace: the library's device-resident
+    scratch holds the split-K partials.  coef (m x r, device float64) may be
+    passed in so that the call itself allocates nothing."""
+    m, n = X.shape
+    r = basis.shape[0]
+    if coef is None:
+        coef = torch.empty((m, r), dtype=torch.float64, device=basis.device)
+    st = _lib.pcfv_pod_project_noalloc(_cuda_stream_ptr(torch, basis.device), _ptr(X), int(m), int(n), int(r),
+                                       _ptr(mean), _ptr(basis), _ptr(coef))
+    if st != OK:
+        raise PcfvError(st, _lib.pcfv_last_error(None).decode())
     return coef
 
 
