@@ -18,18 +18,17 @@ from paper_2306_00165_amd import inputs
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-11
-# At Ny = 49 the adjoint is less well conditioned: the transposed Stokes solve
-# of the lowest-kappa mode goes through an influence matrix of condition ~1e5
-# (both implementations agree with a 40-digit reference to <= 2e-14 there),
-# and J* amplifies perturbations of that solve's output by ~300 (measured with
-# 1e-16 noise).  The bound for the adjoint and the descent direction at
-# 48 x 49 x 48 is therefore 5e-11.
-TOL_ADJ49 = 5e-11
-# At Ny = 65 the lowest-kappa influence matrix is worse conditioned still
-# (condition ~3e5 of the dense tau system there); the same amplification
-# argument gives the bound used for the adjoint and the descent step of the
-# 96 x 65 x 96 instance.
-TOL_ADJ65 = 2e-10
+# One exception, the adjoint of a smooth field in the wide 96 x 65 x 96 box
+# (Lx = 4 pi): there the lowest mode has kappa^2 = 0.25 and the influence
+# matrix of the GPU's Stokes solve has condition ~7e5; its tau-residual entry
+# (~ -1.5e-5) is a cancellation of O(1) terms that long double resolves only to
+# ~1e-14 relative, which leaves ~1e-13 in that mode's transposed solve and,
+# through the nu L* term of J* (~240x for this mode), 2.8e-11 in J* w.  The
+# oracle is accurate to 4e-13 there (tests/test_oracle_precision.py, against a
+# 40-digit evaluation), so the bound below is the GPU's own error, stated: 5e-11.
+# The descent step of that instance, and everything at 48 x 49 x 48 (adjoint
+# error 8e-13, descent step 1.5e-13 measured), meet 1e-11.
+TOL_ADJ_WIDE = 5e-11
 
 
 def rel(a, b):
@@ -214,7 +213,7 @@ def test_metric_residual_and_adjoint(metric):
           ", ".join(f"({g.kx[i // g.nkz]}, {i % g.nkz}, {per_mode.ravel()[i]:.1e})" for i in worst))
     assert e_r < TOL
     assert abs(cost - m.inner(r_ref, r_ref)) < TOL * cost
-    assert e_a < TOL_ADJ49
+    assert e_a < TOL
 
 
 def test_metric_projection_properties(metric):
@@ -247,7 +246,7 @@ def test_metric_descent_step_matches_oracle_direction(metric):
     assert st == 0
     e = rel(to_np(u) - u0, want - u0)
     print(f"[gpu] 48x49x48 descent step rel err {e:.3e}")
-    assert e < TOL_ADJ49
+    assert e < TOL
 
 
 # -- several guesses in one context ---------------------------------------------------
@@ -601,7 +600,9 @@ def test_every_launch_shape_matches_oracle(shape_ctx, xs, nt, mt):
     assert c.tuning() == (xs, nt, mt)
     u, w = guess(g, 11), guess(g, 12)
     assert rel(to_np(c.residual(u)), m.residual(u)) < TOL
-    assert rel(to_np(c.adjoint(u, w)), m.adjoint(u, w)) < TOL_ADJ49
+    e_a = rel(to_np(c.adjoint(u, w)), m.adjoint(u, w))
+    print(f"[gpu] shape {(xs, nt, mt)}: adjoint rel err {e_a:.2e}")
+    assert e_a < TOL
     U = torch.as_tensor(u).to("cuda:0").contiguous()
     c.descend(U, max_steps=1, dtau=0.02)
     assert rel(to_np(U), m.descent_step(u, 0.02)[0]) < TOL
@@ -646,11 +647,11 @@ def test_wide_box_residual_adjoint_and_step(wide):
         print(f"[gpu] 96x65x96 guess {b}: residual {e_r:.2e} adjoint {e_a:.2e}")
         assert e_r < TOL
         assert abs(costs[b] - m.inner(rr, rr)) < TOL * costs[b]
-        assert e_a < TOL_ADJ65
+        assert e_a < TOL_ADJ_WIDE
     for b in range(2, 8):
         assert np.array_equal(r[b], r[b % 2]) and np.array_equal(a[b], a[b % 2])
     c.descend(U, max_steps=1, dtau=0.01)
     u1, _ = m.descent_step(us[0], 0.01)
     e_s = float(np.abs(to_np(U[0]) - u1).max() / np.abs(u1 - us[0]).max())
     print(f"[gpu] 96x65x96 descent step error relative to the update {e_s:.2e}")
-    assert e_s < TOL_ADJ65
+    assert e_s < TOL
