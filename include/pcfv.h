@@ -207,15 +207,25 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* opts
 
 /* DMD extrapolation (Sec. 6) of each guess.  snaps: device, [M][batch][n_state]
  * minimal state vectors (pcfv_pack_state), oldest first, consecutive ones
- * dtau_snap apart, 3 <= M <= 256.  For r = 1..r* (r* = numerical rank of the
- * window, singular values above 1e-7 of the largest) the steady state
- * Re(b_1 phi_1) of the rank-r exact DMD (mode with the smallest |omega|,
- * amplitudes fitted at the last snapshot) is formed and its cost evaluated;
- * the cheapest is written to u_out (batch fields), its cost to cost_host[b]
- * and r to rank_host[b] (either may be NULL).  A guess whose window has rank 0
- * gets its last snapshot and rank 0.  Synchronises. */
+ * dtau_snap apart, 3 <= M <= 256.  Candidates (Sec. 6.1-6.2, and a reading for
+ * targets without an omega = 0 mode), for r = 1, 2, ..:
+ *   kind 0 (r <= r*, the numerical rank of [psi_1 .. psi_{M-1}], singular
+ *     values above 1e-7 of the largest): Re(b_1 phi_1) of the rank-r exact
+ *     DMD of the snapshots, the mode with the smallest |omega|, amplitudes
+ *     fitted at the last snapshot;
+ *   kind 1 (r <= r*_d, the numerical rank of the differences
+ *     [d_1 .. d_{M-2}], d_k = psi_{k+1} - psi_k): the fixed point of the
+ *     affine model fitted by the rank-r exact DMD of the differences,
+ *     psi_M + Re sum_{|lambda_q| < 1} b_q phi_q lambda_q / (1 - lambda_q)
+ *     (exact for affine dynamics around any fixed point, the laminar state
+ *     included).
+ * Each candidate's true cost J^2 is evaluated; the cheapest (earliest in the
+ * order rank, kind on ties) is written to u_out (batch fields), its cost to
+ * cost_host[b], its rank and kind to rank_host[b] and kind_host[b] (any of the
+ * three may be NULL).  A guess whose window has rank 0 gets its last snapshot,
+ * rank 0 and kind -1.  Synchronises. */
 pcfv_status pcfv_dmd_extrapolate(pcfv_ctx* ctx, const double* snaps, int M, double dtau_snap,
-                                 double* u_out, double* cost_host, int* rank_host);
+                                 double* u_out, double* cost_host, int* rank_host, int* kind_host);
 
 /* Norms per guess b: out_host[3b] = ||u||_W, out_host[3b+1] = ||u_b + u||_W,
  * out_host[3b+2] = D = <curl U, curl U>_W (so that laminar flow has D = 1,
@@ -456,15 +466,16 @@ pcfv_status pcfv_learned_propose(pcfv_ctx* ctx, const pcfv_learned_model* model,
  * returns the table size in doubles, or 0 if cfg or which is invalid. */
 size_t pcfv_host_table(const pcfv_config* cfg, int which, double* out, size_t cap);
 
-/* Host-side DMD algebra of Sec. 6.1-6.2 (for tests, no device): given the
- * M x M Gram matrix Ge = Ge_hi + Ge_lo (row-major, an unevaluated sum of two
- * doubles per entry; Ge_lo may be NULL) of E = [psi_1, psi_2 - psi_1, ..,
- * psi_M - psi_{M-1}], writes for r = 1..r* the M-1 coefficients c with steady
- * state psi_s(r) = sum_k c_k psi_{k+2} into coef[(r-1)(M-1) + k] (at most cap
- * doubles) and returns r* (singular values of [psi_1..psi_{M-1}] above 1e-7
- * times the largest), or -1 on invalid input.  3 <= M <= 256. */
-int pcfv_host_dmd(const double* Ge_hi, const double* Ge_lo, int M, double dtau, double* coef,
-                  size_t cap);
+/* Test hook (no device): the host-side DMD algebra of Sec. 6.1-6.2.  Given
+ * the M x M Gram matrix Ge = Ge_hi + Ge_lo (row-major, an unevaluated sum of
+ * two doubles per entry; Ge_lo may be NULL) of E = [psi_1, psi_2 - psi_1, ..,
+ * psi_M - psi_{M-1}], writes the candidates of pcfv_dmd_extrapolate in their
+ * evaluation order: candidate i's M-1 coefficients c (steady state
+ * psi_s = sum_k c_k psi_{k+2}) to coef[i (M-1) + k] and its (rank, kind) to
+ * labels[2i], labels[2i+1], for i < cap (either array may be NULL).  Returns
+ * the number of candidates, or -1 on invalid input.  3 <= M <= 256. */
+int pcfv_host_dmd(const double* Ge_hi, const double* Ge_lo, int M, double dtau, double* coef, int* labels,
+                  int cap);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,23 @@ psi_s = b_1 phi_1 (real part; the data are real), and the truncation rank
 r <= r* (r* = numerical rank of Psi) is the one whose extrapolated state has
 the smallest cost J.
 
+Reading for targets the paper's rule cannot reach.  The smallest-|omega|
+mode is the limit of the linear model only when one mode neither grows nor
+decays (omega ~ 0, a non-trivial fixed point).  When the trajectory heads for
+the laminar state every fitted mode decays and no such mode exists; when the
+window is short, the fitted rate of the fixed-point mode is not close to 0.
+Both cases are covered by the limit of an affine model psi_{k+1} - psi* =
+A (psi_k - psi*): its differences d_k = psi_{k+1} - psi_k obey d_{k+1} = A d_k
+(linear, no fixed point needed), so the exact DMD of the difference pairs
+(d_k, d_{k+1}) with amplitudes fitted at the last difference gives the future
+differences b_q phi_q lambda_q^j, and their sum is the limit
+    psi_inf = psi_M + Re sum_{|lambda_q| < 1} b_q phi_q lambda_q / (1 - lambda_q).
+It is exact for affine dynamics around any fixed point, the laminar state
+(psi* = 0) included.  So beside the paper's candidate (kind 0, ranks
+r <= r*) each rank r <= r*_d (numerical rank of [d_1 .. d_{M-2}]) offers this
+limit (kind 1).  Every candidate is judged by its true cost, and the cheapest
+one (earliest in the order rank, then kind, on ties) is the extrapolation.
+
 Snapshots are minimal real state vectors (oracle.state.pack).  The numerical
 rank counts singular values above RANK_TOL times the largest.
 """
@@ -52,18 +69,41 @@ def steady_state(snaps, dtau, r):
     return np.real(b[q] * Phi[:, q]), omega[q]
 
 
+def affine_limit(snaps, dtau, r):
+    """psi_M + Re sum_{|lambda_q| < 1} b_q phi_q lambda_q/(1 - lambda_q) from the
+    rank-r exact DMD of the snapshot differences."""
+    S = np.asarray(snaps, dtype=float)
+    lam, omega, Phi, b = dmd(np.diff(S, axis=0), dtau, r)
+    gain = np.where(np.abs(lam) < 1, lam / (1 - lam), 0.0)
+    return S[-1] + np.real(Phi @ (b * gain))
+
+
+def candidates(snaps, dtau, rstar):
+    """[(rank, kind, psi)]: kind 0 the paper's smallest-|omega| mode for
+    r <= rstar, kind 1 the affine limit for r <= r*_d, ordered by rank, then
+    kind."""
+    S = np.asarray(snaps, dtype=float)
+    rstar_d = numerical_rank(np.diff(S, axis=0)) if rstar > 0 else 0
+    out = []
+    for r in range(1, max(rstar, rstar_d) + 1):
+        if r <= rstar:
+            out.append((r, 0, steady_state(S, dtau, r)[0]))
+        if r <= rstar_d:
+            out.append((r, 1, affine_limit(S, dtau, r)))
+    return out
+
+
 def extrapolate(method, fields, dtau):
     """DMD extrapolation of a window of snapshot fields (same grid): returns
-    (u_s, cost_s, r) for the rank r <= r* whose steady state has the smallest
-    cost (Sec. 6.2), or (None, inf, 0) if the window has rank 0."""
+    (u_s, cost_s, r, kind) for the candidate of smallest true cost (Sec. 6.2
+    and the reading above), or (None, inf, 0, -1) if the window has rank 0."""
     g = method.g
     psis = np.stack([state.pack(g, u) for u in fields])
     rstar = numerical_rank(psis)
-    best = (None, np.inf, 0)
-    for r in range(1, rstar + 1):
-        psi_s, _ = steady_state(psis, dtau, r)
-        u_s = state.unpack(g, psi_s)
+    best = (None, np.inf, 0, -1)
+    for r, kind, psi in candidates(psis, dtau, rstar):
+        u_s = state.unpack(g, psi)
         c = method.cost(u_s)
         if c < best[1]:
-            best = (u_s, c, r)
+            best = (u_s, c, r, kind)
     return best

@@ -29,19 +29,32 @@ def _run(cmd):
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
 
 
-def build(verbose=False, jobs=None):
-    """Compile every source into paper_2306_00165_amd/_lib/libpcfv.so."""
+def _headers():
+    out = []
+    for d in (os.path.join(HERE, "csrc"), os.path.join(ROOT, "include")):
+        out += [os.path.join(d, f) for f in os.listdir(d) if f.endswith((".h", ".hpp"))]
+    return out
+
+
+def build(verbose=False, jobs=None, incremental=False):
+    """Compile every source into paper_2306_00165_amd/_lib/libpcfv.so.  With
+    incremental, objects newer than their source and every header are kept."""
     os.makedirs(LIB_DIR, exist_ok=True)
     os.makedirs(OBJ_DIR, exist_ok=True)
+    newest_header = max(os.path.getmtime(h) for h in _headers())
     objs, cmds = [], []
     for s in SOURCES:
         o = os.path.join(OBJ_DIR, os.path.basename(s) + ".o")
         objs.append(o)
-        cmds.append([HIPCC] + FLAGS + ["-c", os.path.join(HERE, s), "-o", o])
+        src = os.path.join(HERE, s)
+        if (incremental and os.path.exists(o) and
+                os.path.getmtime(o) > max(os.path.getmtime(src), newest_header)):
+            continue
+        cmds.append([HIPCC] + FLAGS + ["-c", src, "-o", o])
     if verbose:
         for c in cmds:
             print(" ".join(c))
-    with ThreadPoolExecutor(max_workers=jobs or min(len(cmds), os.cpu_count() or 1)) as ex:
+    with ThreadPoolExecutor(max_workers=jobs or max(1, min(len(cmds), os.cpu_count() or 1))) as ex:
         for f in [ex.submit(_run, c) for c in cmds]:
             f.result()
     tmp = LIB + ".tmp"
@@ -51,4 +64,5 @@ def build(verbose=False, jobs=None):
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

@@ -375,10 +375,13 @@ pcfv_status learned_core(pcfv_ctx* ctx, const pcfv_learned_model* md, const doub
     return PCFV_OK;
 }
 
-// DMD extrapolation of the window snaps ([M][B][n_state]); writes the best
-// candidate of each guess to u_out (last snapshot if none), its cost and rank.
+// DMD extrapolation of the window snaps ([M][B][n_state]): every candidate of
+// every guess (ranks r <= r*, the kinds of dmd_candidates) is judged by its true
+// cost; writes the cheapest of each guess to u_out (the last snapshot if it has
+// none), its cost, rank and kind (0 and -1 for none).  Candidates are
+// evaluated slot by slot, slot i holding the i-th candidate of every guess.
 pcfv_status dmd_core(pcfv_ctx* ctx, const double* snaps, int M, double dtau, double* u_out,
-                     std::vector<double>& best_cost, std::vector<int>& best_rank) {
+                     std::vector<double>& best_cost, std::vector<int>& best_rank, std::vector<int>& best_kind) {
     const KP& p = ctx->kp;
     const int B = p.B;
     const long long n = p.nstate;
@@ -390,30 +393,27 @@ pcfv_status dmd_core(pcfv_ctx* ctx, const double* snaps, int M, double dtau, dou
     PCFV_TRY(hipMemcpyAsync(G.data(), ctx->dmdG, (size_t)B * gbytes, hipMemcpyDeviceToHost, ctx->stream),
              "copy gram");
     PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
-    std::vector<std::vector<std::vector<double>>> coef(B);
-    std::vector<int> rstar(B, 0);
-    int rmax = 0;
+    std::vector<std::vector<DmdCandidate>> cands(B);
+    size_t nslots = 0;
     for (int b = 0; b < B; ++b) {
         std::vector<long double> Gb((size_t)M * M);
         for (size_t k = 0; k < Gb.size(); ++k)
             Gb[k] = (long double)G[((size_t)b * M * M + k) * 2] + (long double)G[((size_t)b * M * M + k) * 2 + 1];
-        std::vector<double> om;
         std::string err;
-        const int r = dmd_candidates(Gb, M, dtau, coef[b], om, err);
-        if (r < 0) return fail(ctx, PCFV_EINVAL, err);
-        rstar[b] = r;
-        rmax = std::max(rmax, r);
+        if (dmd_candidates(Gb, M, dtau, cands[b], err) < 0) return fail(ctx, PCFV_EINVAL, err);
+        nslots = std::max(nslots, cands[b].size());
     }
     best_cost.assign(B, std::numeric_limits<double>::infinity());
     best_rank.assign(B, 0);
+    best_kind.assign(B, -1);
     // fallback: the last snapshot
     PCFV_TRY(launch_unpack(p, ctx->stream, snaps + (size_t)(M - 1) * B * n, dd(u_out)), "unpack");
     std::vector<double> cvec((size_t)B * (M - 1));
     std::vector<double> costs(B);
-    for (int r = 1; r <= rmax; ++r) {
+    for (size_t slot = 0; slot < nslots; ++slot) {
         for (int b = 0; b < B; ++b)
             for (int k = 0; k < M - 1; ++k)
-                cvec[(size_t)b * (M - 1) + k] = (r <= rstar[b]) ? coef[b][r - 1][k] : 0.0;
+                cvec[(size_t)b * (M - 1) + k] = (slot < cands[b].size()) ? cands[b][slot].coef[k] : 0.0;
         PCFV_TRY(hipMemcpyAsync(ctx->dmdC, cvec.data(), cvec.size() * sizeof(double), hipMemcpyHostToDevice,
                                 ctx->stream),
                  "copy coefficients");
@@ -425,9 +425,10 @@ pcfv_status dmd_core(pcfv_ctx* ctx, const double* snaps, int M, double dtau, dou
         st = read_scalars(ctx, 1, 0, costs.data());
         if (st != PCFV_OK) return st;
         for (int b = 0; b < B; ++b)
-            if (r <= rstar[b] && std::isfinite(costs[b]) && costs[b] < best_cost[b]) {
+            if (slot < cands[b].size() && std::isfinite(costs[b]) && costs[b] < best_cost[b]) {
                 best_cost[b] = costs[b];
-                best_rank[b] = r;
+                best_rank[b] = cands[b][slot].rank;
+                best_kind[b] = cands[b][slot].kind;
                 PCFV_TRY(hipMemcpyAsync(u_out + (size_t)b * 3 * p.nm * p.N * 2,
                                         reinterpret_cast<const char*>(ctx->tmp) + b * fbytes1, fbytes1,
                                         hipMemcpyDeviceToDevice, ctx->stream),
@@ -715,12 +716,12 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
             next_snap += o->dmd_stride;
             if (nsnap == o->dmd_window) {
                 std::vector<double> cnow, nnow, dcost;
-                std::vector<int> drank;
+                std::vector<int> drank, dkind;
                 s = cost_and_norm(ctx, u, cnow, nnow);
                 if (s != PCFV_OK) return s;
                 double2* cand = ctx->a;   // scratch: recomputed by every step
                 s = dmd_core(ctx, o->dmd_buffer, o->dmd_window, o->dmd_stride * dtau,
-                             reinterpret_cast<double*>(cand), dcost, drank);
+                             reinterpret_cast<double*>(cand), dcost, drank, dkind);
                 if (s != PCFV_OK) return s;
                 ++n_dmd;
                 std::vector<double> lcost;
@@ -811,15 +812,16 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
 }
 
 pcfv_status pcfv_dmd_extrapolate(pcfv_ctx* ctx, const double* snaps, int M, double dtau_snap,
-                                 double* u_out, double* cost_host, int* rank_host) {
+                                 double* u_out, double* cost_host, int* rank_host, int* kind_host) {
     if (!ctx || !snaps || !u_out) return fail(ctx, PCFV_EINVAL, "NULL argument");
     std::vector<double> cost;
-    std::vector<int> rank;
-    pcfv_status s = dmd_core(ctx, snaps, M, dtau_snap, u_out, cost, rank);
+    std::vector<int> rank, kind;
+    pcfv_status s = dmd_core(ctx, snaps, M, dtau_snap, u_out, cost, rank, kind);
     if (s != PCFV_OK) return s;
     for (int b = 0; b < ctx->kp.B; ++b) {
         if (cost_host) cost_host[b] = cost[b];
         if (rank_host) rank_host[b] = rank[b];
+        if (kind_host) kind_host[b] = kind[b];
     }
     PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
     return PCFV_OK;
@@ -1234,22 +1236,23 @@ pcfv_status pcfv_learned_propose(pcfv_ctx* ctx, const pcfv_learned_model* model,
     return PCFV_OK;
 }
 
-int pcfv_host_dmd(const double* Ge_hi, const double* Ge_lo, int M, double dtau, double* coef,
-                  size_t cap) {
-    if (!Ge_hi || M < 3 || M > kMaxDmd) return -1;
+int pcfv_host_dmd(const double* Ge_hi, const double* Ge_lo, int M, double dtau, double* coef, int* labels,
+                  int cap) {
+    if (!Ge_hi || M < 3 || M > kMaxDmd || cap < 0) return -1;
     std::vector<long double> G((size_t)M * M);
     for (size_t k = 0; k < G.size(); ++k)
         G[k] = (long double)Ge_hi[k] + (Ge_lo ? (long double)Ge_lo[k] : 0.0L);
-    std::vector<std::vector<double>> c;
-    std::vector<double> om;
+    std::vector<DmdCandidate> c;
     std::string err;
-    const int r = dmd_candidates(G, M, dtau, c, om, err);
-    if (r < 0) return -1;
-    size_t k = 0;
-    for (const auto& row : c)
-        for (double v : row)
-            if (coef && k < cap) coef[k++] = v;
-    return r;
+    if (dmd_candidates(G, M, dtau, c, err) < 0) return -1;
+    for (int i = 0; i < (int)c.size() && i < cap; ++i) {
+        if (coef) std::copy(c[i].coef.begin(), c[i].coef.end(), coef + (size_t)i * (M - 1));
+        if (labels) {
+            labels[2 * i] = c[i].rank;
+            labels[2 * i + 1] = c[i].kind;
+        }
+    }
+    return (int)c.size();
 }
 
 size_t pcfv_host_table(const pcfv_config* cfg, int which, double* out, size_t cap) {

@@ -301,88 +301,144 @@ std::vector<cld> lstsq(CM P, std::vector<cld> z) {
 
 namespace {
 
-// Candidates from the Cholesky factor R of the Gram matrix (E = Q R):
-// coefficients over Y = [psi_2 .. psi_M] (M - 1 each).
-int candidates_from_R(const RM& R, int M, double dtau, std::vector<std::vector<double>>& coef,
-                      std::vector<double>& omega, std::string& err) {
+// Rank-r exact DMD of pairs (x_k, y_k) given in the orthonormal basis Q of
+// the snapshot span: AX, AY (M x n) hold their Q-coordinates, z those of the
+// vector the amplitudes are fitted to.  Returns the eigenvalues lam, and in
+// wy (n x r) the coordinates over the y columns of every mode's amplitude
+// times its eigenvector: mode q = sum_k wy(k, q) y_k = b_q phi_q.
+struct DmdFit {
+    std::vector<cld> lam;
+    CM wy;
+};
+bool dmd_fit(const RM& AX, const RM& AY, const std::vector<ld>& z, const RM& U, const std::vector<ld>& s,
+             const RM& V, int r, DmdFit& f, std::string& err) {
+    const int M = AX.r, n = AX.c;
+    RM B(M, r), At(r, r);   // B = AY V_r Sigma_r^{-1}, A~ = U_r^T B
+    for (int i = 0; i < M; ++i)
+        for (int q = 0; q < r; ++q) {
+            ld acc = 0;
+            for (int k = 0; k < n; ++k) acc += AY(i, k) * V(k, q);
+            B(i, q) = acc / s[q];
+        }
+    for (int p = 0; p < r; ++p)
+        for (int q = 0; q < r; ++q) {
+            ld acc = 0;
+            for (int i = 0; i < M; ++i) acc += U(i, p) * B(i, q);
+            At(p, q) = acc;
+        }
+    CM W;
+    if (!eig_general(At, f.lam, W)) {
+        err = "DMD eigenvalue iteration did not converge";
+        return false;
+    }
+    CM P(M, r);  // phi = Q P
+    for (int i = 0; i < M; ++i)
+        for (int q = 0; q < r; ++q) {
+            cld acc = 0;
+            for (int p = 0; p < r; ++p) acc += B(i, p) * W(p, q);
+            P(i, q) = acc;
+        }
+    std::vector<cld> zc(M);
+    for (int i = 0; i < M; ++i) zc[i] = z[i];
+    const std::vector<cld> b = lstsq(P, zc);
+    f.wy = CM(n, r);   // phi_q = Y V_r Sigma_r^{-1} w_q
+    for (int k = 0; k < n; ++k)
+        for (int q = 0; q < r; ++q) {
+            cld acc = 0;
+            for (int p = 0; p < r; ++p) acc += V(k, p) / s[p] * W(p, q);
+            f.wy(k, q) = acc * b[q];
+        }
+    return true;
+}
+
+int numerical_rank(const std::vector<ld>& s) {
+    if (s.empty() || !(s[0] > 0)) return 0;
+    int r = 0;
+    while (r < (int)s.size() && s[r] > (ld)kDmdRankTol * s[0]) ++r;
+    return r;
+}
+
+// Candidates from the Cholesky factor R of the Gram matrix (E = Q R), as
+// coefficients over psi_2 .. psi_M (M - 1 each); see dmd.hpp.
+int candidates_from_R(const RM& R, int M, double dtau, std::vector<DmdCandidate>& out, std::string& err) {
+    (void)dtau;   // the candidates depend on the eigenvalues only through lambda
     const int n = M - 1;
-    RM AX(M, n), AY(M, n);
-    std::vector<ld> z(M, 0);
+    // (R T)[i][k] = sum_{j <= k} R[i][j]: Q-coordinates of psi_{k+1}
+    RM RT(M, M);
     for (int i = 0; i < M; ++i) {
         ld acc = 0;
-        for (int k = 0; k < M; ++k) {  // (R T)[i][k] = sum_{j <= k} R[i][j]
+        for (int k = 0; k < M; ++k) {
             acc += R(i, k);
-            if (k < n) AX(i, k) = acc;
-            if (k >= 1) AY(i, k - 1) = acc;
+            RT(i, k) = acc;
         }
-        z[i] = acc;
+    }
+    // kind 0: snapshot pairs (psi_k, psi_{k+1}), amplitudes at psi_M
+    RM AX(M, n), AY(M, n);
+    std::vector<ld> z(M);
+    for (int i = 0; i < M; ++i) {
+        for (int k = 0; k < n; ++k) {
+            AX(i, k) = RT(i, k);
+            AY(i, k) = RT(i, k + 1);
+        }
+        z[i] = RT(i, M - 1);
     }
     RM U, V;
     std::vector<ld> s;
     svd_jacobi(AX, U, s, V);
-    if (s.empty() || !(s[0] > 0)) return 0;
-    int rstar = 0;
-    while (rstar < n && s[rstar] > (ld)kDmdRankTol * s[0]) ++rstar;
-    for (int r = 1; r <= rstar; ++r) {
-        RM B(M, r), At(r, r);   // B = AY V_r Sigma_r^{-1}, A~ = U_r^T B
-        for (int i = 0; i < M; ++i)
-            for (int q = 0; q < r; ++q) {
-                ld acc = 0;
-                for (int k = 0; k < n; ++k) acc += AY(i, k) * V(k, q);
-                B(i, q) = acc / s[q];
-            }
-        for (int p = 0; p < r; ++p)
-            for (int q = 0; q < r; ++q) {
-                ld acc = 0;
-                for (int i = 0; i < M; ++i) acc += U(i, p) * B(i, q);
-                At(p, q) = acc;
-            }
-        std::vector<cld> lam;
-        CM W;
-        if (!eig_general(At, lam, W)) {
-            err = "DMD eigenvalue iteration did not converge";
-            return -1;
+    const int rstar = numerical_rank(s);
+    // kind 1: difference pairs (d_k, d_{k+1}), d_k = psi_{k+1} - psi_k = Q R e_{k+1},
+    // amplitudes at the last difference
+    const int nd = M - 2;
+    RM DX(M, nd), DY(M, nd), Ud, Vd;
+    std::vector<ld> zd(M), sd;
+    for (int i = 0; i < M; ++i) {
+        for (int k = 0; k < nd; ++k) {
+            DX(i, k) = R(i, k + 1);
+            DY(i, k) = R(i, k + 2);
         }
-        int q1 = 0;
-        ld best = -1;
-        for (int q = 0; q < r; ++q) {
-            const ld mag = std::abs(std::log(lam[q]));
-            if (best < 0 || mag < best) {
-                best = mag;
-                q1 = q;
-            }
+        zd[i] = R(i, M - 1);
+    }
+    svd_jacobi(DX, Ud, sd, Vd);
+    const int rstar_d = (rstar > 0) ? numerical_rank(sd) : 0;
+    for (int r = 1; r <= std::max(rstar, rstar_d); ++r) {
+        if (r <= rstar) {   // Re(b_1 phi_1), the mode with the smallest |ln lambda|
+            DmdFit f;
+            if (!dmd_fit(AX, AY, z, U, s, V, r, f, err)) return -1;
+            int q1 = 0;
+            for (int q = 1; q < r; ++q)
+                if (std::abs(std::log(f.lam[q])) < std::abs(std::log(f.lam[q1]))) q1 = q;
+            DmdCandidate c{r, 0, std::vector<double>(n)};
+            for (int k = 0; k < n; ++k) c.coef[k] = (double)std::real(f.wy(k, q1));   // y_k = psi_{k+2}
+            out.push_back(std::move(c));
         }
-        CM P(M, r);  // phi = Q P
-        for (int i = 0; i < M; ++i)
+        if (r <= rstar_d) {   // psi_M + Re sum_{|lambda|<1} b_q phi_q lambda_q / (1 - lambda_q)
+            DmdFit f;
+            if (!dmd_fit(DX, DY, zd, Ud, sd, Vd, r, f, err)) return -1;
+            std::vector<ld> cy(nd, 0);   // over y_k = d_{k+2} = psi_{k+3} - psi_{k+2}
             for (int q = 0; q < r; ++q) {
-                cld acc = 0;
-                for (int p = 0; p < r; ++p) acc += B(i, p) * W(p, q);
-                P(i, q) = acc;
+                if (!(std::abs(f.lam[q]) < 1)) continue;
+                const cld g = f.lam[q] / (cld(1) - f.lam[q]);
+                for (int k = 0; k < nd; ++k) cy[k] += std::real(f.wy(k, q) * g);
             }
-        std::vector<cld> zc(M);
-        for (int i = 0; i < M; ++i) zc[i] = z[i];
-        const std::vector<cld> b = lstsq(P, zc);
-        std::vector<ld> c(n);
-        for (int k = 0; k < n; ++k) {  // Re(V_r Sigma_r^{-1} w_q1 b_q1)
-            cld acc = 0;
-            for (int p = 0; p < r; ++p) acc += V(k, p) / s[p] * W(p, q1);
-            c[k] = std::real(acc * b[q1]);
+            DmdCandidate c{r, 1, std::vector<double>(n, 0.0)};
+            std::vector<ld> cp(n, 0);   // over psi_{j+2}, j = 0..n-1
+            for (int k = 0; k < nd; ++k) {
+                cp[k + 1] += cy[k];
+                cp[k] -= cy[k];
+            }
+            cp[n - 1] += 1;   // psi_M
+            for (int k = 0; k < n; ++k) c.coef[k] = (double)cp[k];
+            out.push_back(std::move(c));
         }
-        std::vector<double> cy(n);
-        for (int k = 0; k < n; ++k) cy[k] = (double)c[k];
-        coef.push_back(cy);
-        omega.push_back((double)(best / (ld)dtau));
     }
     return rstar;
 }
 
 }  // namespace
 
-int dmd_candidates(const std::vector<long double>& Ge, int M, double dtau,
-                   std::vector<std::vector<double>>& coef, std::vector<double>& omega,
+int dmd_candidates(const std::vector<long double>& Ge, int M, double dtau, std::vector<DmdCandidate>& out,
                    std::string& err) {
-    coef.clear();
-    omega.clear();
+    out.clear();
     if (M < 3 || (int)Ge.size() != M * M || !(dtau > 0)) {
         err = "DMD needs at least 3 snapshots and dtau > 0";
         return -1;
@@ -390,7 +446,7 @@ int dmd_candidates(const std::vector<long double>& Ge, int M, double dtau,
     RM G(M, M);
     for (int i = 0; i < M; ++i)
         for (int j = 0; j < M; ++j) G(i, j) = 0.5L * (Ge[(size_t)i * M + j] + Ge[(size_t)j * M + i]);
-    return candidates_from_R(cholesky_upper(G), M, dtau, coef, omega, err);
+    return candidates_from_R(cholesky_upper(G), M, dtau, out, err);
 }
 
 }  // namespace pcfv

@@ -10,19 +10,30 @@ namespace pcfv {
 // snapshot matrix.
 constexpr double kDmdRankTol = 1e-7;
 
+// One extrapolation candidate: psi_s = sum_k coef[k] psi_{k+2} (k = 0..M-2).
+struct DmdCandidate {
+    int rank;                  // DMD truncation rank r
+    int kind;                  // 0: Re(b_1 phi_1), the mode of the snapshot DMD with the
+                               //    smallest |omega| (Sec. 6.2);
+                               // 1: the fixed point of the affine model fitted to the
+                               //    snapshot differences d_k = psi_{k+1} - psi_k:
+                               //    psi_M + Re sum_{|lambda_q| < 1} b_q phi_q lambda_q / (1 - lambda_q)
+    std::vector<double> coef;  // M - 1 real coefficients over psi_2..psi_M
+};
+
 // Snapshots psi_1..psi_M (M >= 3) are represented by the Gram matrix
 // Ge[i][j] = e_i . e_j (row-major, M x M) of E = [psi_1, psi_2 - psi_1, ..,
 // psi_M - psi_{M-1}], which keeps the small variations of a converging
 // window resolved.  Ge must be accurate well beyond double precision (the
 // Cholesky factor inherits its error times cond(E)^2); the device Gram is
-// accumulated in double-double.  For each rank r = 1..r*, coef[r-1] receives
-// the M-1 real coefficients c with psi_s(r) = sum_k c_k psi_{k+2}
-// (k = 0..M-2), the steady state Re(b_1 phi_1) of the rank-r exact DMD (mode
-// with the smallest |ln lambda|), and omega[r-1] its |omega| =
-// |ln lambda_1| / dtau.  Returns r* (0 if the window is degenerate); err gets
-// a message on failure (return -1).
-int dmd_candidates(const std::vector<long double>& Ge, int M, double dtau,
-                   std::vector<std::vector<double>>& coef, std::vector<double>& omega,
+// accumulated in double-double.  out receives, for r = 1, 2, .., the kind-0
+// candidate of the rank-r exact DMD of the snapshot pairs (r <= r*, the
+// numerical rank of [psi_1 .. psi_{M-1}]) and the kind-1 candidate of the
+// rank-r exact DMD of the difference pairs (r <= r*_d, the numerical rank of
+// [d_1 .. d_{M-2}]), amplitudes fitted at the last snapshot / difference, in
+// the order (rank, kind).  Returns r* (0 if the window is degenerate: then
+// no candidate); err gets a message on failure (return -1).
+int dmd_candidates(const std::vector<long double>& Ge, int M, double dtau, std::vector<DmdCandidate>& out,
                    std::string& err);
 
 }  // namespace pcfv

@@ -138,8 +138,13 @@ def config1_guess():
 def config2_guess():
     """32 x 33 x 32 streak + vortex seed: |kx| <= 1, kz in {1, 2}, Chebyshev
     degree <= 6 in every component, E = 5e-3, seed 2."""
-    return random_field(32, 33, 32, envelope=lambda k: 1.0, energy=5e-3, seed=2,
-                        vdeg=2, edeg=4,
+    return streak_vortex_guess(32, 33, 32, 5e-3, 2)
+
+
+def streak_vortex_guess(Nx, Ny, Nz, energy, seed, Lx=LX_W03, Lz=LZ_W03):
+    """The 32 x 33 x 32 recipe on any grid: |kx| <= 1, kz in {1, 2}, Chebyshev
+    degree <= 6 in every component."""
+    return random_field(Nx, Ny, Nz, Lx, Lz, envelope=lambda k: 1.0, energy=energy, seed=seed, vdeg=2, edeg=4,
                         mode_filter=lambda kx, kz: abs(kx) <= 1 and kz in (1, 2))
 
 

@@ -139,9 +139,9 @@ def load_library(path=_LIB_PATH):
     lib.pcfv_host_table.restype = ctypes.c_size_t
     lib.pcfv_host_table.argtypes = [cfgp, i, dp, ctypes.c_size_t]
     lib.pcfv_dmd_extrapolate.restype = i
-    lib.pcfv_dmd_extrapolate.argtypes = [vp, vp, i, d, vp, dp, ctypes.POINTER(i)]
+    lib.pcfv_dmd_extrapolate.argtypes = [vp, vp, i, d, vp, dp, ctypes.POINTER(i), ctypes.POINTER(i)]
     lib.pcfv_host_dmd.restype = i
-    lib.pcfv_host_dmd.argtypes = [dp, dp, i, d, dp, ctypes.c_size_t]
+    lib.pcfv_host_dmd.argtypes = [dp, dp, i, d, dp, ctypes.POINTER(i), i]
     lib.pcfv_autotune.restype = i
     lib.pcfv_autotune.argtypes = [vp, vp, i, ctypes.POINTER(TuneEntry), i, ctypes.POINTER(i)]
     lib.pcfv_get_tuning.restype = i
@@ -233,22 +233,22 @@ def host_table(cfg, which):
 
 
 def host_dmd(Ge_hi, dtau, Ge_lo=None):
-    """Host DMD algebra on the Gram matrix Ge_hi + Ge_lo of snapshot
-    differences: returns a list (one entry per rank r = 1..r*) of coefficient
-    vectors c (length M-1) with steady state sum_k c_k psi_{k+2}."""
-    dptr = ctypes.POINTER(ctypes.c_double)
+    """Host DMD algebra (test hook): the candidates [(rank, kind, coef)] of a
+    window from the Gram matrix of its snapshot differences."""
     hi = np.ascontiguousarray(Ge_hi, dtype=np.float64)
     M = hi.shape[0]
     lo = None if Ge_lo is None else np.ascontiguousarray(Ge_lo, dtype=np.float64)
-    if hi.shape != (M, M) or (lo is not None and lo.shape != (M, M)):
-        raise ValueError("Gram matrix must be square")
-    cap = M * (M - 1)
-    out = np.zeros(cap)
-    r = _lib.pcfv_host_dmd(hi.ctypes.data_as(dptr), None if lo is None else lo.ctypes.data_as(dptr),
-                           M, float(dtau), out.ctypes.data_as(dptr), cap)
-    if r < 0:
+    dptr = ctypes.POINTER(ctypes.c_double)
+    n = _lib.pcfv_host_dmd(hi.ctypes.data_as(dptr), None if lo is None else lo.ctypes.data_as(dptr), int(M),
+                           float(dtau), None, None, 0)
+    if n < 0:
         raise ValueError("invalid DMD input")
-    return [out[k * (M - 1):(k + 1) * (M - 1)] for k in range(r)]
+    coef = np.zeros((max(n, 1), M - 1))
+    labels = np.zeros(2 * max(n, 1), dtype=np.int32)
+    _lib.pcfv_host_dmd(hi.ctypes.data_as(dptr), None if lo is None else lo.ctypes.data_as(dptr), int(M),
+                       float(dtau), coef.ctypes.data_as(dptr), labels.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                       int(n))
+    return [(int(labels[2 * i]), int(labels[2 * i + 1]), coef[i]) for i in range(n)]
 
 
 def _ptr(t):
@@ -380,9 +380,10 @@ class Context:
             self._check(st)
         return st, rep.as_dict()
 
-    def dmd_extrapolate(self, snaps, dtau_snap):
+    def dmd_extrapolate(self, snaps, dtau_snap, with_kind=False):
         """snaps: device float64 tensor [M][batch][n_state] (M state vectors per
-        guess, oldest first).  Returns (u_s, cost(s), rank(s))."""
+        guess, oldest first).  Returns (u_s, cost(s), rank(s)) and, with
+        with_kind, the candidate kind(s) as a fourth item."""
         t = self.torch
         snaps = t.as_tensor(snaps).to(self.device, t.float64).contiguous()
         M = snaps.shape[0]
@@ -391,9 +392,11 @@ class Context:
         out = self.empty()
         cost = self._scalars(1)
         rank = (ctypes.c_int * self.batch)()
+        kind = (ctypes.c_int * self.batch)()
         self._check(_lib.pcfv_dmd_extrapolate(self._h, _ptr(snaps), int(M), float(dtau_snap), _ptr(out),
-                                              cost, rank))
-        return out, self._unbatch(cost, 1), self._unbatch(rank, 1)
+                                              cost, rank, kind))
+        res = (out, self._unbatch(cost, 1), self._unbatch(rank, 1))
+        return res + (self._unbatch(kind, 1),) if with_kind else res
 
     def norms(self, u):
         u = self._field(u)

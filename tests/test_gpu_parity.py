@@ -298,32 +298,46 @@ def _oracle_window(m, u, steps_before, nsnap, stride, dtau):
     return win
 
 
-def _dmd_tol(psis, r):
+def _dmd_tol(psis, r, kind=0):
     """1e3 * eps * s_1 / (s_r - s_{r+1}): the perturbation bound of the rank-r
-    DMD subspace for round-off at the snapshot scale."""
-    s = np.linalg.svd(np.asarray(psis)[:-1].T, compute_uv=False)
+    DMD subspace (of the snapshots for kind 0, of their differences for kind 1)
+    for round-off at the snapshot scale, relative to the result's max-norm."""
+    X = np.asarray(psis)
+    if kind == 1:
+        X = np.diff(X, axis=0)
+    s = np.linalg.svd(X[:-1].T, compute_uv=False)
     gap = s[r - 1] - (s[r] if r < len(s) else 0.0)
     return 1e3 * np.finfo(float).eps * s[0] / gap
 
 
-def test_dmd_extrapolate_matches_oracle(ctxs):
-    """Same oracle snapshots into both: the GPU picks the oracle's rank, its
-    state matches the oracle's steady state within the subspace bound, and the
-    cost it reports is the cost of the state it returns."""
+def _check_dmd_against_oracle(c, m, g, win, dtau_snap, label):
     from oracle import dmd
-    g, m, c = ctxs("cfg1")
-    win = _oracle_window(m, inputs.config1_guess(), 40, 10, 4, 0.02)
     psis = np.stack([state.pack(g, w) for w in win])
-    u_ref, c_ref, r_ref = dmd.extrapolate(m, win, 0.08)
-    u_s, cost, r = c.dmd_extrapolate(psis[:, None, :], 0.08)
+    u_ref, c_ref, r_ref, k_ref = dmd.extrapolate(m, win, dtau_snap)
+    u_s, cost, r, kind = c.dmd_extrapolate(psis[:, None, :], dtau_snap, with_kind=True)
     u_s = to_np(u_s)
-    print(f"[gpu] dmd rank {r} (oracle {r_ref}) cost {cost:.6e} (oracle {c_ref:.6e}) "
-          f"state rel err {rel(u_s, u_ref):.3e} tol {_dmd_tol(psis, r_ref):.1e}", flush=True)
-    assert r == r_ref
-    assert rel(u_s, u_ref) < _dmd_tol(psis, r_ref)
+    tol = _dmd_tol(psis, r_ref, k_ref) * max(1.0, np.abs(win[-1]).max() / np.abs(u_ref).max())
+    print(f"[gpu] dmd {label}: rank {r} kind {kind} (oracle {r_ref} {k_ref}) cost {cost:.6e} "
+          f"(oracle {c_ref:.6e}) state rel err {rel(u_s, u_ref):.3e} tol {tol:.1e}", flush=True)
+    assert (r, kind) == (r_ref, k_ref)
+    assert rel(u_s, u_ref) < tol
     assert abs(cost - m.cost(u_s)) < TOL * cost
     assert cost < m.cost(win[-1])
     assert max(c.check_state(u_s)) < 1e-15
+    return r, kind
+
+
+def test_dmd_extrapolate_matches_oracle(ctxs):
+    """Same oracle snapshots into both: a window of a descent heading for the
+    laminar state, and the same window shifted by a fixed admissible field (a
+    target with a non-zero fixed point).  The GPU picks the oracle's rank and
+    kind, its state matches the oracle's within the subspace bound, and the
+    cost it reports is the cost of the state it returns."""
+    g, m, c = ctxs("cfg1")
+    win = _oracle_window(m, inputs.config1_guess(), 40, 10, 4, 0.02)
+    _check_dmd_against_oracle(c, m, g, win, 0.08, "decaying window")
+    shift = guess(g, 44, 3e-3)
+    _check_dmd_against_oracle(c, m, g, [w + shift for w in win], 0.08, "shifted window")
 
 
 def test_dmd_extrapolate_batched_matches_single():
@@ -337,13 +351,14 @@ def test_dmd_extrapolate_batched_matches_single():
             for s, e in [(31, 1e-3), (32, 2e-3)]]
     psis = np.stack([np.stack([state.pack(g, w) for w in win]) for win in wins], axis=1)  # [M][B][n]
     cb = Context(16, 25, 16, batch=2)
-    ub, costb, rb = cb.dmd_extrapolate(psis, 0.06)
+    psis[:, 1, :] += state.pack(g, inputs.random_field(16, 25, 16, energy=3e-3, seed=34))  # a shifted target
+    ub, costb, rb, kb = cb.dmd_extrapolate(psis, 0.06, with_kind=True)
     c1 = Context(16, 25, 16)
     for b in range(2):
-        u1, cost1, r1 = c1.dmd_extrapolate(psis[:, b:b + 1, :], 0.06)
-        assert rb[b] == r1
+        u1, cost1, r1, k1 = c1.dmd_extrapolate(psis[:, b:b + 1, :], 0.06, with_kind=True)
+        assert (rb[b], kb[b]) == (r1, k1)
         assert rel(to_np(ub[b]), to_np(u1)) < 1e-14
-        assert abs(costb[b] - cost1) < 1e-14 * cost1
+        assert abs(costb[b] - cost1) <= 1e-14 * cost1
 
 
 def test_descend_with_dmd_equals_composed_entry_points(ctxs):
@@ -370,17 +385,19 @@ def test_descend_with_dmd_equals_composed_entry_points(ctxs):
         snaps.append(to_np(c.pack(v)))
         if k < W - 1:
             c.descend(v, max_steps=stride, dtau=dtau)
-    u_s, cost_s, r_s = c.dmd_extrapolate(np.stack(snaps)[:, None, :], stride * dtau)
+    u_s, cost_s, r_s, k_s = c.dmd_extrapolate(np.stack(snaps)[:, None, :], stride * dtau, with_kind=True)
     c.descend(u_s, max_steps=after, dtau=dtau)
     assert rel(to_np(u), to_np(u_s)) < 1e-15
     # oracle replay of the schedule
     win = _oracle_window(m, u0, 40, W, stride, dtau)
     psis = np.stack([state.pack(g, w) for w in win])
     snap_err = max(rel(a, b) for a, b in zip(snaps, psis))
-    u_ref, c_ref, r_ref = dmd.extrapolate(m, win, stride * dtau)
+    u_ref, c_ref, r_ref, k_ref = dmd.extrapolate(m, win, stride * dtau)
+    assert k_s == k_ref
     for _ in range(after):
         u_ref, _ = m.descent_step(u_ref, dtau)
-    tol = _dmd_tol(psis, r_ref) * max(1.0, snap_err / np.finfo(float).eps)
+    tol = (_dmd_tol(psis, r_ref, k_ref) * max(1.0, snap_err / np.finfo(float).eps) *
+           max(1.0, np.abs(win[-1]).max() / np.abs(u_ref).max()))
     print(f"[gpu] descend+dmd rank {r_s} (oracle {r_ref}) snapshot err {snap_err:.2e} "
           f"state rel err {rel(to_np(u), u_ref):.3e} tol {tol:.1e}", flush=True)
     assert r_s == r_ref

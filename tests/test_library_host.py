@@ -213,31 +213,50 @@ def _exact_gram(E):
     return hi, lo
 
 
+def _check_host_candidates(snaps, dtau):
+    """The library's candidates equal the oracle's, label by label, within
+    1e3 * eps * s_1 / (s_r - s_{r+1}) (the first-order perturbation bound of
+    the rank-r singular subspace both sides compute, relative to the snapshot
+    scale); returns them."""
+    from oracle import dmd
+    E = np.vstack([snaps[0], np.diff(snaps, axis=0)])
+    hi, lo = _exact_gram(E)
+    got = pcfv.host_dmd(hi, dtau, lo)
+    rstar = dmd.numerical_rank(snaps)
+    want = dmd.candidates(snaps, dtau, rstar)
+    assert [(r, k) for r, k, _ in got] == [(r, k) for r, k, _ in want]
+    s = np.linalg.svd(snaps[:-1].T, compute_uv=False)
+    for (r, k, c), (_, _, ref) in zip(got, want):
+        psi = c @ snaps[1:]
+        gap = s[r - 1] - (s[r] if r < len(s) else 0.0)
+        tol = 1e3 * np.finfo(float).eps * s[0] / gap
+        # kind 1 sums a geometric series from psi_M: its error scales with the snapshots
+        scale = np.abs(ref).max() if k == 0 else max(np.abs(ref).max(), np.abs(snaps).max())
+        assert np.abs(psi - ref).max() <= tol * scale, (r, k, tol)
+    return got
+
+
 @pytest.mark.parametrize("nmodes,M", [(1, 4), (3, 8), (6, 20)])
 def test_host_dmd_matches_oracle_on_affine_windows(nmodes, M):
     """Affine dynamics with a known fixed point psi*: the library's Gram-based
-    DMD algebra returns the numerical rank of the oracle's SVD, recovers psi*
-    at full rank like the oracle does, and at every truncated rank agrees with
-    the oracle's steady state within 1e3 * eps * s_1 / (s_r - s_{r+1}) (the
-    first-order perturbation bound of the rank-r singular subspace that both
-    sides compute, relative to the snapshot scale)."""
+    DMD algebra gives the oracle's candidates (same ranks and kinds, same
+    states) and recovers psi* at full rank."""
     from test_oracle_dmd import affine_window
-    from oracle import dmd
     snaps, psi_star, _ = affine_window(200, nmodes, M, seed=nmodes)
-    E = np.vstack([snaps[0], np.diff(snaps, axis=0)])
-    hi, lo = _exact_gram(E)
-    coefs = pcfv.host_dmd(hi, 1.0, lo)
-    rstar = dmd.numerical_rank(snaps)
-    assert len(coefs) == rstar == nmodes + 1
-    s = np.linalg.svd(snaps[:-1].T, compute_uv=False)
-    for r, c in enumerate(coefs, start=1):
-        psi = c @ snaps[1:]
-        ref, _ = dmd.steady_state(snaps, 1.0, r)
-        gap = s[r - 1] - (s[r] if r < len(s) else 0.0)
-        tol = 1e3 * np.finfo(float).eps * s[0] / gap
-        assert np.abs(psi - ref).max() <= tol * np.abs(ref).max(), (r, tol)
-    psi = coefs[-1] @ snaps[1:]
-    assert np.abs(psi - psi_star).max() < 1e-9 * np.abs(psi_star).max()
+    got = _check_host_candidates(snaps, 1.0)
+    assert max(r for r, _, _ in got) == nmodes + 1
+    full = [c for r, k, c in got if r == nmodes + 1 and k == 0][0]
+    assert np.abs(full @ snaps[1:] - psi_star).max() < 1e-9 * np.abs(psi_star).max()
+
+
+def test_host_dmd_affine_limit_of_a_decaying_window_is_the_origin():
+    """Every mode decaying (psi* = 0): the full-rank kind-1 candidate is the
+    origin to round-off, as in the oracle."""
+    from test_oracle_dmd import decaying_window
+    snaps = decaying_window(120, [0.03, 0.1, 0.25], 10, seed=4)
+    got = _check_host_candidates(snaps, 1.0)
+    lim = [c for r, k, c in got if r == 3 and k == 1]
+    assert len(lim) == 1 and np.abs(lim[0] @ snaps[1:]).max() < 1e-10 * np.abs(snaps).max()
 
 
 def test_host_dmd_rank_one_window_and_invalid_input():
@@ -247,9 +266,9 @@ def test_host_dmd_rank_one_window_and_invalid_input():
     psi = np.random.default_rng(4).standard_normal(50)
     snaps = np.array([psi] * 5)
     E = np.vstack([snaps[0], np.diff(snaps, axis=0)])
-    coefs = pcfv.host_dmd(E @ E.T, 0.5)
-    assert len(coefs) == 1
-    np.testing.assert_allclose(coefs[0] @ snaps[1:], psi, rtol=1e-14, atol=0)
+    cands = pcfv.host_dmd(E @ E.T, 0.5)
+    assert [(r, k) for r, k, _ in cands] == [(1, 0)]
+    np.testing.assert_allclose(cands[0][2] @ snaps[1:], psi, rtol=1e-14, atol=0)
     with pytest.raises(ValueError):
         pcfv.host_dmd(np.eye(2), 1.0)
     with pytest.raises(ValueError):

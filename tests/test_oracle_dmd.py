@@ -57,8 +57,8 @@ def test_extrapolation_of_a_descent_window_lowers_the_cost():
             window.append(u.copy())
         u, _ = m.descent_step(u, 0.02)
     c_now = m.cost(window[-1])
-    u_s, c_s, r = dmd.extrapolate(m, window, 4 * 0.02)
-    assert r >= 1 and u_s is not None
+    u_s, c_s, r, kind = dmd.extrapolate(m, window, 4 * 0.02)
+    assert r >= 1 and kind >= 0 and u_s is not None
     assert max(m.defects(u_s)) < 1e-12
     assert c_s < c_now
 
@@ -79,19 +79,22 @@ def test_numerical_rank_counts_singular_values_of_the_first_m_minus_1_snapshots(
 
 
 def test_rank_is_chosen_by_least_true_cost(monkeypatch):
-    """Sec. 6.2: among r = 1..r*, the rank whose extrapolated state has the
-    smallest cost is taken.  With a stub DMD whose rank-r steady state is
-    marked by its first entry and a stub cost table, the choice must be the
-    argmin over r <= r* (not the largest rank, not beyond r*), returning that
-    candidate, its cost and r."""
+    """Sec. 6.2: among the candidates of ranks r = 1..r*, the one whose
+    extrapolated state has the smallest cost is taken.  With a stub candidate
+    list (the rank marked in each state's first entry) and a stub cost table,
+    the choice must be the argmin over r <= r* (not the largest rank, not
+    beyond r*), returning that candidate, its cost, r and its kind."""
     g = Grid(6, 9, 6)
     n = g.n_state()
     table = {1: 3.0, 2: 1.0, 3: 2.0, 4: 0.5, 5: 4.0, 6: 0.1}
 
-    def fake_steady(psis, dtau, r):
-        psi = np.zeros(n)
-        psi[0] = r
-        return psi, 0.0
+    def fake_candidates(psis, dtau, rstar):
+        out = []
+        for r in range(1, rstar + 1):
+            psi = np.zeros(n)
+            psi[0] = r
+            out.append((r, r % 2, psi))
+        return out
 
     class StubMethod:
         def __init__(self):
@@ -100,11 +103,59 @@ def test_rank_is_chosen_by_least_true_cost(monkeypatch):
         def cost(self, u):
             return table[int(round(state.pack(g, u)[0]))]
 
-    monkeypatch.setattr(dmd, "steady_state", fake_steady)
+    monkeypatch.setattr(dmd, "candidates", fake_candidates)
     monkeypatch.setattr(dmd, "numerical_rank", lambda psis, tol=dmd.RANK_TOL: 5)
     fields = [state.unpack(g, np.full(n, float(k))) for k in range(4)]
-    u_s, c_s, r = dmd.extrapolate(StubMethod(), fields, 1.0)
-    assert (r, c_s) == (4, 0.5)
+    u_s, c_s, r, kind = dmd.extrapolate(StubMethod(), fields, 1.0)
+    assert (r, c_s, kind) == (4, 0.5, 0)
     assert state.pack(g, u_s)[0] == 4.0
     monkeypatch.setattr(dmd, "numerical_rank", lambda psis, tol=dmd.RANK_TOL: 0)
-    assert dmd.extrapolate(StubMethod(), fields, 1.0) == (None, np.inf, 0)
+    assert dmd.extrapolate(StubMethod(), fields, 1.0) == (None, np.inf, 0, -1)
+
+
+def decaying_window(n, rates, M, seed, psi_star=None):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, len(rates))))
+    c0 = rng.standard_normal(len(rates))
+    base = np.zeros(n) if psi_star is None else psi_star
+    return np.array([base + Q @ (c0 * np.exp(-np.asarray(rates) * k)) for k in range(M)])
+
+
+def test_affine_limit_of_a_decaying_window_is_the_origin():
+    """psi_{k+1} = A psi_k with every mode decaying (a trajectory heading for
+    the laminar state, psi* = 0): the full-rank affine limit (kind 1) from the
+    differences is the origin to round-off, while the paper's smallest-|omega|
+    candidate (kind 0) keeps the slowest mode's current part."""
+    rates = [0.03, 0.1, 0.25]
+    snaps = decaying_window(120, rates, 10, seed=4)
+    r = dmd.numerical_rank(snaps)
+    assert r == 3 and dmd.numerical_rank(np.diff(snaps, axis=0)) == 3
+    cands = {(rr, k): psi for rr, k, psi in dmd.candidates(snaps, 1.0, r)}
+    scale = np.abs(snaps[-1]).max()
+    assert np.abs(cands[(3, 1)]).max() < 1e-10 * scale
+    lam, omega, Phi, b = dmd.dmd(snaps, 1.0, 3)
+    q = int(np.argmin(np.abs(omega)))
+    assert abs(omega[q].real + 0.03) < 1e-9
+    slow = np.real(b[q] * Phi[:, q])
+    np.testing.assert_allclose(cands[(3, 0)], slow, rtol=0, atol=1e-12)
+    assert np.abs(slow).max() > 0.1 * scale
+    # a truncated affine fit is not exact
+    assert np.abs(cands[(1, 1)]).max() > 1e-6 * scale
+
+
+def test_affine_limit_recovers_a_nonzero_fixed_point():
+    """Affine dynamics around psi* != 0, with one slow mode (rate 1e-3): both
+    the paper's candidate at full rank and the affine limit of the differences
+    at full rank return psi*; the geometric-series gain lambda/(1 - lambda)
+    sums the slow mode's whole future decay."""
+    rng = np.random.default_rng(8)
+    psi_star = rng.standard_normal(150)
+    snaps = decaying_window(150, [1e-3, 0.2, 0.5], 12, seed=5, psi_star=psi_star)
+    r = dmd.numerical_rank(snaps)
+    rd = dmd.numerical_rank(np.diff(snaps, axis=0))
+    assert (r, rd) == (4, 3)
+    cands = {(rr, k): psi for rr, k, psi in dmd.candidates(snaps, 1.0, r)}
+    np.testing.assert_allclose(cands[(4, 0)], psi_star, rtol=0, atol=1e-8 * np.abs(psi_star).max())
+    np.testing.assert_allclose(cands[(3, 1)], psi_star, rtol=0, atol=1e-8 * np.abs(psi_star).max())
+    assert (4, 1) not in cands
+    assert [k for rr, k in cands if rr <= 3] == [0, 1] * 3
