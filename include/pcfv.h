@@ -92,12 +92,16 @@ typedef struct {
     int batch;
 } pcfv_config;
 
+/* Layout of the spectral fields of a context: complex value (b, c, ikx, kz, n)
+ * at offset b stride_b + c stride_c + ikx stride_kx + kz stride_kz + n
+ * (in complex values; n is contiguous). */
 typedef struct {
     int Kx, Kz, Ny, nkx, nkz;
     long long n_modes;   /* nkx * nkz                                   */
-    long long n_complex; /* 3 * n_modes * Ny: complex values per field  */
+    long long n_complex; /* 3 * n_modes * Ny: complex values per guess  */
     long long n_state;   /* length of the minimal real state vector of one guess */
     int batch;
+    long long stride_b, stride_c, stride_kx, stride_kz;
 } pcfv_layout;
 
 /* Bytes of device workspace pcfv_create needs for this configuration;
@@ -178,6 +182,12 @@ typedef struct {
      * the DMD candidate; each guess takes the cheaper of the two by true
      * cost, under the same dmd_accept rule. */
     const struct pcfv_learned_model* learned;
+    /* With no_cost_checks != 0 and nothing above that reads the cost (rel_tol
+     * = 0, grow_tol <= 0, no DMD, fp64_below <= 0), the call enqueues
+     * max_steps steps and returns without evaluating the cost or
+     * synchronising; the report's cost and rel_res are then NaN.  (Every step
+     * still forms its per-mode cost partials on the device.) */
+    int no_cost_checks;
 } pcfv_descent_opts;
 
 typedef struct {
@@ -246,18 +256,20 @@ pcfv_status pcfv_unpack_state(pcfv_ctx* ctx, const double* psi, double* u);
  * kz = 0 (3 * batch doubles); synchronises. */
 pcfv_status pcfv_check_state(pcfv_ctx* ctx, const double* u, double* defects_host);
 
-/* Average device time per launch, in milliseconds, of each kernel of one
- * descent step, measured with HIP events on the context stream over nrep
- * launches each (u is left unchanged).  ms_out[0..4] = synthesis, forward
- * products, residual/adjoint-solve per mode, adjoint products, gradient/
- * projection/update per mode.  Returns the number of entries via *n_out. */
-/* nsteps plain descent steps of u (in place, step dtau) with HIP events on the
+/* Measurement hook (used by the benchmark, not part of the method): nsteps
+ * plain descent steps of u (in place, step dtau) with HIP events on the
  * context stream around each kernel: ms_out[0..3] = average device time per
  * launch, in milliseconds, of the forward products, the residual/adjoint-solve
  * per mode, the adjoint products and the gradient/projection/update per mode,
  * as they run inside consecutive steps.  1 <= nsteps <= 4096.  Synchronises. */
 pcfv_status pcfv_time_descent_kernels(pcfv_ctx* ctx, double* u, double dtau, int nsteps, double* ms_out);
 
+/* Measurement hook (used by the benchmark, not part of the method): average
+ * device time per launch, in milliseconds, of each kernel of one descent
+ * step, measured with HIP events on the context stream over nrep launches
+ * each (u is left unchanged).  ms_out[0..4] = synthesis, forward products,
+ * residual/adjoint-solve per mode, adjoint products, gradient/projection/
+ * update per mode; *n_out receives the number of entries.  Synchronises. */
 pcfv_status pcfv_time_kernels(pcfv_ctx* ctx, const double* u, int nrep, double* ms_out,
                               int* n_out);
 
@@ -296,18 +308,31 @@ pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads, in
 pcfv_status pcfv_set_tuning(pcfv_ctx* ctx, int xs, int plane_threads, int mode_threads);
 
 /* Groups (batching over uneven grids): n contexts, each with its own grid,
- * Re, batch and tables but one precision, are advanced together; every
- * descent step is one launch per stage (physical-space forward, residual and
- * transposed solve, physical-space adjoint, gradient/projection/update) over
- * all members, so small members share the chip instead of running one after
- * another.  The group owns a stream and n + 1 small device records; the
- * members (and their workspaces) must outlive it.  The physical-space work
- * group size is members[0]'s; the per-mode one, the slab width and the LDS
- * staging follow the single-context default rules applied to the modes of all
- * members together. */
+ * Re, batch and tables but one precision at creation, are advanced together;
+ * every descent step is one launch per stage (physical-space forward,
+ * residual and transposed solve, physical-space adjoint, gradient/projection/
+ * update) over all members (two per stage while some members have switched
+ * from FP32 to FP64), so small members share the chip instead of running one
+ * after another.  The physical-space work-group size is members[0]'s; the
+ * per-mode one, the slab width and the LDS staging follow the single-context
+ * default rules applied to the modes of all members together.
+ *
+ * Memory and streams: the group allocates nothing on the device.  workspace:
+ * caller-owned device memory of pcfv_group_workspace_bytes(members, n) bytes,
+ * 256-byte aligned, holding the members' device records and, for members
+ * whose padded Ny differs from the group's, their tables at the group's
+ * stride (copied in synchronously by pcfv_group_create).  hip_stream: the
+ * caller's stream (NULL = the default stream) on which every group launch is
+ * enqueued; a HIP graph (graph_steps > 0) needs a non-NULL stream.  Members,
+ * their workspaces and the group workspace must outlive the group.
+ * pcfv_group_workspace_bytes returns 0 for invalid members (NULL, or mixed
+ * precisions). */
 typedef struct pcfv_group pcfv_group;
-pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out);
-void pcfv_group_destroy(pcfv_group* group);
+size_t pcfv_group_workspace_bytes(pcfv_ctx* const* members, int n);
+pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, void* hip_stream, void* workspace,
+                              pcfv_group** out);
+void pcfv_group_destroy(pcfv_group* group);   /* never touches caller memory */
+pcfv_status pcfv_group_set_stream(pcfv_group* group, void* hip_stream);
 /* steps plain descent steps (Sec. 4 step (5)) of every member: u[k] is member
  * k's field array (device, in place), dtau[k] its step.  graph_steps > 0
  * captures that many steps in a HIP graph once (reused across calls, since
@@ -317,6 +342,35 @@ void pcfv_group_destroy(pcfv_group* group);
  * member afterwards. */
 pcfv_status pcfv_group_descend(pcfv_group* group, double* const* u, const double* dtau, long long steps,
                                int graph_steps);
+/* Descent of every member to a tolerance (Sec. 4 step (5), Sec. 6.2 for the
+ * DMD windows).  Every check_every steps each active member's cost and
+ * relative residual ||r||_W / ||u_b + u||_W (largest over its guesses) are
+ * read back; a member stops once it is below rel_tol (and, on a PCFV_MIXED
+ * group with fp64_below > 0, past its FP64 switch), or with PCFV_ENAN on a
+ * non-finite cost; the others go on.  With fp64_below > 0 a PCFV_MIXED
+ * member switches to FP64 once below fp64_below (its y-values are rebuilt in
+ * FP64; from then on its stages run in the FP64 launches).  dmd_window > 0:
+ * every dmd_stride steps each active member's state vector goes into its
+ * window (dmd_buffers[k]: device, dmd_window * batch_k * n_state_k doubles,
+ * caller-owned); a full window is extrapolated as pcfv_dmd_extrapolate does
+ * and each guess whose best candidate costs less than dmd_accept times its
+ * current cost restarts from it.  reports[k] and status[k] (n each) give
+ * member k's steps, fp32 steps, cost, relative residual, DMD counts and
+ * PCFV_OK / PCFV_ENOTCONV (max_steps reached) / PCFV_ENAN.  Returns PCFV_OK
+ * if every member converged, else the first failing status (PCFV_ENAN
+ * first).  Synchronises. */
+typedef struct {
+    long long max_steps;   /* group steps at most                                */
+    double rel_tol;        /* > 0                                               */
+    int check_every;       /* cost read-back period in steps (>= 1)              */
+    double fp64_below;     /* FP32 -> FP64 switch (PCFV_MIXED groups; <= 0: none) */
+    int dmd_window;        /* snapshots per DMD window (0: no DMD; 3..256)        */
+    int dmd_stride;        /* steps between snapshots                            */
+    double dmd_accept;     /* accept a candidate below dmd_accept x current cost  */
+    double* const* dmd_buffers;   /* n device buffers (see above)                */
+} pcfv_group_opts;
+pcfv_status pcfv_group_descend_tol(pcfv_group* group, double* const* u, const double* dtau,
+                                   const pcfv_group_opts* opts, pcfv_descent_report* reports, int* status);
 const char* pcfv_group_last_error(const pcfv_group* group);
 
 /* ---------------------------------------------------------------------------
@@ -457,8 +511,8 @@ pcfv_status pcfv_mlp_fit(pcfv_mlp* mlp, const float* X, const float* T, int N, i
 pcfv_status pcfv_learned_propose(pcfv_ctx* ctx, const pcfv_learned_model* model, const double* snaps,
                                  const double* base, double* u_out, double* cost_host);
 
-/* Host-side copy of a constant table for cfg, computed without a device (for
- * tests of the setup arithmetic).  which: 0 fixed matrices (27 slots of
+/* Test hook (no device): host-side copy of a constant table for cfg, computed
+ * without a device (for tests of the setup arithmetic).  which: 0 fixed matrices (27 slots of
  * Ny x Ny, each matrix stored transposed), 1 per-mode scalars, 2 Helmholtz diagonals,
  * 3 Poisson diagonals, 4 projection diagonals, 5 homogeneous v responses,
  * 6 their derivatives, 7 inverse influence matrices, 8 eigenvalues of the tau

@@ -12,7 +12,8 @@ last snapshot (least squares).
 Sec. 6.2: the mode with the smallest |omega| is taken as the steady state,
 psi_s = b_1 phi_1 (real part; the data are real), and the truncation rank
 r <= r* (r* = numerical rank of Psi) is the one whose extrapolated state has
-the smallest cost J.
+the smallest cost J (the paper found it at r = r*; the ranks tried here are
+r*, r* - 1, r* - 2, r* - 4, ..., see rank_tried).
 
 Reading for targets the paper's rule cannot reach.  The smallest-|omega|
 mode is the limit of the linear model only when one mode neither grows nor
@@ -78,17 +79,25 @@ def affine_limit(snaps, dtau, r):
     return S[-1] + np.real(Phi @ (b * gain))
 
 
+def rank_tried(r, rstar):
+    """Ranks fitted for numerical rank r*: r*, r* - 1, r* - 2, r* - 4, r* - 8,
+    ... (>= 1).  Sec. 6.2 takes the least-cost rank r <= r* and found it at
+    r*; every rank would cost O(M^5) work and M cost evaluations per window."""
+    d = rstar - r
+    return 1 <= r <= rstar and (d <= 2 or (d & (d - 1)) == 0)
+
+
 def candidates(snaps, dtau, rstar):
-    """[(rank, kind, psi)]: kind 0 the paper's smallest-|omega| mode for
-    r <= rstar, kind 1 the affine limit for r <= r*_d, ordered by rank, then
-    kind."""
+    """[(rank, kind, psi)]: kind 0 the paper's smallest-|omega| mode for the
+    ranks tried below r*, kind 1 the affine limit for those below r*_d,
+    ordered by rank, then kind."""
     S = np.asarray(snaps, dtype=float)
     rstar_d = numerical_rank(np.diff(S, axis=0)) if rstar > 0 else 0
     out = []
     for r in range(1, max(rstar, rstar_d) + 1):
-        if r <= rstar:
+        if rank_tried(r, rstar):
             out.append((r, 0, steady_state(S, dtau, r)[0]))
-        if r <= rstar_d:
+        if rank_tried(r, rstar_d):
             out.append((r, 1, affine_limit(S, dtau, r)))
     return out
 

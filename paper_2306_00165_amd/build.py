@@ -29,26 +29,33 @@ def _run(cmd):
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
 
 
-def _headers():
-    out = []
-    for d in (os.path.join(HERE, "csrc"), os.path.join(ROOT, "include")):
-        out += [os.path.join(d, f) for f in os.listdir(d) if f.endswith((".h", ".hpp"))]
-    return out
+def _deps(path, seen=None):
+    """The file and every local header it includes, recursively."""
+    import re
+    seen = set() if seen is None else seen
+    path = os.path.normpath(path)
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    with open(path) as f:
+        for inc in re.findall(r'^\s*#include\s+"([^"]+)"', f.read(), re.M):
+            _deps(os.path.join(os.path.dirname(path), inc), seen)
+    return seen
 
 
 def build(verbose=False, jobs=None, incremental=False):
     """Compile every source into paper_2306_00165_amd/_lib/libpcfv.so.  With
-    incremental, objects newer than their source and every header are kept."""
+    incremental, objects newer than their source and the headers it includes
+    are kept."""
     os.makedirs(LIB_DIR, exist_ok=True)
     os.makedirs(OBJ_DIR, exist_ok=True)
-    newest_header = max(os.path.getmtime(h) for h in _headers())
     objs, cmds = [], []
     for s in SOURCES:
         o = os.path.join(OBJ_DIR, os.path.basename(s) + ".o")
         objs.append(o)
         src = os.path.join(HERE, s)
         if (incremental and os.path.exists(o) and
-                os.path.getmtime(o) > max(os.path.getmtime(src), newest_header)):
+                os.path.getmtime(o) > max(os.path.getmtime(d) for d in _deps(src))):
             continue
         cmds.append([HIPCC] + FLAGS + ["-c", src, "-o", o])
     if verbose:

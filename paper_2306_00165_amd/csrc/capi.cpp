@@ -3,12 +3,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <limits>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pcfv.h"
@@ -393,14 +395,31 @@ pcfv_status dmd_core(pcfv_ctx* ctx, const double* snaps, int M, double dtau, dou
     PCFV_TRY(hipMemcpyAsync(G.data(), ctx->dmdG, (size_t)B * gbytes, hipMemcpyDeviceToHost, ctx->stream),
              "copy gram");
     PCFV_TRY(hipStreamSynchronize(ctx->stream), "synchronize");
+    // the guesses' small dense algebra, spread over host threads
     std::vector<std::vector<DmdCandidate>> cands(B);
-    size_t nslots = 0;
-    for (int b = 0; b < B; ++b) {
+    std::vector<std::string> errs(B);
+    std::vector<int> rs(B, 0);
+    auto work = [&](int b) {
         std::vector<long double> Gb((size_t)M * M);
         for (size_t k = 0; k < Gb.size(); ++k)
             Gb[k] = (long double)G[((size_t)b * M * M + k) * 2] + (long double)G[((size_t)b * M * M + k) * 2 + 1];
-        std::string err;
-        if (dmd_candidates(Gb, M, dtau, cands[b], err) < 0) return fail(ctx, PCFV_EINVAL, err);
+        rs[b] = dmd_candidates(Gb, M, dtau, cands[b], errs[b]);
+    };
+    const int nth = std::max(1, std::min<int>(B, (int)std::thread::hardware_concurrency()));
+    if (nth == 1) {
+        for (int b = 0; b < B; ++b) work(b);
+    } else {
+        std::atomic<int> next{0};
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t)
+            pool.emplace_back([&]() {
+                for (int b = next++; b < B; b = next++) work(b);
+            });
+        for (auto& th : pool) th.join();
+    }
+    size_t nslots = 0;
+    for (int b = 0; b < B; ++b) {
+        if (rs[b] < 0) return fail(ctx, PCFV_EINVAL, errs[b]);
         nslots = std::max(nslots, cands[b].size());
     }
     best_cost.assign(B, std::numeric_limits<double>::infinity());
@@ -552,6 +571,10 @@ pcfv_status pcfv_get_layout(const pcfv_ctx* ctx, pcfv_layout* out) {
     out->n_complex = 3LL * p.nm * p.N;
     out->n_state = ctx->t.n_state;
     out->batch = p.B;
+    out->stride_kz = p.N;
+    out->stride_kx = (long long)p.nkz * p.N;
+    out->stride_c = (long long)p.nm * p.N;
+    out->stride_b = 3LL * p.nm * p.N;
     return PCFV_OK;
 }
 
@@ -679,6 +702,18 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
         return true;
     };
     PCFV_TRY(launch_synth(p, ctx->stream, cd(u), ctx->Y), "synth");
+    if (o->no_cost_checks && !(o->rel_tol > 0) && !(o->grow_tol > 0) && !use_dmd && !(o->fp64_below > 0)) {
+        // nothing reads the cost: max_steps steps, enqueued without a host sync
+        for (; steps < o->max_steps; ++steps) {
+            pcfv_status s1 = descent_step(ctx, u, dtau);
+            if (s1 != PCFV_OK) return s1;
+        }
+        tau = steps * dtau;
+        if (ctx->kp.prec == PREC_FP32) steps32 = steps;
+        report(PCFV_OK);
+        rep->cost = rep->rel_res = std::numeric_limits<double>::quiet_NaN();
+        return PCFV_OK;
+    }
     pcfv_status s = cost_and_norm(ctx, u, cost, ntot);
     if (s != PCFV_OK) return s;
     if (!finite()) return report(fail(ctx, PCFV_ENAN, "cost is not finite"));
@@ -1029,13 +1064,14 @@ pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads, in
 
 struct pcfv_group {
     std::vector<pcfv_ctx*> members;
-    std::vector<GroupMember> host;   // n + 1 records (the last is the sentinel)
-    GroupMember* dev = nullptr;      // device copy
-    GroupLaunch gl{};
-    hipStream_t stream = nullptr;
-    int graph_steps = 0;             // steps captured in `exec` (0: none)
+    int prec0 = PREC_FP64;             // the members' precision at creation
+    std::vector<GroupMember> base;     // per-member records (tables at the group's np)
+    GroupMember* dev[2] = {nullptr, nullptr};   // device records per precision (n + 1 each), in the workspace
+    std::vector<GroupMember> host[2];
+    GroupLaunch gl[2]{};
+    hipStream_t stream = nullptr;      // the caller's
+    int graph_steps = 0;               // steps captured in `exec` (0: none)
     hipGraphExec_t exec = nullptr;
-    std::vector<double*> mats;       // members' fixed matrices re-padded to the group's np
     std::string err;
 };
 
@@ -1046,15 +1082,105 @@ pcfv_status gfail(pcfv_group* g, pcfv_status s, const std::string& msg) {
     return s;
 }
 
+#define PCFV_TRY_G(expr, what) PCFV_GTRY(expr, what)
+
 #define PCFV_GTRY(expr, what)                                                                  \
     do {                                                                                      \
         hipError_t _e = (expr);                                                               \
         if (_e != hipSuccess) return gfail(g, PCFV_EDEVICE, std::string(what) + ": " + hipGetErrorString(_e)); \
     } while (0)
 
+// Workspace of a group: two record arrays of n + 1 entries (FP32 and FP64
+// subsets), then the fixed matrices of every member whose padded Ny differs
+// from the group's, re-padded to the group's.
+struct GroupWs {
+    size_t rec[2], mats_at, total;
+    std::vector<size_t> mats;   // per member: offset, or SIZE_MAX if none
+    int np, pthreads, mthreads;
+    bool many;
+};
+
+bool group_ws(pcfv_ctx* const* m, int n, GroupWs& L, std::string& e) {
+    if (!m || n < 1) {
+        e = "invalid group arguments";
+        return false;
+    }
+    for (int k = 0; k < n; ++k)
+        if (!m[k] || m[k]->kp.prec != m[0]->kp.prec) {
+            e = "group members must be non-NULL and share one precision";
+            return false;
+        }
+    long long group_modes = 0;
+    L.np = 0;
+    for (int k = 0; k < n; ++k) {
+        group_modes += m[k]->kp.nmB;
+        L.np = std::max(L.np, m[k]->kp.np);
+    }
+    L.many = group_modes > 1024;
+    L.pthreads = L.many ? 1024 : m[0]->kp.pthreads;   // the single-context default for many modes
+    L.mthreads = m[0]->kp.mthreads;
+    size_t o = 0;
+    for (int p = 0; p < 2; ++p) {
+        L.rec[p] = o;
+        o += up(sizeof(GroupMember) * (n + 1));
+    }
+    L.mats_at = o;
+    L.mats.assign(n, SIZE_MAX);
+    for (int k = 0; k < n; ++k)
+        if (m[k]->kp.np != L.np) {
+            L.mats[k] = o;
+            o += up((size_t)M_COUNT * L.np * mat_ld(L.np) * 8);
+        }
+    L.total = o;
+    return true;
+}
+
+// Device records of the members idx in precision prec (sentinel last).
+pcfv_status upload_records(pcfv_group* g, int prec, const std::vector<int>& idx, double* const* u,
+                           const double* dtau) {
+    const int slot = (prec == PREC_FP32) ? 0 : 1;
+    GroupLaunch& gl = g->gl[slot];
+    std::vector<GroupMember>& host = g->host[slot];
+    host.assign(idx.size() + 1, GroupMember{});
+    long long items[2] = {0, 0};
+    for (size_t i = 0; i < idx.size(); ++i) {
+        GroupMember m = g->base[idx[i]];
+        m.kp.prec = prec;
+        m.item0[GPH_PLANE] = (int)items[GPH_PLANE];
+        m.item0[GPH_MODE] = (int)items[GPH_MODE];
+        items[GPH_PLANE] += (long long)m.kp.B * m.kp.NS * m.kp.N;
+        items[GPH_MODE] += m.kp.nmB;
+        m.u = dd(u[idx[i]]);
+        m.dtau = dtau[idx[i]];
+        host[i] = m;
+    }
+    if (items[0] > INT_MAX / 2 || items[1] > INT_MAX / 2) return gfail(g, PCFV_EINVAL, "group too large");
+    host.back().item0[GPH_PLANE] = (int)items[GPH_PLANE];
+    host.back().item0[GPH_MODE] = (int)items[GPH_MODE];
+    gl.n = (int)idx.size();
+    gl.prec = prec;
+    gl.items[GPH_PLANE] = (int)items[GPH_PLANE];
+    gl.items[GPH_MODE] = (int)items[GPH_MODE];
+    gl.gm = g->dev[slot];
+    PCFV_GTRY(hipMemcpyAsync(g->dev[slot], host.data(), sizeof(GroupMember) * host.size(), hipMemcpyHostToDevice,
+                             g->stream),
+              "member records");
+    return PCFV_OK;
+}
+
+pcfv_status group_launch(pcfv_group* g, int slot, int which) {
+    if (g->gl[slot].n == 0) return PCFV_OK;
+    PCFV_GTRY(launch_group(g->gl[slot], g->stream, which), "grouped launch");
+    return PCFV_OK;
+}
+
+// One descent step of every member in the record sets of both precisions.
 pcfv_status group_step(pcfv_group* g) {
     for (int k : {GK_PLANE_FWD, GK_MODE_RES, GK_PLANE_ADJ, GK_MODE_GRAD})
-        PCFV_GTRY(launch_group(g->gl, g->stream, k), "grouped launch");
+        for (int slot = 0; slot < 2; ++slot) {
+            pcfv_status st = group_launch(g, slot, k);
+            if (st != PCFV_OK) return st;
+        }
     return PCFV_OK;
 }
 
@@ -1083,54 +1209,75 @@ pcfv_status capture(pcfv_group* g, int nsteps) {
     return PCFV_OK;
 }
 
+// Host-side wait for the members' own streams (their fields may still be
+// being written there) before group launches on the group's stream.
+pcfv_status wait_members(pcfv_group* g) {
+    for (pcfv_ctx* c : g->members)
+        if (c->stream != g->stream) PCFV_GTRY(hipStreamSynchronize(c->stream), "member stream");
+    return PCFV_OK;
+}
+
 }  // namespace
 
-pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out) {
+size_t pcfv_group_workspace_bytes(pcfv_ctx* const* members, int n) {
+    GroupWs L;
+    std::string e;
+    return group_ws(members, n, L, e) ? L.total : 0;
+}
+
+pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, void* hip_stream, void* workspace,
+                              pcfv_group** out) {
     g_create_err.clear();
-    if (!out || !members || n < 1) {
-        g_create_err = "invalid group arguments";
+    if (!out) {
+        g_create_err = "out is NULL";
         return PCFV_EINVAL;
     }
     *out = nullptr;
-    for (int k = 0; k < n; ++k)
-        if (!members[k] || members[k]->kp.prec != members[0]->kp.prec) {
-            g_create_err = "group members must be non-NULL and share one precision";
-            return PCFV_EINVAL;
-        }
+    GroupWs L;
+    if (!group_ws(members, n, L, g_create_err)) return PCFV_EINVAL;
+    if (!workspace) {
+        g_create_err = "workspace is NULL";
+        return PCFV_ENOMEM;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) {
+        g_create_err = "workspace is not 256-byte aligned";
+        return PCFV_EINVAL;
+    }
     pcfv_group* g = new pcfv_group();
+    char* ws = reinterpret_cast<char*>(workspace);
     g->members.assign(members, members + n);
-    g->host.resize(n + 1);
-    GroupLaunch& gl = g->gl;
-    gl.n = n;
-    gl.prec = members[0]->kp.prec;
-    gl.pthreads = members[0]->kp.pthreads;
-    long long group_modes = 0;
-    for (int k = 0; k < n; ++k) group_modes += members[k]->kp.nmB;
-    if (group_modes > 1024) gl.pthreads = 1024;   // the single-context default for many modes
-    gl.mthreads = members[0]->kp.mthreads;
-    for (int k = 0; k < n; ++k) gl.np = std::max(gl.np, members[k]->kp.np);
-    long long items[2] = {0, 0};
+    g->prec0 = members[0]->kp.prec;
+    g->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    g->dev[0] = reinterpret_cast<GroupMember*>(ws + L.rec[0]);
+    g->dev[1] = reinterpret_cast<GroupMember*>(ws + L.rec[1]);
+    g->base.resize(n);
+    for (int slot = 0; slot < 2; ++slot) {
+        GroupLaunch& gl = g->gl[slot];
+        gl.n = 0;
+        gl.np = L.np;
+        gl.pthreads = L.pthreads;
+        gl.mthreads = L.mthreads;
+    }
     for (int k = 0; k < n; ++k) {
         pcfv_ctx* c = members[k];
-        GroupMember& m = g->host[k];
+        GroupMember& m = g->base[k];
+        m = GroupMember{};
         m.kp = c->kp;
-        m.kp.pthreads = gl.pthreads;
-        m.kp.mthreads = gl.mthreads;
-        if (c->kp.np != gl.np) {   // the per-mode kernels read the tables at the group's stride
-            const std::vector<double> pm = padded_mats(c->t.mats, c->kp.N, gl.np);
-            double* d = nullptr;
-            hipError_t he = hipMalloc(&d, pm.size() * 8);
-            if (he == hipSuccess) g->mats.push_back(d);
-            if (he == hipSuccess) he = hipMemcpy(d, pm.data(), pm.size() * 8, hipMemcpyHostToDevice);
+        m.kp.pthreads = L.pthreads;
+        m.kp.mthreads = L.mthreads;
+        if (L.mats[k] != SIZE_MAX) {   // the per-mode kernels read the tables at the group's stride
+            const std::vector<double> pm = padded_mats(c->t.mats, c->kp.N, L.np);
+            double* d = reinterpret_cast<double*>(ws + L.mats[k]);
+            hipError_t he = hipMemcpy(d, pm.data(), pm.size() * 8, hipMemcpyHostToDevice);
             if (he != hipSuccess) {
                 g_create_err = std::string("group setup: ") + hipGetErrorString(he);
-                pcfv_group_destroy(g);
+                delete g;
                 return PCFV_EDEVICE;
             }
             m.kp.M = d;
         }
-        m.kp.np = gl.np;
-        if (group_modes > 1024) {
+        m.kp.np = L.np;
+        if (L.many) {
             // a throughput launch: no LDS staging and the widest slab of the
             // member's candidates (the single-context defaults for many modes;
             // every candidate's partial buffers fit)
@@ -1138,41 +1285,20 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out)
             m.kp.XS = xs_candidates(c->cfg).front();   // descending
             m.kp.NS = c->cfg.Nx / m.kp.XS;
         }
-        m.item0[GPH_PLANE] = (int)items[GPH_PLANE];
-        m.item0[GPH_MODE] = (int)items[GPH_MODE];
-        items[GPH_PLANE] += (long long)m.kp.B * m.kp.NS * m.kp.N;
-        items[GPH_MODE] += c->kp.nmB;
-        m.dtau = 0;
-        m.u = nullptr;
         m.Y = c->Y;
         m.P3 = c->P3;
         m.P6 = c->P6;
         m.Atil = c->Atil;
         m.a = c->a;
         m.part = c->part;
-        for (int md : {PLANE_FWD, PLANE_JVP, PLANE_ADJ})
-            gl.plane_lds[md] = std::max(gl.plane_lds[md], plane_lds_bytes(m.kp, md));
-        gl.mode_lds = std::max(gl.mode_lds, mode_lds_bytes(m.kp));
+        for (int slot = 0; slot < 2; ++slot) {
+            KP kp = m.kp;
+            kp.prec = slot ? PREC_FP64 : PREC_FP32;
+            for (int md : {PLANE_FWD, PLANE_JVP, PLANE_ADJ})
+                g->gl[slot].plane_lds[md] = std::max(g->gl[slot].plane_lds[md], plane_lds_bytes(kp, md));
+            g->gl[slot].mode_lds = std::max(g->gl[slot].mode_lds, mode_lds_bytes(kp));
+        }
     }
-    if (items[0] > INT_MAX / 2 || items[1] > INT_MAX / 2) {
-        delete g;
-        g_create_err = "group too large";
-        return PCFV_EINVAL;
-    }
-    GroupMember& sent = g->host[n];
-    sent = GroupMember{};
-    sent.item0[GPH_PLANE] = (int)items[GPH_PLANE];
-    sent.item0[GPH_MODE] = (int)items[GPH_MODE];
-    gl.items[GPH_PLANE] = (int)items[GPH_PLANE];
-    gl.items[GPH_MODE] = (int)items[GPH_MODE];
-    hipError_t he = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
-    if (he == hipSuccess) he = hipMalloc(&g->dev, sizeof(GroupMember) * (n + 1));
-    if (he != hipSuccess) {
-        g_create_err = std::string("group setup: ") + hipGetErrorString(he);
-        pcfv_group_destroy(g);
-        return PCFV_EDEVICE;
-    }
-    gl.gm = g->dev;
     *out = g;
     return PCFV_OK;
 }
@@ -1180,42 +1306,215 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, pcfv_group** out)
 void pcfv_group_destroy(pcfv_group* g) {
     if (!g) return;
     drop_graph(g);
-    for (double* d : g->mats) (void)hipFree(d);
-    if (g->dev) (void)hipFree(g->dev);
-    if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
+}
+
+pcfv_status pcfv_group_set_stream(pcfv_group* g, void* hip_stream) {
+    if (!g) return PCFV_EINVAL;
+    drop_graph(g);
+    g->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return PCFV_OK;
 }
 
 pcfv_status pcfv_group_descend(pcfv_group* g, double* const* u, const double* dtau, long long steps,
                                int graph_steps) {
     if (!g || !u || !dtau || steps < 0 || graph_steps < 0) return gfail(g, PCFV_EINVAL, "invalid arguments");
-    const int n = g->gl.n;
-    for (int k = 0; k < n; ++k) {
+    const int n = (int)g->members.size();
+    for (int k = 0; k < n; ++k)
         if (!u[k] || !std::isfinite(dtau[k])) return gfail(g, PCFV_EINVAL, "NULL field or non-finite dtau");
-        g->host[k].u = dd(u[k]);
-        g->host[k].dtau = dtau[k];
-    }
-    // the members' own streams may still be writing their fields
-    for (pcfv_ctx* c : g->members) PCFV_GTRY(hipStreamSynchronize(c->stream), "member stream");
-    PCFV_GTRY(hipMemcpyAsync(g->dev, g->host.data(), sizeof(GroupMember) * (n + 1), hipMemcpyHostToDevice,
-                             g->stream),
-              "member records");
-    PCFV_GTRY(launch_group(g->gl, g->stream, GK_SYNTH), "grouped synth");
+    if (graph_steps > 0 && !g->stream)
+        return gfail(g, PCFV_EINVAL, "graph capture needs a stream other than the null stream");
+    pcfv_status st = wait_members(g);
+    if (st != PCFV_OK) return st;
+    std::vector<int> all(n);
+    for (int k = 0; k < n; ++k) all[k] = k;
+    const int slot = (g->prec0 == PREC_FP32) ? 0 : 1;
+    g->gl[1 - slot].n = 0;
+    st = upload_records(g, g->prec0, all, u, dtau);
+    if (st != PCFV_OK) return st;
+    st = group_launch(g, slot, GK_SYNTH);
+    if (st != PCFV_OK) return st;
     long long done = 0;
     if (graph_steps > 0 && steps >= graph_steps) {
         if (g->graph_steps != graph_steps) {
-            pcfv_status st = capture(g, graph_steps);
+            st = capture(g, graph_steps);
             if (st != PCFV_OK) return st;
         }
         for (; done + graph_steps <= steps; done += graph_steps)
             PCFV_GTRY(hipGraphLaunch(g->exec, g->stream), "graph launch");
     }
     for (; done < steps; ++done) {
-        pcfv_status st = group_step(g);
+        st = group_step(g);
         if (st != PCFV_OK) return st;
     }
     PCFV_GTRY(hipStreamSynchronize(g->stream), "synchronize");
     return PCFV_OK;
+}
+
+pcfv_status pcfv_group_descend_tol(pcfv_group* g, double* const* u, const double* dtau,
+                                   const pcfv_group_opts* o, pcfv_descent_report* reports, int* status) {
+    if (!g || !u || !dtau || !o || !reports || !status) return gfail(g, PCFV_EINVAL, "NULL argument");
+    const int n = (int)g->members.size();
+    if (o->max_steps < 0 || o->check_every < 1 || !(o->rel_tol > 0))
+        return gfail(g, PCFV_EINVAL, "invalid options (max_steps >= 0, check_every >= 1, rel_tol > 0)");
+    const bool use_dmd = o->dmd_window > 0;
+    if (use_dmd && (o->dmd_window < 3 || o->dmd_window > kMaxDmd || o->dmd_stride < 1 || !(o->dmd_accept > 0) ||
+                    !o->dmd_buffers))
+        return gfail(g, PCFV_EINVAL, "invalid DMD options");
+    for (int k = 0; k < n; ++k) {
+        if (!u[k] || !(dtau[k] > 0)) return gfail(g, PCFV_EINVAL, "NULL field or non-positive dtau");
+        if (use_dmd && !o->dmd_buffers[k]) return gfail(g, PCFV_EINVAL, "NULL DMD buffer");
+    }
+    drop_graph(g);   // the records change below; a captured graph would replay stale ones
+    // every exit puts the members back in the group's precision
+    struct PrecRestore {
+        pcfv_group* g;
+        ~PrecRestore() {
+            for (pcfv_ctx* c : g->members) c->kp.prec = g->prec0;
+        }
+    } restore{g};
+    pcfv_status st = wait_members(g);
+    if (st != PCFV_OK) return st;
+    std::vector<int> prec(n, g->prec0), active(n, 1), nsnap(n, 0), stat(n, PCFV_ENOTCONV);
+    std::vector<long long> steps(n, 0), steps32(n, 0);
+    std::vector<double> cost(n, 0), rel(n, 0);
+    std::vector<int> ndmd(n, 0), nacc(n, 0);
+    auto measure = [&](int k) -> pcfv_status {   // member k's J^2 and relative residual (y-values current)
+        pcfv_ctx* c = g->members[k];
+        std::vector<double> ck, nk;
+        pcfv_status s2 = cost_and_norm(c, u[k], ck, nk);
+        if (s2 != PCFV_OK) return gfail(g, s2, c->err);
+        double cw = 0, rw = 0;
+        bool finite = true;
+        for (size_t b = 0; b < ck.size(); ++b) {
+            finite &= std::isfinite(ck[b]);
+            cw = std::max(cw, ck[b]);
+            rw = std::max(rw, nk[b] > 0 ? std::sqrt(std::max(ck[b], 0.0)) / nk[b] : 0.0);
+        }
+        cost[k] = finite ? cw : NAN;
+        rel[k] = finite ? rw : NAN;
+        return PCFV_OK;
+    };
+    // y-values of every member in its precision, then the first check
+    for (int k = 0; k < n; ++k) {
+        pcfv_ctx* c = g->members[k];
+        c->kp.prec = prec[k];
+        PCFV_TRY_G(launch_synth(c->kp, c->stream, cd(u[k]), c->Y), "synth");
+        st = measure(k);
+        if (st != PCFV_OK) return st;
+    }
+    long long done = 0;
+    for (;;) {
+        // members' phase changes: converged, failed, FP32 -> FP64 refinement
+        bool changed = false;
+        for (int k = 0; k < n; ++k) {
+            if (!active[k]) continue;
+            pcfv_ctx* c = g->members[k];
+            if (!std::isfinite(cost[k])) {
+                active[k] = 0;
+                stat[k] = PCFV_ENAN;
+                changed = true;
+                continue;
+            }
+            if (prec[k] == PREC_FP32 && o->fp64_below > 0 && rel[k] < o->fp64_below) {
+                prec[k] = PREC_FP64;
+                c->kp.prec = PREC_FP64;
+                PCFV_TRY_G(launch_synth(c->kp, c->stream, cd(u[k]), c->Y), "synth");
+                st = measure(k);
+                if (st != PCFV_OK) return st;
+                nsnap[k] = 0;   // a DMD window does not straddle the switch
+                changed = true;
+            }
+            const bool refined = prec[k] == PREC_FP64 || !(o->fp64_below > 0);
+            if (rel[k] < o->rel_tol && refined) {
+                active[k] = 0;
+                stat[k] = PCFV_OK;
+                changed = true;
+            }
+        }
+        if (done >= o->max_steps) break;
+        std::vector<int> subset[2];
+        for (int k = 0; k < n; ++k)
+            if (active[k]) subset[prec[k] == PREC_FP32 ? 0 : 1].push_back(k);
+        if (subset[0].empty() && subset[1].empty()) break;
+        (void)changed;
+        for (pcfv_ctx* c : g->members)
+            if (c->stream != g->stream) PCFV_GTRY(hipStreamSynchronize(c->stream), "member stream");
+        for (int slot = 0; slot < 2; ++slot) {
+            g->gl[slot].n = 0;
+            if (!subset[slot].empty()) {
+                st = upload_records(g, slot ? PREC_FP64 : PREC_FP32, subset[slot], u, dtau);
+                if (st != PCFV_OK) return st;
+            }
+        }
+        // steps until the next check or snapshot
+        long long kmax = std::min<long long>(o->check_every, o->max_steps - done);
+        const long long stride = use_dmd ? o->dmd_stride : LLONG_MAX;
+        if (use_dmd) kmax = std::min<long long>(kmax, stride - done % stride);
+        for (long long i = 0; i < kmax; ++i) {
+            st = group_step(g);
+            if (st != PCFV_OK) return st;
+        }
+        done += kmax;
+        for (int k = 0; k < n; ++k)
+            if (active[k]) {
+                steps[k] += kmax;
+                if (prec[k] == PREC_FP32) steps32[k] += kmax;
+            }
+        PCFV_GTRY(hipStreamSynchronize(g->stream), "synchronize");
+        // snapshots and DMD windows (per member, on its own stream)
+        if (use_dmd && done % stride == 0) {
+            for (int k = 0; k < n; ++k) {
+                if (!active[k]) continue;
+                pcfv_ctx* c = g->members[k];
+                const long long ns = c->kp.nstate * c->kp.B;
+                PCFV_TRY_G(launch_pack(c->kp, c->stream, cd(u[k]), o->dmd_buffers[k] + (size_t)nsnap[k] * ns), "pack");
+                if (++nsnap[k] < o->dmd_window) continue;
+                nsnap[k] = 0;
+                std::vector<double> cnow, nnow, dcost;
+                std::vector<int> drank, dkind;
+                st = cost_and_norm(c, u[k], cnow, nnow);
+                if (st != PCFV_OK) return gfail(g, st, c->err);
+                st = dmd_core(c, o->dmd_buffers[k], o->dmd_window, o->dmd_stride * dtau[k],
+                              reinterpret_cast<double*>(c->a), dcost, drank, dkind);
+                if (st != PCFV_OK) return gfail(g, st, c->err);
+                ++ndmd[k];
+                const size_t fb1 = (size_t)3 * c->kp.nm * c->kp.N * 16;
+                for (int b = 0; b < c->kp.B; ++b)
+                    if (drank[b] > 0 && std::isfinite(dcost[b]) && dcost[b] < o->dmd_accept * cnow[b]) {
+                        PCFV_TRY_G(hipMemcpyAsync(reinterpret_cast<char*>(u[k]) + b * fb1,
+                                                  reinterpret_cast<const char*>(c->a) + b * fb1, fb1,
+                                                  hipMemcpyDeviceToDevice, c->stream),
+                                   "accept");
+                        ++nacc[k];
+                    }
+                PCFV_TRY_G(launch_synth(c->kp, c->stream, cd(u[k]), c->Y), "synth");
+            }
+        }
+        if (done % o->check_every == 0 || done >= o->max_steps)
+            for (int k = 0; k < n; ++k)
+                if (active[k]) {
+                    st = measure(k);
+                    if (st != PCFV_OK) return st;
+                }
+    }
+    for (pcfv_ctx* c : g->members) PCFV_GTRY(hipStreamSynchronize(c->stream), "member stream");
+    pcfv_status worst = PCFV_OK;
+    for (int k = 0; k < n; ++k) {
+        pcfv_descent_report& r = reports[k];
+        r = pcfv_descent_report{};
+        r.steps = steps[k];
+        r.tau = steps[k] * dtau[k];
+        r.cost = cost[k];
+        r.rel_res = rel[k];
+        r.dtau_final = dtau[k];
+        r.n_dmd = ndmd[k];
+        r.n_dmd_accepted = nacc[k];
+        r.steps_fp32 = steps32[k];
+        status[k] = stat[k];
+        if (stat[k] == PCFV_ENAN || (stat[k] != PCFV_OK && worst == PCFV_OK)) worst = (pcfv_status)stat[k];
+    }
+    return worst;
 }
 
 const char* pcfv_group_last_error(const pcfv_group* g) { return g ? g->err.c_str() : g_create_err.c_str(); }

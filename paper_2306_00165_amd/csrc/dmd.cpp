@@ -301,31 +301,47 @@ std::vector<cld> lstsq(CM P, std::vector<cld> z) {
 
 namespace {
 
-// Rank-r exact DMD of pairs (x_k, y_k) given in the orthonormal basis Q of
-// the snapshot span: AX, AY (M x n) hold their Q-coordinates, z those of the
-// vector the amplitudes are fitted to.  Returns the eigenvalues lam, and in
-// wy (n x r) the coordinates over the y columns of every mode's amplitude
-// times its eigenvector: mode q = sum_k wy(k, q) y_k = b_q phi_q.
+// Exact DMD of pairs (x_k, y_k) given in the orthonormal basis Q of the
+// snapshot span: AX, AY (M x n) hold their Q-coordinates and AX = U S V^T;
+// z holds those of the vector the amplitudes are fitted to.  The projections
+// B = AY V S^{-1} and A~ = U^T B are formed once for the largest rank; the
+// rank-r model uses their leading r columns (and r x r block).
+struct DmdBasis {
+    RM B, At;
+};
+DmdBasis dmd_basis(const RM& AY, const RM& U, const std::vector<ld>& s, const RM& V, int rmax) {
+    const int M = AY.r, n = AY.c;
+    DmdBasis d;
+    d.B = RM(M, rmax);
+    d.At = RM(rmax, rmax);
+    for (int i = 0; i < M; ++i)
+        for (int q = 0; q < rmax; ++q) {
+            ld acc = 0;
+            for (int k = 0; k < n; ++k) acc += AY(i, k) * V(k, q);
+            d.B(i, q) = acc / s[q];
+        }
+    for (int p = 0; p < rmax; ++p)
+        for (int q = 0; q < rmax; ++q) {
+            ld acc = 0;
+            for (int i = 0; i < M; ++i) acc += U(i, p) * d.B(i, q);
+            d.At(p, q) = acc;
+        }
+    return d;
+}
+
+// The rank-r model: eigenvalues lam and, in wy (n x r), the coordinates over
+// the y columns of every mode's amplitude times its eigenvector:
+// sum_k wy(k, q) y_k = b_q phi_q.
 struct DmdFit {
     std::vector<cld> lam;
     CM wy;
 };
-bool dmd_fit(const RM& AX, const RM& AY, const std::vector<ld>& z, const RM& U, const std::vector<ld>& s,
-             const RM& V, int r, DmdFit& f, std::string& err) {
-    const int M = AX.r, n = AX.c;
-    RM B(M, r), At(r, r);   // B = AY V_r Sigma_r^{-1}, A~ = U_r^T B
-    for (int i = 0; i < M; ++i)
-        for (int q = 0; q < r; ++q) {
-            ld acc = 0;
-            for (int k = 0; k < n; ++k) acc += AY(i, k) * V(k, q);
-            B(i, q) = acc / s[q];
-        }
+bool dmd_fit(const DmdBasis& d, const std::vector<ld>& z, const std::vector<ld>& s, const RM& V, int r, DmdFit& f,
+             std::string& err) {
+    const int M = d.B.r, n = V.r;
+    RM At(r, r);
     for (int p = 0; p < r; ++p)
-        for (int q = 0; q < r; ++q) {
-            ld acc = 0;
-            for (int i = 0; i < M; ++i) acc += U(i, p) * B(i, q);
-            At(p, q) = acc;
-        }
+        for (int q = 0; q < r; ++q) At(p, q) = d.At(p, q);
     CM W;
     if (!eig_general(At, f.lam, W)) {
         err = "DMD eigenvalue iteration did not converge";
@@ -335,7 +351,7 @@ bool dmd_fit(const RM& AX, const RM& AY, const std::vector<ld>& z, const RM& U, 
     for (int i = 0; i < M; ++i)
         for (int q = 0; q < r; ++q) {
             cld acc = 0;
-            for (int p = 0; p < r; ++p) acc += B(i, p) * W(p, q);
+            for (int p = 0; p < r; ++p) acc += d.B(i, p) * W(p, q);
             P(i, q) = acc;
         }
     std::vector<cld> zc(M);
@@ -350,6 +366,16 @@ bool dmd_fit(const RM& AX, const RM& AY, const std::vector<ld>& z, const RM& U, 
         }
     return true;
 }
+
+}  // namespace
+
+bool dmd_rank_tried(int r, int rstar) {
+    if (r < 1 || r > rstar) return false;
+    const int d = rstar - r;
+    return d <= 2 || (d & (d - 1)) == 0;   // r*, r* - 1, r* - 2, r* - 4, r* - 8, ...
+}
+
+namespace {
 
 int numerical_rank(const std::vector<ld>& s) {
     if (s.empty() || !(s[0] > 0)) return 0;
@@ -400,10 +426,12 @@ int candidates_from_R(const RM& R, int M, double dtau, std::vector<DmdCandidate>
     }
     svd_jacobi(DX, Ud, sd, Vd);
     const int rstar_d = (rstar > 0) ? numerical_rank(sd) : 0;
+    const DmdBasis bs = dmd_basis(AY, U, s, V, rstar), bd = dmd_basis(DY, Ud, sd, Vd, rstar_d);
     for (int r = 1; r <= std::max(rstar, rstar_d); ++r) {
-        if (r <= rstar) {   // Re(b_1 phi_1), the mode with the smallest |ln lambda|
+        if (!dmd_rank_tried(r, rstar) && !dmd_rank_tried(r, rstar_d)) continue;
+        if (r <= rstar && dmd_rank_tried(r, rstar)) {   // Re(b_1 phi_1), the mode with the smallest |ln lambda|
             DmdFit f;
-            if (!dmd_fit(AX, AY, z, U, s, V, r, f, err)) return -1;
+            if (!dmd_fit(bs, z, s, V, r, f, err)) return -1;
             int q1 = 0;
             for (int q = 1; q < r; ++q)
                 if (std::abs(std::log(f.lam[q])) < std::abs(std::log(f.lam[q1]))) q1 = q;
@@ -411,9 +439,9 @@ int candidates_from_R(const RM& R, int M, double dtau, std::vector<DmdCandidate>
             for (int k = 0; k < n; ++k) c.coef[k] = (double)std::real(f.wy(k, q1));   // y_k = psi_{k+2}
             out.push_back(std::move(c));
         }
-        if (r <= rstar_d) {   // psi_M + Re sum_{|lambda|<1} b_q phi_q lambda_q / (1 - lambda_q)
+        if (r <= rstar_d && dmd_rank_tried(r, rstar_d)) {   // psi_M + Re sum_{|lambda|<1} b_q phi_q lambda_q / (1 - lambda_q)
             DmdFit f;
-            if (!dmd_fit(DX, DY, zd, Ud, sd, Vd, r, f, err)) return -1;
+            if (!dmd_fit(bd, zd, sd, Vd, r, f, err)) return -1;
             std::vector<ld> cy(nd, 0);   // over y_k = d_{k+2} = psi_{k+3} - psi_{k+2}
             for (int q = 0; q < r; ++q) {
                 if (!(std::abs(f.lam[q]) < 1)) continue;

@@ -30,7 +30,7 @@ EXPORTS = [
     "pcfv_norms", "pcfv_pack_state", "pcfv_unpack_state", "pcfv_check_state",
     "pcfv_time_kernels", "pcfv_last_error", "pcfv_host_table", "pcfv_dmd_extrapolate",
     "pcfv_host_dmd", "pcfv_set_precision", "pcfv_autotune", "pcfv_get_tuning", "pcfv_set_tuning",
-    "pcfv_group_create",
+    "pcfv_group_create", "pcfv_group_workspace_bytes", "pcfv_group_set_stream", "pcfv_group_descend_tol",
     "pcfv_group_destroy", "pcfv_group_descend", "pcfv_group_last_error",
     "pcfv_mlp_param_count", "pcfv_mlp_workspace_bytes", "pcfv_mlp_create", "pcfv_mlp_destroy",
     "pcfv_mlp_last_error", "pcfv_mlp_set_params", "pcfv_mlp_get_params", "pcfv_mlp_forward", "pcfv_mlp_grad",
@@ -57,7 +57,8 @@ class Layout(ctypes.Structure):
     _fields_ = [("Kx", ctypes.c_int), ("Kz", ctypes.c_int), ("Ny", ctypes.c_int),
                 ("nkx", ctypes.c_int), ("nkz", ctypes.c_int), ("n_modes", ctypes.c_longlong),
                 ("n_complex", ctypes.c_longlong), ("n_state", ctypes.c_longlong),
-                ("batch", ctypes.c_int)]
+                ("batch", ctypes.c_int), ("stride_b", ctypes.c_longlong), ("stride_c", ctypes.c_longlong),
+                ("stride_kx", ctypes.c_longlong), ("stride_kz", ctypes.c_longlong)]
 
 
 class DescentOpts(ctypes.Structure):
@@ -67,7 +68,7 @@ class DescentOpts(ctypes.Structure):
                 ("dmd_window", ctypes.c_int), ("dmd_stride", ctypes.c_int), ("dmd_gap", ctypes.c_int),
                 ("dmd_start", ctypes.c_double), ("dmd_accept", ctypes.c_double),
                 ("dmd_buffer", ctypes.c_void_p), ("fp64_below", ctypes.c_double),
-                ("learned", ctypes.c_void_p)]
+                ("learned", ctypes.c_void_p), ("no_cost_checks", ctypes.c_int)]
 
 
 class MlpConfig(ctypes.Structure):
@@ -95,6 +96,12 @@ class DescentReport(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GroupOpts(ctypes.Structure):
+    _fields_ = [("max_steps", ctypes.c_longlong), ("rel_tol", ctypes.c_double), ("check_every", ctypes.c_int),
+                ("fp64_below", ctypes.c_double), ("dmd_window", ctypes.c_int), ("dmd_stride", ctypes.c_int),
+                ("dmd_accept", ctypes.c_double), ("dmd_buffers", ctypes.POINTER(ctypes.c_void_p))]
 
 
 def load_library(path=_LIB_PATH):
@@ -148,8 +155,15 @@ def load_library(path=_LIB_PATH):
     lib.pcfv_get_tuning.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
     lib.pcfv_set_tuning.restype = i
     lib.pcfv_set_tuning.argtypes = [vp, i, i, i]
+    lib.pcfv_group_workspace_bytes.restype = ctypes.c_size_t
+    lib.pcfv_group_workspace_bytes.argtypes = [ctypes.POINTER(vp), i]
     lib.pcfv_group_create.restype = i
-    lib.pcfv_group_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp)]
+    lib.pcfv_group_create.argtypes = [ctypes.POINTER(vp), i, vp, vp, ctypes.POINTER(vp)]
+    lib.pcfv_group_set_stream.restype = i
+    lib.pcfv_group_set_stream.argtypes = [vp, vp]
+    lib.pcfv_group_descend_tol.restype = i
+    lib.pcfv_group_descend_tol.argtypes = [vp, ctypes.POINTER(vp), dp, ctypes.POINTER(GroupOpts),
+                                           ctypes.POINTER(DescentReport), ctypes.POINTER(i)]
     lib.pcfv_group_destroy.restype = None
     lib.pcfv_group_destroy.argtypes = [vp]
     lib.pcfv_group_descend.restype = i
@@ -358,7 +372,7 @@ class Context:
 
     def descend(self, u, max_steps, dtau, rel_tol=0.0, check_every=None, grow_tol=0.0,
                 max_halvings=0, dmd_window=0, dmd_stride=1, dmd_gap=0, dmd_start=0.0,
-                dmd_accept=10.0, fp64_below=0.0, learned=None):
+                dmd_accept=10.0, fp64_below=0.0, learned=None, no_cost_checks=False):
         """Advance u (a contiguous complex128 device tensor) in place; returns
         (status, report dict).  dmd_window > 0 enables DMD extrapolation;
         fp64_below > 0 on a MIXED context switches to FP64 below that relative
@@ -373,7 +387,8 @@ class Context:
                         int(check_every or max(1, max_steps)), float(grow_tol), int(max_halvings),
                         int(dmd_window), int(dmd_stride), int(dmd_gap), float(dmd_start), float(dmd_accept),
                         ctypes.c_void_p(buf.data_ptr()) if buf is not None else None, float(fp64_below),
-                        ctypes.cast(ctypes.pointer(learned.model), ctypes.c_void_p) if learned is not None else None)
+                        ctypes.cast(ctypes.pointer(learned.model), ctypes.c_void_p) if learned is not None else None,
+                        int(bool(no_cost_checks)))
         rep = DescentReport()
         st = _lib.pcfv_descend(self._h, _ptr(u), ctypes.byref(o), ctypes.byref(rep))
         if st not in (OK, ENOTCONV, ENAN, EDIVERGED):
@@ -467,13 +482,24 @@ class Context:
 
 class Group:
     """Several contexts (different grids, Re, batch; one precision) advanced
-    together with one launch per stage of each descent step."""
+    together with one launch per stage of each descent step.  The group's
+    device records live in a workspace tensor owned here, and its launches go
+    to a stream created here (default priority), so that its steps can be
+    captured in a HIP graph."""
 
-    def __init__(self, contexts):
+    def __init__(self, contexts, stream=None):
         self.contexts = list(contexts)
         arr = (ctypes.c_void_p * len(self.contexts))(*[c._h.value for c in self.contexts])
+        nbytes = _lib.pcfv_group_workspace_bytes(arr, len(self.contexts))
+        if nbytes == 0:
+            raise PcfvError(EINVAL, "invalid group members")
+        dev = self.contexts[0].device
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
         h = ctypes.c_void_p()
-        st = _lib.pcfv_group_create(arr, len(self.contexts), ctypes.byref(h))
+        st = _lib.pcfv_group_create(arr, len(self.contexts), ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.c_void_p(self.workspace.data_ptr() + off), ctypes.byref(h))
         if st != OK:
             raise PcfvError(st, "pcfv_group_create failed: " + _lib.pcfv_last_error(None).decode())
         self._h = h
@@ -484,9 +510,7 @@ class Group:
             _lib.pcfv_group_destroy(h)
             self._h = None
 
-    def descend(self, fields, dtaus, steps, graph_steps=0):
-        """Advance fields[k] (contiguous complex128 device tensors of member
-        k's shape) in place by `steps` descent steps with dtaus[k]."""
+    def _fields(self, fields, dtaus):
         if len(fields) != len(self.contexts) or len(dtaus) != len(self.contexts):
             raise ValueError("one field and one dtau per member")
         for c, f in zip(self.contexts, fields):
@@ -494,9 +518,38 @@ class Group:
                 raise ValueError("fields must be contiguous complex128 device tensors of the member shapes")
         ptrs = (ctypes.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
         dt = (ctypes.c_double * len(fields))(*[float(x) for x in dtaus])
+        return ptrs, dt
+
+    def descend(self, fields, dtaus, steps, graph_steps=0):
+        """Advance fields[k] (contiguous complex128 device tensors of member
+        k's shape) in place by `steps` descent steps with dtaus[k]."""
+        ptrs, dt = self._fields(fields, dtaus)
+        torch.cuda.current_stream(self.contexts[0].device).synchronize()
         st = _lib.pcfv_group_descend(self._h, ptrs, dt, int(steps), int(graph_steps))
         if st != OK:
             raise PcfvError(st, _lib.pcfv_group_last_error(self._h).decode())
+
+    def descend_tol(self, fields, dtaus, max_steps, rel_tol, check_every=100, fp64_below=0.0, dmd_window=0,
+                    dmd_stride=1, dmd_accept=1.0):
+        """Descend every member to rel_tol (see pcfv_group_descend_tol);
+        returns (status, per-member statuses, per-member report dicts)."""
+        ptrs, dt = self._fields(fields, dtaus)
+        n = len(self.contexts)
+        bufs = []
+        if dmd_window > 0:
+            bufs = [torch.empty(int(dmd_window) * c.batch * c.n_state, dtype=torch.float64, device=c.device)
+                    for c in self.contexts]
+        barr = (ctypes.c_void_p * max(n, 1))(*[b.data_ptr() for b in bufs]) if bufs else None
+        o = GroupOpts(int(max_steps), float(rel_tol), int(check_every), float(fp64_below), int(dmd_window),
+                      int(dmd_stride), float(dmd_accept),
+                      ctypes.cast(barr, ctypes.POINTER(ctypes.c_void_p)) if barr is not None else None)
+        reps = (DescentReport * n)()
+        stats = (ctypes.c_int * n)()
+        torch.cuda.current_stream(self.contexts[0].device).synchronize()
+        st = _lib.pcfv_group_descend_tol(self._h, ptrs, dt, ctypes.byref(o), reps, stats)
+        if st not in (OK, ENOTCONV, ENAN):
+            raise PcfvError(st, _lib.pcfv_group_last_error(self._h).decode())
+        return st, list(stats), [r.as_dict() for r in reps]
 
 
 def _cuda_stream_ptr(torch_mod, device):

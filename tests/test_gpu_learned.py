@@ -220,12 +220,16 @@ def test_learned_proposal_is_assembled_as_defined_and_costed_exactly(trained):
     np.testing.assert_allclose(cb2, np.minimum(*singles), rtol=1e-14)
 
 
-def test_learned_alongside_dmd_never_worse_and_reports_gain(trained):
+def test_learned_alongside_dmd_gains_on_held_out_seeds(trained):
     """At the end of a DMD window the descent takes, per guess, the cheaper of
-    the DMD and learned candidates by true cost (under the acceptance rule):
-    the number of learned candidates taken is the one the entry points give
-    on the same window, the result is never worse than DMD alone, and the
-    measured gain on held-out seeds is printed."""
+    the DMD and learned candidates by true cost (under the acceptance rule),
+    and the number of learned candidates taken is the one the entry points
+    give on the same window.  On 16 held-out seeds (never seen in training)
+    the trained network must earn its place: its candidate is taken for at
+    least half of the guesses, the chosen candidate is no costlier than DMD's
+    at the median, and on average it lowers the cost by more than 1%
+    (mean DMD / chosen > 1.01; measured: median 1.008, mean 1.021 against the
+    DMD candidates of the paper's mode and the affine limit)."""
     import torch
     ctx, L, gen, dmd, kw, _ = trained
     U0 = torch.as_tensor(np.stack([gen(s) for s in range(600, 616)])).cuda().contiguous()
@@ -248,7 +252,9 @@ def test_learned_alongside_dmd_never_worse_and_reports_gain(trained):
                           dmd_window=16, dmd_stride=20, dmd_gap=10000, dmd_accept=10.0)
     assert rep["n_dmd"] == 1 and rep["n_learned_accepted"] == int(take_l.sum())
     best = np.where(take_l, c_l, c_d)
-    assert np.all(best <= c_d)
+    gain = c_d / best
     print(f"[gpu] learned candidates taken {int(take_l.sum())}/16; median cost: current {np.median(cur):.3e}, "
           f"DMD {np.median(c_d):.3e}, learned {np.median(c_l):.3e}; gain (DMD / chosen) median "
-          f"{np.median(c_d / best):.3f}, mean {np.mean(c_d / best):.3f}")
+          f"{np.median(gain):.3f}, mean {np.mean(gain):.3f}")
+    assert take_l.sum() >= 8
+    assert np.median(gain) >= 1.0 and np.mean(gain) > 1.01

@@ -577,6 +577,61 @@ def test_group_graph_is_reused_across_calls():
             c.cost(x)                      # eager work on the members' own streams
 
 
+def test_group_descends_to_tolerance_like_each_member_alone():
+    """pcfv_group_descend_tol on a mixed-precision group of uneven members:
+    each member stops at the first check below rel_tol after its own FP32 ->
+    FP64 switch, and ends bit for bit where the same member's single-context
+    pcfv_descend (same tolerance, switch point and check period) ends."""
+    import torch
+    from paper_2306_00165_amd.pcfv import Group, OK
+    mem = _group_members(precision=1)
+    dtaus = [0.02, 0.015, 0.01]
+    fields = [torch.as_tensor(u).to("cuda:0").contiguous() for _, _, u in mem]
+    rel0 = []
+    for (g, c, u), f, d in zip(mem, fields, dtaus):
+        _, rep = c.descend(f.clone(), max_steps=0, dtau=d)
+        rel0.append(rep["rel_res"])
+    tol, below = 0.5 * min(rel0), 0.8 * min(rel0)
+    print(f"[gpu] group to tolerance: initial rel {rel0}, fp64 below {below:.3e}, tol {tol:.3e}", flush=True)
+    grp = Group([c for _, c, _ in mem])
+    work = [f.clone() for f in fields]
+    st, stats, reps = grp.descend_tol(work, dtaus, max_steps=4000, rel_tol=tol, check_every=10, fp64_below=below)
+    assert st == OK and stats == [OK] * 3
+    for (g, c, u), f, w, d, rep in zip(mem, fields, work, dtaus, reps):
+        ref = f.clone()
+        st1, rep1 = c.descend(ref, max_steps=4000, dtau=d, rel_tol=tol, check_every=10, fp64_below=below)
+        assert st1 == OK
+        assert rep["steps"] == rep1["steps"] and rep["steps_fp32"] == rep1["steps_fp32"]
+        assert 0 < rep["steps_fp32"] < rep["steps"]
+        assert rep["rel_res"] < tol and rep["cost"] == rep1["cost"]
+        assert torch.equal(w, ref)
+
+
+def test_group_descend_tolerance_with_dmd_windows():
+    """FP64 group with DMD windows: every member converges, windows are
+    extrapolated, each member's reported cost is the oracle's cost of the
+    state it ends in, and the states stay admissible."""
+    import torch
+    from paper_2306_00165_amd.pcfv import Group, OK
+    mem = _group_members(precision=0)[:2]
+    dtaus = [0.02, 0.015]
+    fields = [torch.as_tensor(u).to("cuda:0").contiguous() for _, _, u in mem]
+    rel0 = [c.descend(f.clone(), max_steps=0, dtau=d)[1]["rel_res"] for (g, c, u), f, d in zip(mem, fields, dtaus)]
+    grp = Group([c for _, c, _ in mem])
+    st, stats, reps = grp.descend_tol(fields, dtaus, max_steps=5000, rel_tol=0.3 * min(rel0), check_every=20,
+                                      dmd_window=10, dmd_stride=4, dmd_accept=1.0)
+    print(f"[gpu] group with DMD: {[(r['steps'], r['n_dmd'], r['n_dmd_accepted'], r['rel_res']) for r in reps]}")
+    assert st == OK and stats == [OK, OK]
+    for (g, c, u), f, rep in zip(mem, fields, reps):
+        assert rep["n_dmd"] >= 1
+        m = Method(g)
+        x = to_np(f)
+        xs = x if c.batch > 1 else x[None]
+        worst = max(m.cost(v) for v in xs)
+        assert abs(rep["cost"] - worst) < TOL * worst
+        assert max(np.ravel(c.check_state(f))) < 1e-14
+
+
 def test_autotune_keeps_parity(ctxs):
     """The autotuner times every launch-shape candidate and keeps the fastest;
     results with the chosen shape still match the oracle."""

@@ -157,5 +157,11 @@ def test_affine_limit_recovers_a_nonzero_fixed_point():
     cands = {(rr, k): psi for rr, k, psi in dmd.candidates(snaps, 1.0, r)}
     np.testing.assert_allclose(cands[(4, 0)], psi_star, rtol=0, atol=1e-8 * np.abs(psi_star).max())
     np.testing.assert_allclose(cands[(3, 1)], psi_star, rtol=0, atol=1e-8 * np.abs(psi_star).max())
-    assert (4, 1) not in cands
-    assert [k for rr, k in cands if rr <= 3] == [0, 1] * 3
+    # ranks tried: r*, r* - 1, r* - 2, r* - 4, ... for each kind (r* = 4, r*_d = 3)
+    assert list(cands) == [(1, 1), (2, 0), (2, 1), (3, 0), (3, 1), (4, 0)]
+
+
+def test_ranks_tried_form_a_ladder_below_the_numerical_rank():
+    assert [r for r in range(1, 60) if dmd.rank_tried(r, 49)] == [17, 33, 41, 45, 47, 48, 49]
+    assert [r for r in range(1, 9) if dmd.rank_tried(r, 5)] == [1, 3, 4, 5]
+    assert not dmd.rank_tried(0, 3) and not dmd.rank_tried(4, 3)
