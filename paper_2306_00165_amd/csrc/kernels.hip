@@ -828,7 +828,11 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     const int nmB = p.nmB, mo = b * nm;                // y-value arrays are [f][j][b * nm + m]
     const int Kx = p.Kx;
     const int x0 = s * XS, tid = threadIdx.x;
-    const int per = XS * nkz, pz = XS * Nz, tzs = nkz + 1;
+    const int per = XS * nkz, tzs = nkz + 1;
+    // LDS rows are padded by one entry (x-slab rows of the spectral buffer xb
+    // to nkz + 1, of the products pb to Nz + 1): lanes at neighbouring x read
+    // rows that start in different banks instead of the same one
+    const int ldz = nkz + 1, pfs = XS * ldz, ldq = Nz + 1, pz = XS * ldq;
     // Twiddle tables: TX[xl][ikx] = exp(2 pi i kx x / Nx) for the slab's x and
     // every retained kx, TZ[z][kz] = exp(2 pi i kz z / Nz) with rows padded to
     // nkz + 1 entries, so that lanes running over kz (forward z transform) and
@@ -836,7 +840,7 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     CR* TX = sm;
     CR* TZ = TX + XS * nkx;
     CR* xb = TZ + Nz * tzs;
-    R* pb = reinterpret_cast<R*>(xb + NXF * per);
+    R* pb = reinterpret_cast<R*>(xb + NXF * pfs);
     // With p.stage the plane's y-values are staged in LDS with one coalesced
     // pass (they are read nkx times each by the inverse x transform); the
     // staging area is the products buffer, which is not live yet.  Staging
@@ -913,10 +917,11 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
                 aW = cmac(aW, Wp[(size_t)ikx * nkz], tw);
                 if constexpr (NG1 > 0) aT = cmac(aT, Ap[(size_t)ikx * nkz], tw);
             }
-            xb[(3 * g) * per + rem] = aV;
-            xb[(3 * g + 1) * per + rem] = imul(alpha, aK);
-            xb[(3 * g + 2) * per + rem] = aW;
-            if constexpr (NG1 > 0) xb[(3 * NG3 + g) * per + rem] = aT;
+            const int xo = xl * ldz + kz;
+            xb[(3 * g) * pfs + xo] = aV;
+            xb[(3 * g + 1) * pfs + xo] = imul(alpha, aK);
+            xb[(3 * g + 2) * pfs + xo] = aW;
+            if constexpr (NG1 > 0) xb[(3 * NG3 + g) * pfs + xo] = aT;
         }
     };
     if (stage)
@@ -941,7 +946,7 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     const int hz = pair ? Nz / 2 : Nz, npt = pair ? 2 : 1;
     for (int it = tid; it < XS * hz; it += PLANE_THREADS) {
         const int xl = it / hz, z = it - xl * hz;
-        const CR* c0 = xb + xl * nkz;   // field f at c0[f * per + kz]
+        const CR* c0 = xb + xl * ldz;   // field f at c0[f * pfs + kz]
         const CR* tz = TZ + z * tzs;
         R ve[NG3][4], vo[NG3][4], ae[NA], ao[NA];   // even- and odd-kz sums
 #pragma unroll
@@ -955,7 +960,7 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             const R kzr = (R)kz;
 #pragma unroll
             for (int g = 0; g < NG3; ++g) {
-                const CR cV = c0[(3 * g) * per + kz], cA = c0[(3 * g + 1) * per + kz], cW = c0[(3 * g + 2) * per + kz];
+                const CR cV = c0[(3 * g) * pfs + kz], cA = c0[(3 * g + 1) * pfs + kz], cW = c0[(3 * g + 2) * pfs + kz];
                 v[g][0] = fmar(-cV.y, tw.y, fmar(cV.x, tw.x, v[g][0]));
                 v[g][3] = fmar(kzr, fmar(cV.y, tw.x, cV.x * tw.y), v[g][3]);
                 v[g][1] = fmar(-cA.y, tw.y, fmar(cA.x, tw.x, v[g][1]));
@@ -963,7 +968,7 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             }
 #pragma unroll
             for (int i = 0; i < NG1; ++i) {
-                const CR cc = c0[(3 * NG3 + i) * per + kz];
+                const CR cc = c0[(3 * NG3 + i) * pfs + kz];
                 a[i] = fmar(-cc.y, tw.y, fmar(cc.x, tw.x, a[i]));
             }
         };
@@ -980,17 +985,17 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
         for (int h = 0; h < 2; ++h) {   // h = 0: point z, h = 1: point z + Nz/2
             if (h >= npt) break;
             const R sg = h ? (R)-1 : (R)1;
-            const int pt = xl * Nz + z + h * hz;
+            const int pt = xl * ldq + z + h * hz;
             R val[NG3][4], at[NA];
 #pragma unroll
             for (int g = 0; g < NG3; ++g) {
-                val[g][0] = c0[(3 * g) * per].x + two * (ve[g][0] + sg * vo[g][0]);
-                val[g][1] = c0[(3 * g + 1) * per].x + two * (ve[g][1] + sg * vo[g][1]);
-                val[g][2] = c0[(3 * g + 2) * per].x + two * (ve[g][2] + sg * vo[g][2]);
+                val[g][0] = c0[(3 * g) * pfs].x + two * (ve[g][0] + sg * vo[g][0]);
+                val[g][1] = c0[(3 * g + 1) * pfs].x + two * (ve[g][1] + sg * vo[g][1]);
+                val[g][2] = c0[(3 * g + 2) * pfs].x + two * (ve[g][2] + sg * vo[g][2]);
                 val[g][3] = -two * beta * (ve[g][3] + sg * vo[g][3]);
             }
 #pragma unroll
-            for (int i = 0; i < NG1; ++i) at[i] = c0[(3 * NG3 + i) * per].x + two * (ae[i] + sg * ao[i]);
+            for (int i = 0; i < NG1; ++i) at[i] = c0[(3 * NG3 + i) * pfs].x + two * (ae[i] + sg * ao[i]);
             val[0][0] += yj;   // base flow u_b = y e_x
             val[0][2] += (R)1; // d(u_b)_x / dy = 1
             if (MODE == PLANE_FWD) {
@@ -1028,20 +1033,20 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
         const int o = it / per, rem = it - o * per, xl = rem / nkz, kz = rem - xl * nkz;
         const CR* tzk = TZ + kz;   // tzk[z * tzs] = exp(2 pi i kz z / Nz)
         if (MODE != PLANE_ADJ) {
-            const R* q = pb + o * pz + xl * Nz;
+            const R* q = pb + o * pz + xl * ldq;
             R ar = 0, ai = 0;
             for (int z = 0; z < Nz; ++z) {
                 const CR tw = tzk[z * tzs];
                 ar += q[z] * tw.x;
                 ai -= q[z] * tw.y;
             }
-            xb[o * per + rem] = mkc(ar * invNz, ai * invNz);
+            xb[o * pfs + xl * ldz + kz] = mkc(ar * invNz, ai * invNz);
         } else {
             const int i = o;
-            const R* q1 = pb + (9 + i) * pz + xl * Nz;      // Q_i
-            const R* q2 = pb + (3 * i + 2) * pz + xl * Nz;  // P_{i,z}
-            const R* qx = pb + (3 * i) * pz + xl * Nz;      // P_{i,x}
-            const R* qy = pb + (3 * i + 1) * pz + xl * Nz;  // P_{i,y}
+            const R* q1 = pb + (9 + i) * pz + xl * ldq;      // Q_i
+            const R* q2 = pb + (3 * i + 2) * pz + xl * ldq;  // P_{i,z}
+            const R* qx = pb + (3 * i) * pz + xl * ldq;      // P_{i,x}
+            const R* qy = pb + (3 * i + 1) * pz + xl * ldq;  // P_{i,y}
             R ar = 0, ai = 0, br = 0, bi = 0, xr = 0, xi = 0, yr = 0, yi = 0;
             for (int z = 0; z < Nz; ++z) {
                 const CR tw = tzk[z * tzs];
@@ -1054,9 +1059,10 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
                 yr += qy[z] * tw.x;
                 yi -= qy[z] * tw.y;
             }
-            xb[(3 * i) * per + rem] = cscl(invNz, csub(mkc(ar, ai), imul(beta * (R)kz, mkc(br, bi))));  // Q_i - i b P_{i,z}
-            xb[(3 * i + 1) * per + rem] = mkc(xr * invNz, xi * invNz);
-            xb[(3 * i + 2) * per + rem] = mkc(yr * invNz, yi * invNz);
+            const int xo = xl * ldz + kz;
+            xb[(3 * i) * pfs + xo] = cscl(invNz, csub(mkc(ar, ai), imul(beta * (R)kz, mkc(br, bi))));  // Q_i - i b P_{i,z}
+            xb[(3 * i + 1) * pfs + xo] = mkc(xr * invNz, xi * invNz);
+            xb[(3 * i + 2) * pfs + xo] = mkc(yr * invNz, yi * invNz);
         }
     }
     __syncthreads();
@@ -1078,7 +1084,7 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             const CR tw = tx[xl * nkx];
 #pragma unroll
             for (int f = 0; f < NIN; ++f) {   // (ar, ai) += v conj(tw)
-                const CR v = xb[f * per + xl * nkz + kz];
+                const CR v = xb[f * pfs + xl * ldz + kz];
                 ar[f] = fmar(v.y, tw.y, fmar(v.x, tw.x, ar[f]));
                 ai[f] = fmar(-v.x, tw.y, fmar(v.y, tw.x, ai[f]));
             }
@@ -1713,10 +1719,10 @@ size_t plane_lds_bytes(const KP& p, int mode) {
     const int ng3 = (mode == PLANE_JVP) ? 6 : 3, ng1 = (mode == PLANE_ADJ) ? 3 : 0;
     const int npf = (mode == PLANE_ADJ) ? 12 : 3;
     const size_t nxf = 3 * ng3 + ng1, r = p.prec == PREC_FP32 ? 4 : 8;
-    const size_t products = (size_t)npf * p.XS * p.Nz * r;
+    const size_t products = (size_t)npf * p.XS * (p.Nz + 1) * r;
     const size_t staged = (mode == PLANE_JVP || !p.stage) ? 0 : (size_t)(2 * ng3 + ng1) * p.nm * 2 * r;   // aliases products
     const size_t twiddles = (size_t)p.XS * p.nkx + (size_t)p.Nz * (p.nkz + 1);
-    return twiddles * 2 * r + nxf * p.XS * p.nkz * 2 * r + std::max(products, staged);
+    return twiddles * 2 * r + nxf * p.XS * (p.nkz + 1) * 2 * r + std::max(products, staged);
 }
 
 size_t mode_lds_bytes(const KP& p) {
