@@ -230,6 +230,57 @@ def extra_legs(torch, inputs, steps):
     return out
 
 
+def dmd_schedule_leg(torch, inputs, steps=20000, every=500, window=50, dtau=0.02):
+    """The DMD schedule of Sec. 6.2 on the 32x33x32 streak + vortex seed
+    (E = 5e-3, seed 2, Re = 400, dtau = 0.02): FP64 descent for `steps`
+    steps with a DMD extrapolation every `every` steps from the last `window`
+    snapshots (every/window steps apart, the last one the current state),
+    taken when its true cost is below the current one; beside it the same
+    descent without extrapolation.  Returns the cost history of both runs
+    and every window's best candidate (rank, kind, cost)."""
+    from paper_2306_00165_amd.pcfv import Context
+    c = Context(32, 33, 32)
+    U0 = torch.as_tensor(inputs.config2_guess()).to("cuda:0").contiguous()
+    stride = every // window
+
+    def state(u):
+        _, rep = c.descend(u, max_steps=0, dtau=dtau)
+        return rep["cost"], rep["rel_res"]
+
+    u = U0.clone()
+    plain = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for blk in range(steps // every):
+        c.descend(u, max_steps=every, dtau=dtau, no_cost_checks=True)
+        J, rel = state(u)
+        plain.append({"steps": (blk + 1) * every, "cost": J, "rel_res": rel})
+    t_plain = time.perf_counter() - t0
+    u = U0.clone()
+    hist = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for blk in range(steps // every):
+        snaps = []
+        for _ in range(window):
+            c.descend(u, max_steps=stride, dtau=dtau, no_cost_checks=True)
+            snaps.append(c.pack(u))
+        J, rel = state(u)
+        u_s, Js, r, kind = c.dmd_extrapolate(torch.stack(snaps), stride * dtau, with_kind=True)
+        take = r > 0 and Js < J
+        if take:
+            u.copy_(u_s)
+        J2, rel2 = state(u)
+        hist.append({"steps": (blk + 1) * every, "cost_before": J, "rel_before": rel,
+                     "candidate_cost": Js if r > 0 else None, "rank": r, "kind": kind,
+                     "accepted": bool(take), "cost": J2, "rel_res": rel2})
+    t_dmd = time.perf_counter() - t0
+    return {"workload": "32x33x32 streak+vortex seed E=5e-3 seed 2, Re=400, dtau=0.02, FP64, "
+                        f"{steps} steps, DMD every {every} steps from the last {window} snapshots",
+            "plain": {"seconds": round(t_plain, 2), "history": plain},
+            "dmd": {"seconds": round(t_dmd, 2), "history": hist}}
+
+
 TOL_LADDER = [1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8, 1e-9, 1e-10]
 
 
@@ -344,6 +395,8 @@ def main():
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision and group legs")
+    ap.add_argument("--dmd-schedule", action="store_true",
+                    help="only run the 32x33x32 DMD schedule (cost history, plain vs DMD) and print it")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
@@ -355,6 +408,11 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         run_copy_calibration()
+        return
+    if args.dmd_schedule:
+        import torch
+        from paper_2306_00165_amd import inputs
+        print(json.dumps(dmd_schedule_leg(torch, inputs)))
         return
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
