@@ -88,7 +88,6 @@ KP base_kp(const pcfv_config& c) {
     // case: more work groups) and at most 16 otherwise (fewer slabs, less
     // partial traffic); the 1024-thread physical-space groups of both cases
     // waste the fewest partial passes over the slab's work items
-    p.stage = (p.nmB <= 1024) ? 1 : 0;   // LDS staging pays when occupancy is not the limit
     p.XS = 1;
     const int xs_max = (p.nmB <= 1024) ? 12 : 16;
     for (int xs = xs_max; xs >= 1; --xs) {
@@ -1278,10 +1277,9 @@ pcfv_status pcfv_group_create(pcfv_ctx* const* members, int n, void* hip_stream,
         }
         m.kp.np = L.np;
         if (L.many) {
-            // a throughput launch: no LDS staging and the widest slab of the
-            // member's candidates (the single-context defaults for many modes;
-            // every candidate's partial buffers fit)
-            m.kp.stage = 0;
+            // a throughput launch: the widest slab of the member's candidates
+            // (the single-context default for many modes; every candidate's
+            // partial buffers fit)
             m.kp.XS = xs_candidates(c->cfg).front();   // descending
             m.kp.NS = c->cfg.Nx / m.kp.XS;
         }

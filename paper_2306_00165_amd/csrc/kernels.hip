@@ -827,95 +827,96 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     const int N = p.N, Nx = p.Nx, Nz = p.Nz, nkx = p.nkx, nkz = p.nkz, nm = p.nm, XS = p.XS;
     const int nmB = p.nmB, mo = b * nm;                // y-value arrays are [f][j][b * nm + m]
     const int Kx = p.Kx;
-    const int x0 = s * XS, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int per = XS * nkz, tzs = nkz + 1;
     // LDS rows are padded by one entry (x-slab rows of the spectral buffer xb
     // to nkz + 1, of the products pb to Nz + 1): lanes at neighbouring x read
     // rows that start in different banks instead of the same one
     const int ldz = nkz + 1, pfs = XS * ldz, ldq = Nz + 1, pz = XS * ldq;
-    // Twiddle tables: TX[xl][ikx] = exp(2 pi i kx x / Nx) for the slab's x and
-    // every retained kx, TZ[z][kz] = exp(2 pi i kz z / Nz) with rows padded to
-    // nkz + 1 entries, so that lanes running over kz (forward z transform) and
-    // lanes running over z (inverse z transform) both read distinct LDS banks.
-    CR* TX = sm;
-    CR* TZ = TX + XS * nkx;
+    // The slab holds the points x = s + NS xl (xl < XS): since
+    //   exp(2 pi i kx x / Nx) = exp(2 pi i kx s / Nx) exp(2 pi i (kx mod XS) xl / XS),
+    // its x transforms split into a fold of the retained kx by kx mod XS (with
+    // the slab's phase) and an XS-point DFT.
+    // Twiddle tables: TS[ikx] = exp(2 pi i kx s / Nx) for every retained kx,
+    // TD[xl][q] = exp(2 pi i q xl / XS) (symmetric), TZ[z][kz] =
+    // exp(2 pi i kz z / Nz) with rows padded to nkz + 1 entries, so that lanes
+    // running over kz (forward z transform) and lanes running over z (inverse
+    // z transform) both read distinct LDS banks.
+    CR* TS = sm;
+    CR* TD = TS + nkx;
+    CR* TZ = TD + XS * XS;
     CR* xb = TZ + Nz * tzs;
     R* pb = reinterpret_cast<R*>(xb + NXF * pfs);
-    // With p.stage the plane's y-values are staged in LDS with one coalesced
-    // pass (they are read nkx times each by the inverse x transform); the
-    // staging area is the products buffer, which is not live yet.  Staging
-    // costs LDS (occupancy), so it is used for launches with few modes.  Staged
-    // fields: V and W of each velocity group (2 g, 2 g + 1), then the adjoint
-    // fields.  Setup pass q covers entry i = q * PLANE_THREADS + tid of both
-    // twiddle tables and mode i of every staged field; a thread issues all of
-    // a pass's global loads before it stores any of them.
-    const bool stage = (MODE != PLANE_JVP) && p.stage;
-    constexpr int NSF = 2 * NG3 + NG1;
-    CR* st = reinterpret_cast<CR*>(pb);
+    // The folded arrays (inverse x) and the XS-point DFTs (forward x) use the
+    // products buffer, which is not live at those times: array a at
+    // zb[a * pfs + q * ldz + kz].
+    CR* zb = reinterpret_cast<CR*>(pb);
     {
-        const int ntx = XS * nkx, ntz = Nz * nkz, nsm = stage ? nm : 0;
-        const int nset = max(max(ntx, ntz), nsm);
+        const int ntd = XS * XS, ntz = Nz * nkz;
+        const int nset = max(max(nkx, ntd), ntz);
 #pragma unroll 1
         for (int i = tid; i < nset; i += PLANE_THREADS) {
-            double2 vx = make_double2(0.0, 0.0), vz = make_double2(0.0, 0.0);
-            const int xl = i / nkx, ikx = i - xl * nkx, kx = (ikx <= Kx) ? ikx : ikx - nkx;
+            double2 vs = make_double2(0.0, 0.0), vd = vs, vz = vs;
+            const int kx = (i <= Kx) ? i : i - nkx;
+            const int xl = i / XS, q = i - xl * XS;
             const int z = i / nkz, kz = i - z * nkz;
-            if (i < ntx) vx = p.twx[(int)((long long)(kx + Nx) * (x0 + xl) % Nx)];
+            if (i < nkx) vs = p.twx[(kx + Nx) * s % Nx];
+            if (i < ntd) vd = p.twx[(q * xl) % XS * p.NS];
             if (i < ntz) vz = p.twz[(kz * z) % Nz];
-            R svx[NSF], svy[NSF];   // two real arrays: kept in registers
-            if (i < nsm) {
-#pragma unroll
-                for (int f = 0; f < NSF; ++f) {
-                    const CR* src = (f < 2 * NG3) ? Y1 : Y2;
-                    const int comp = (f < 2 * NG3) ? ((f & 1) ? 3 + (f >> 1) : (f >> 1)) : f - 2 * NG3;
-                    const CR v = src[((size_t)comp * N + j) * nmB + mo + i];
-                    svx[f] = v.x;
-                    svy[f] = v.y;
-                }
-            }
-            if (i < ntx) TX[i] = narrow<CR>(vx);
+            if (i < nkx) TS[i] = narrow<CR>(vs);
+            if (i < ntd) TD[i] = narrow<CR>(vd);
             if (i < ntz) TZ[z * tzs + kz] = narrow<CR>(vz);
-            if (i < nsm)
-#pragma unroll
-                for (int f = 0; f < NSF; ++f) st[f * nm + i] = mkc(svx[f], svy[f]);
         }
     }
     __syncthreads();
 
-    // inverse transform in x for the slab's x positions, all retained kz; the
-    // y-values come from LDS (staged) or straight from global memory, as two
-    // instantiations so that each pointer has one address space
-    // Work item (g, xl, kz): velocity group g and, in the adjoint variant, the
-    // adjoint field g too (NG1 == NG3 there), sharing the twiddles.
-    auto inverse_x = [&](auto staged) {
-        constexpr bool ST = decltype(staged)::value;
-        for (int it = tid; it < NG3 * per; it += PLANE_THREADS) {
-            const int g = it / per, rem = it - g * per, xl = rem / nkz, kz = rem - xl * nkz;
-            const CR* Vp;
-            const CR* Wp;
-            const CR* Ap = nullptr;
-            if constexpr (ST) {
-                Vp = st + (2 * g) * nm + kz;
-                Wp = st + (2 * g + 1) * nm + kz;
-                if constexpr (NG1 > 0) Ap = st + (2 * NG3 + g) * nm + kz;
-            } else {
-                const CR* src = (g < 3) ? Y1 : Y2;
-                const int comp = g % 3;
-                Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
-                Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
-                if constexpr (NG1 > 0) Ap = Y2 + ((size_t)g * N + j) * nmB + mo + kz;
-            }
-            // aV = sum V tw, aK = sum kx V tw (then aA = i alpha aK), aW, aT = sum W tw, A tw
-            CR aV = mkc(zero, zero), aK = mkc(zero, zero), aW = mkc(zero, zero), aT = mkc(zero, zero);
-            const CR* tx = TX + xl * nkx;
-            for (int ikx = 0; ikx < nkx; ++ikx) {
-                const R kx = (R)((ikx <= Kx) ? ikx : ikx - nkx);
-                const CR tw = tx[ikx];
+    // Inverse transform in x for the slab's points, all retained kz, in chunks
+    // of up to three velocity groups g (fields V, i a V, W; in the adjoint
+    // variant the adjoint field g too, NG1 == NG3 there).
+    //  fold: work item (g, q, kz) forms, over the retained kx = q (mod XS),
+    //        Z[q] = sum Y[kx] exp(2 pi i kx s / Nx) for V, kx V, W (and A);
+    //        every y-value of the plane is read once, from global memory;
+    //  DFT:  work item (g, xl, kz) forms sum_q Z[q] exp(2 pi i q xl / XS).
+    constexpr int NZA = NG1 > 0 ? 4 : 3;     // folded arrays per group
+    constexpr int GCH = NG3 < 3 ? NG3 : 3;   // groups per chunk
+    for (int g0 = 0; g0 < NG3; g0 += GCH) {
+        for (int it = tid; it < GCH * per; it += PLANE_THREADS) {
+            const int gc = it / per, rem = it - gc * per, q = rem / nkz, kz = rem - q * nkz;
+            const int g = g0 + gc;
+            const CR* src = (g < 3) ? Y1 : Y2;
+            const int comp = g % 3;
+            const CR* Vp = src + ((size_t)comp * N + j) * nmB + mo + kz;
+            const CR* Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
+            const CR* Ap = (NG1 > 0) ? Y2 + ((size_t)g * N + j) * nmB + mo + kz : nullptr;
+            CR zV = mkc(zero, zero), zK = zV, zW = zV, zA = zV;
+            for (int kx = -Kx + (q + Kx) % XS; kx <= Kx; kx += XS) {
+                const int ikx = (kx >= 0) ? kx : kx + nkx;
+                const CR tw = TS[ikx];
                 const CR vt = cmul(Vp[(size_t)ikx * nkz], tw);
-                aV = cadd(aV, vt);
-                aK = mkc(fmar(kx, vt.x, aK.x), fmar(kx, vt.y, aK.y));
-                aW = cmac(aW, Wp[(size_t)ikx * nkz], tw);
-                if constexpr (NG1 > 0) aT = cmac(aT, Ap[(size_t)ikx * nkz], tw);
+                zV = cadd(zV, vt);
+                zK = mkc(fmar((R)kx, vt.x, zK.x), fmar((R)kx, vt.y, zK.y));
+                zW = cmac(zW, Wp[(size_t)ikx * nkz], tw);
+                if constexpr (NG1 > 0) zA = cmac(zA, Ap[(size_t)ikx * nkz], tw);
+            }
+            CR* zo = zb + (size_t)(NZA * gc) * pfs + q * ldz + kz;
+            zo[0] = zV;
+            zo[pfs] = zK;
+            zo[2 * pfs] = zW;
+            if constexpr (NG1 > 0) zo[3 * pfs] = zA;
+        }
+        __syncthreads();
+        for (int it = tid; it < GCH * per; it += PLANE_THREADS) {
+            const int gc = it / per, rem = it - gc * per, xl = rem / nkz, kz = rem - xl * nkz;
+            const int g = g0 + gc;
+            const CR* zi = zb + (size_t)(NZA * gc) * pfs + kz;
+            const CR* td = TD + xl * XS;
+            CR aV = mkc(zero, zero), aK = aV, aW = aV, aT = aV;
+            for (int q = 0; q < XS; ++q) {
+                const CR tw = td[q];
+                aV = cmac(aV, zi[q * ldz], tw);
+                aK = cmac(aK, zi[pfs + q * ldz], tw);
+                aW = cmac(aW, zi[2 * pfs + q * ldz], tw);
+                if constexpr (NG1 > 0) aT = cmac(aT, zi[3 * pfs + q * ldz], tw);
             }
             const int xo = xl * ldz + kz;
             xb[(3 * g) * pfs + xo] = aV;
@@ -923,12 +924,8 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             xb[(3 * g + 2) * pfs + xo] = aW;
             if constexpr (NG1 > 0) xb[(3 * NG3 + g) * pfs + xo] = aT;
         }
-    };
-    if (stage)
-        inverse_x(std::true_type{});
-    else
-        inverse_x(std::false_type{});
-    __syncthreads();
+        __syncthreads();
+    }
 
     // inverse (complex-to-real) transform in z, then the products.  With Nz
     // even a work item takes the points z and z + Nz/2 of one x: their
@@ -1067,38 +1064,46 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     }
     __syncthreads();
 
-    // forward transform in x over this slab (partial sum), retained modes only;
-    // work item mm forms every output of mode mm, sharing the twiddles.  The
-    // adjoint outputs are X_i = F(A_i) - i a F(B_i) and Y_i = F(C_i) from the
-    // fields (A_i, B_i, C_i) = xb fields (3 i, 3 i + 1, 3 i + 2).
+    // Forward transform in x over this slab (partial sum), retained modes only.
+    //  DFT: work item (f, q, kz) forms F[f][q] = sum_xl v[f][xl] exp(-2 pi i q xl / XS);
+    //  per mode (kx, kz): F[f][kx mod XS] exp(-2 pi i kx s / Nx) / Nx.
+    // The adjoint outputs are X_i = F(A_i) - i a kx F(B_i) and Y_i = F(C_i) from
+    // the fields (A_i, B_i, C_i) = xb fields (3 i, 3 i + 1, 3 i + 2).
     constexpr int NOUT = (MODE == PLANE_ADJ) ? 6 : 3;
     constexpr int NIN = (MODE == PLANE_ADJ) ? 9 : 3;
+    for (int it = tid; it < NIN * per; it += PLANE_THREADS) {
+        const int f = it / per, rem = it - f * per, q = rem / nkz, kz = rem - q * nkz;
+        const CR* v = xb + f * pfs + kz;
+        const CR* td = TD + q * XS;
+        R ar = 0, ai = 0;
+        for (int xl = 0; xl < XS; ++xl) {   // (ar, ai) += v conj(tw)
+            const CR tw = td[xl], x = v[xl * ldz];
+            ar = fmar(x.y, tw.y, fmar(x.x, tw.x, ar));
+            ai = fmar(-x.x, tw.y, fmar(x.y, tw.x, ai));
+        }
+        zb[f * pfs + q * ldz + kz] = mkc(ar, ai);
+    }
+    __syncthreads();
     for (int mm = tid; mm < nm; mm += PLANE_THREADS) {
         const int ikx = mm / nkz, kz = mm - ikx * nkz;
         const int kx = (ikx <= Kx) ? ikx : ikx - nkx;
-        const CR* tx = TX + ikx;   // tx[xl * nkx] = exp(2 pi i kx (x0 + xl) / Nx)
-        R ar[NIN], ai[NIN];
-#pragma unroll
-        for (int f = 0; f < NIN; ++f) ar[f] = ai[f] = 0;
-        for (int xl = 0; xl < XS; ++xl) {
-            const CR tw = tx[xl * nkx];
-#pragma unroll
-            for (int f = 0; f < NIN; ++f) {   // (ar, ai) += v conj(tw)
-                const CR v = xb[f * pfs + xl * ldz + kz];
-                ar[f] = fmar(v.y, tw.y, fmar(v.x, tw.x, ar[f]));
-                ai[f] = fmar(-v.x, tw.y, fmar(v.y, tw.x, ai[f]));
-            }
-        }
+        const int q = ((kx % XS) + XS) % XS;
+        const CR ts = TS[ikx];
+        const CR* fi = zb + q * ldz + kz;   // F[f][q] at fi[f * pfs]
+        // (x + i y) conj(ts) / Nx
+        auto out1 = [&](CR v) {
+            return mkc(fmar(v.y, ts.y, v.x * ts.x) * invNx, fmar(-v.x, ts.y, v.y * ts.x) * invNx);
+        };
         CR* o0 = out + ((size_t)s * NOUT * N + j) * nmB + mo + mm;   // output o at o0[o * N * nmB]
         const size_t os = (size_t)N * nmB;
         if (MODE != PLANE_ADJ) {
 #pragma unroll
-            for (int o = 0; o < 3; ++o) o0[o * os] = mkc(ar[o] * invNx, ai[o] * invNx);
+            for (int o = 0; o < 3; ++o) o0[o * os] = out1(fi[o * pfs]);
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                o0[i * os] = cscl(invNx, csub(mkc(ar[3 * i], ai[3 * i]), imul(alpha * (R)kx, mkc(ar[3 * i + 1], ai[3 * i + 1]))));
-                o0[(3 + i) * os] = mkc(ar[3 * i + 2] * invNx, ai[3 * i + 2] * invNx);
+                o0[i * os] = out1(csub(fi[(3 * i) * pfs], imul(alpha * (R)kx, fi[(3 * i + 1) * pfs])));
+                o0[(3 + i) * os] = out1(fi[(3 * i + 2) * pfs]);
             }
         }
     }
@@ -1720,9 +1725,10 @@ size_t plane_lds_bytes(const KP& p, int mode) {
     const int npf = (mode == PLANE_ADJ) ? 12 : 3;
     const size_t nxf = 3 * ng3 + ng1, r = p.prec == PREC_FP32 ? 4 : 8;
     const size_t products = (size_t)npf * p.XS * (p.Nz + 1) * r;
-    const size_t staged = (mode == PLANE_JVP || !p.stage) ? 0 : (size_t)(2 * ng3 + ng1) * p.nm * 2 * r;   // aliases products
-    const size_t twiddles = (size_t)p.XS * p.nkx + (size_t)p.Nz * (p.nkz + 1);
-    return twiddles * 2 * r + nxf * p.XS * (p.nkz + 1) * 2 * r + std::max(products, staged);
+    const size_t row = (size_t)p.XS * (p.nkz + 1) * 2 * r;   // one x-slab array of nkz + 1 complex per x
+    const size_t folded = (size_t)(ng1 > 0 ? 12 : 9) * row;    // aliases products, as does the x DFT (<= 9 arrays)
+    const size_t twiddles = (size_t)p.nkx + (size_t)p.XS * p.XS + (size_t)p.Nz * (p.nkz + 1);
+    return twiddles * 2 * r + nxf * row + std::max(products, folded);
 }
 
 size_t mode_lds_bytes(const KP& p) {

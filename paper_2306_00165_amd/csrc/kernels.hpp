@@ -15,7 +15,6 @@ struct KP {
     int prec;                // PREC_FP64, or PREC_FP32 for the physical-space transforms and products
     int pthreads;            // threads per work group of the physical-space kernels (256, 512, 576, 768, 1024)
     int mthreads;            // threads per work group of the per-mode kernels (256 or 512)
-    int stage;               // physical-space kernels stage the plane's y-values in LDS (0/1)
     int np;                  // padded Ny of the per-mode kernels: stride of M and of their LDS vectors
     double lam, nu, alpha, beta;
     const double* M;         // M_COUNT fixed matrices, np x mat_ld(np) zero-padded slots, transposed
