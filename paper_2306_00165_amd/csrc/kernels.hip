@@ -841,18 +841,20 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     // TD[xl][q] = exp(2 pi i q xl / XS) (symmetric), TZ[z][kz] =
     // exp(2 pi i kz z / Nz) with rows padded to nkz + 1 entries, so that lanes
     // running over kz (forward z transform) and lanes running over z (inverse
-    // z transform) both read distinct LDS banks.
+    // z transform) both read distinct LDS banks.  With Nz even TZ holds the
+    // rows z < Nz/2 only: the twiddles of z + Nz/2 are (-1)^kz times those of z.
+    const int nzt = (Nz & 1) ? Nz : Nz / 2;
     CR* TS = sm;
     CR* TD = TS + nkx;
     CR* TZ = TD + XS * XS;
-    CR* xb = TZ + Nz * tzs;
+    CR* xb = TZ + nzt * tzs;
     R* pb = reinterpret_cast<R*>(xb + NXF * pfs);
     // The folded arrays (inverse x) and the XS-point DFTs (forward x) use the
     // products buffer, which is not live at those times: array a at
     // zb[a * pfs + q * ldz + kz].
     CR* zb = reinterpret_cast<CR*>(pb);
     {
-        const int ntd = XS * XS, ntz = Nz * nkz;
+        const int ntd = XS * XS, ntz = nzt * nkz;
         const int nset = max(max(nkx, ntd), ntz);
 #pragma unroll 1
         for (int i = tid; i < nset; i += PLANE_THREADS) {
@@ -944,7 +946,11 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     for (int it = tid; it < XS * hz; it += PLANE_THREADS) {
         const int xl = it / hz, z = it - xl * hz;
         const CR* c0 = xb + xl * ldz;   // field f at c0[f * pfs + kz]
-        const CR* tz = TZ + z * tzs;
+        // an unpaired point z >= Nz/2 (Nz even) reads row z - Nz/2 with the
+        // odd-kz twiddles negated
+        const bool up = z >= nzt;
+        const CR* tz = TZ + (up ? z - nzt : z) * tzs;
+        const R so = up ? (R)-1 : (R)1;
         R ve[NG3][4], vo[NG3][4], ae[NA], ao[NA];   // even- and odd-kz sums
 #pragma unroll
         for (int g = 0; g < NG3; ++g)
@@ -952,8 +958,8 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             for (int q = 0; q < 4; ++q) ve[g][q] = vo[g][q] = 0;
 #pragma unroll
         for (int i = 0; i < NA; ++i) ae[i] = ao[i] = 0;
-        auto term = [&](int kz, R (&v)[NG3][4], R (&a)[NA]) {
-            const CR tw = tz[kz];
+        auto term = [&](int kz, R (&v)[NG3][4], R (&a)[NA], R sgn) {
+            const CR t0 = tz[kz], tw = mkc(sgn * t0.x, sgn * t0.y);
             const R kzr = (R)kz;
 #pragma unroll
             for (int g = 0; g < NG3; ++g) {
@@ -970,12 +976,12 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             }
         };
         for (int kz = 1; kz < nkz; kz += 2) {
-            term(kz, vo, ao);
+            term(kz, vo, ao, so);
             if (kz + 1 < nkz) {
                 if constexpr (PAIRABLE)
-                    term(kz + 1, ve, ae);
+                    term(kz + 1, ve, ae, (R)1);
                 else
-                    term(kz + 1, vo, ao);   // one point per item: a single set of sums
+                    term(kz + 1, vo, ao, (R)1);   // one point per item: a single set of sums
             }
         }
 #pragma unroll
@@ -1024,18 +1030,22 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
 
     // forward transform in z (normalised), into xb.  Adjoint variant: work item
     // (i, xl, kz) forms the three outputs of component i, sharing the twiddles.
+    // With Nz even the sum runs over z < Nz/2 of q[z] + (-1)^kz q[z + Nz/2].
     const R invNz = (R)1 / (R)Nz, invNx = (R)1 / (R)Nx;
+    const int zo = (Nz & 1) ? 0 : Nz / 2;
     constexpr int NZI = (MODE == PLANE_ADJ) ? 3 : NZF;
     for (int it = tid; it < NZI * per; it += PLANE_THREADS) {
         const int o = it / per, rem = it - o * per, xl = rem / nkz, kz = rem - xl * nkz;
         const CR* tzk = TZ + kz;   // tzk[z * tzs] = exp(2 pi i kz z / Nz)
+        const R sk = zo ? ((kz & 1) ? (R)-1 : (R)1) : (R)0;   // q[z + zo] weight (zo = 0: q[z] alone)
         if (MODE != PLANE_ADJ) {
             const R* q = pb + o * pz + xl * ldq;
             R ar = 0, ai = 0;
-            for (int z = 0; z < Nz; ++z) {
+            for (int z = 0; z < nzt; ++z) {
                 const CR tw = tzk[z * tzs];
-                ar += q[z] * tw.x;
-                ai -= q[z] * tw.y;
+                const R v = fmar(sk, q[z + zo], q[z]);
+                ar = fmar(v, tw.x, ar);
+                ai = fmar(-v, tw.y, ai);
             }
             xb[o * pfs + xl * ldz + kz] = mkc(ar * invNz, ai * invNz);
         } else {
@@ -1045,16 +1055,18 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             const R* qx = pb + (3 * i) * pz + xl * ldq;      // P_{i,x}
             const R* qy = pb + (3 * i + 1) * pz + xl * ldq;  // P_{i,y}
             R ar = 0, ai = 0, br = 0, bi = 0, xr = 0, xi = 0, yr = 0, yi = 0;
-            for (int z = 0; z < Nz; ++z) {
+            for (int z = 0; z < nzt; ++z) {
                 const CR tw = tzk[z * tzs];
-                ar += q1[z] * tw.x;
-                ai -= q1[z] * tw.y;
-                br += q2[z] * tw.x;
-                bi -= q2[z] * tw.y;
-                xr += qx[z] * tw.x;
-                xi -= qx[z] * tw.y;
-                yr += qy[z] * tw.x;
-                yi -= qy[z] * tw.y;
+                const R v1 = fmar(sk, q1[z + zo], q1[z]), v2 = fmar(sk, q2[z + zo], q2[z]);
+                const R vx = fmar(sk, qx[z + zo], qx[z]), vy = fmar(sk, qy[z + zo], qy[z]);
+                ar = fmar(v1, tw.x, ar);
+                ai = fmar(-v1, tw.y, ai);
+                br = fmar(v2, tw.x, br);
+                bi = fmar(-v2, tw.y, bi);
+                xr = fmar(vx, tw.x, xr);
+                xi = fmar(-vx, tw.y, xi);
+                yr = fmar(vy, tw.x, yr);
+                yi = fmar(-vy, tw.y, yi);
             }
             const int xo = xl * ldz + kz;
             xb[(3 * i) * pfs + xo] = cscl(invNz, csub(mkc(ar, ai), imul(beta * (R)kz, mkc(br, bi))));  // Q_i - i b P_{i,z}
@@ -1727,7 +1739,8 @@ size_t plane_lds_bytes(const KP& p, int mode) {
     const size_t products = (size_t)npf * p.XS * (p.Nz + 1) * r;
     const size_t row = (size_t)p.XS * (p.nkz + 1) * 2 * r;   // one x-slab array of nkz + 1 complex per x
     const size_t folded = (size_t)(ng1 > 0 ? 12 : 9) * row;    // aliases products, as does the x DFT (<= 9 arrays)
-    const size_t twiddles = (size_t)p.nkx + (size_t)p.XS * p.XS + (size_t)p.Nz * (p.nkz + 1);
+    const size_t nzt = (p.Nz & 1) ? p.Nz : p.Nz / 2;   // rows of the z twiddle table
+    const size_t twiddles = (size_t)p.nkx + (size_t)p.XS * p.XS + nzt * (p.nkz + 1);
     return twiddles * 2 * r + nxf * row + std::max(products, folded);
 }
 
