@@ -395,6 +395,7 @@ def main():
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision and group legs")
+    ap.add_argument("--no-time-to-tol", action="store_true", help="skip the time-to-tolerance leg")
     ap.add_argument("--dmd-schedule", action="store_true",
                     help="only run the 32x33x32 DMD schedule (cost history, plain vs DMD) and print it")
     args = ap.parse_args()
@@ -451,7 +452,7 @@ def main():
                 "avg_launch_ms": round(ms[KERNELS.index(dom)], 5),
                 "hbm_GBps_algorithmic": round(nbytes / t_dom / 1e9, 2)}
     extra = {} if args.no_extra else extra_legs(torch, inputs, args.steps)
-    if not args.no_extra:
+    if not args.no_extra and not args.no_time_to_tol:
         extra["time_to_tol"] = time_to_tol_leg(torch, inputs)
     out = {
         "metric": METRIC, "value": round(steps_per_s, 2), "unit": "steps/s", "n_gpus": 1,
