@@ -302,6 +302,45 @@ def _trace(torch, c, U, dtau, seconds, chunk, check, **kw):
     return pts
 
 
+def _ladder_trace(torch, c, U, dtau, seconds, dmd_stride, **kw):
+    """Descend U with rel_tol set to each tolerance of the ladder in turn, one
+    call per tolerance (the call ends there, its DMD stride carried into the
+    next), for about `seconds`; returns [(t, steps, worst rel)] as _trace.
+    Each call's step budget is the time left times the step rate measured so
+    far (first from a short FP64 calibration run on a copy)."""
+    V = U.clone()
+    prec = c.cfg.precision
+    c.set_precision(0)
+    c.descend(V, max_steps=200, dtau=dtau, no_cost_checks=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c.descend(V, max_steps=2000, dtau=dtau, no_cost_checks=True)
+    torch.cuda.synchronize()
+    rate = 2000 / (time.perf_counter() - t1)
+    c.set_precision(prec)
+    del V
+    _, rep = c.descend(U, max_steps=0, dtau=dtau)
+    pts = [(0.0, 0, rep["rel_res"])]
+    torch.cuda.synchronize()
+    t0, steps, stride = time.perf_counter(), 0, dmd_stride
+    for tol in TOL_LADDER:
+        left = seconds - (time.perf_counter() - t0)
+        if left <= 0:
+            break
+        t1 = time.perf_counter()
+        st, rep = c.descend(U, max_steps=max(1, int(left * rate)), dtau=dtau, rel_tol=tol, dmd_stride=stride, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        steps += rep["steps"]
+        if rep["steps"] > 0 and dt > 0:
+            rate = rep["steps"] / dt
+        stride = rep["dmd_stride_final"] or stride
+        pts.append((time.perf_counter() - t0, steps, rep["rel_res"]))
+        if st != 0:
+            break
+    return pts
+
+
 def _first_time(pts, tol):
     for t, _, r in pts:
         if r < tol:
@@ -325,10 +364,13 @@ def time_to_tol_leg(torch, inputs, plain_s=20.0, chosen_s=40.0, late_s=10.0):
     seeds 100-103, dtau = 0.02) in one context.
       plain:  FP64 descent, no extrapolation;
       chosen: the same batch with FP32 transforms and products until every
-              guess is below 1e-3, then FP64, with DMD windows of 50 snapshots
-              200 steps apart (a candidate taken only if it lowers the cost;
-              extrapolating FP32 snapshots fits their rounding noise, so the
-              switch comes early).
+              guess is below 1e-3, then FP64, with DMD windows of 20 snapshots
+              (a candidate taken only if it lowers the cost; extrapolating FP32
+              snapshots fits their rounding noise, so the switch comes early),
+              200 steps apart at first, four times further apart after a window
+              that lowered some guess's cost by less than 10% (up to 6400): near
+              the attracting state the slow directions need longer windows.
+              One descent call per ladder tolerance (_ladder_trace).
     Times are measured as long as a form runs (plain_s, chosen_s seconds).
     Plain descent's time to a tolerance it did not reach is extrapolated and
     labelled so: down to 1e-5 at its own rate over its last third, below 1e-5
@@ -342,13 +384,14 @@ def time_to_tol_leg(torch, inputs, plain_s=20.0, chosen_s=40.0, late_s=10.0):
         .to("cuda:0").contiguous()
     out = {"workload": f"{B} streak+vortex guesses at 32x33x32 in one context, E=5e-3, seeds 100-{99 + B}, "
                        "Re=400, dtau=0.02; the worst guess decides",
-           "chosen": "batched + FP32 until 1e-3 then FP64 + DMD (window 50, stride 200, accept if cheaper)"}
+           "chosen": "batched + FP32 until 1e-3 then FP64 + DMD (window 20, stride 200 growing x4 up to 6400 "
+                     "after a window gaining < 10%, accept if cheaper)"}
     cp = Context(*dims, batch=B)
     plain = _trace(torch, cp, U0.clone(), dtau, plain_s, 4000, 2000)
     cc = Context(*dims, batch=B, precision=MIXED)
     Uc = U0.clone()
-    chosen = _trace(torch, cc, Uc, dtau, chosen_s, 20000, 2000, fp64_below=1e-3,
-                    dmd_window=50, dmd_stride=200, dmd_gap=0, dmd_accept=1.0)
+    chosen = _ladder_trace(torch, cc, Uc, dtau, chosen_s, 200, check_every=500, fp64_below=1e-3,
+                           dmd_window=20, dmd_gap=0, dmd_accept=1.0, dmd_stride_max=6400, dmd_grow_ratio=0.9)
     late = _trace(torch, cp, Uc.clone(), dtau, late_s, 4000, 2000)
     r_plain, r_late = _rate(plain), _rate(late)
     t_p_end, _, rel_p_end = plain[-1]

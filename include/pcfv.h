@@ -188,6 +188,16 @@ typedef struct {
      * synchronising; the report's cost and rel_res are then NaN.  (Every step
      * still forms its per-mode cost partials on the device.) */
     int no_cost_checks;
+    /* Adaptive DMD window (Sec. 6.2 leaves the snapshot spacing open): with
+     * dmd_stride_max > dmd_stride, a window after which some guess's best
+     * candidate costs at least dmd_grow_ratio times its current cost (or has
+     * no candidate) makes the next windows' stride four times longer, up to
+     * dmd_stride_max steps.  Near a fixed point the slowest directions must
+     * move the snapshots enough to be resolved; a longer window does that.
+     * dmd_grow_ratio <= 0 means 0.5.  dmd_stride_max <= dmd_stride: fixed
+     * stride. */
+    int dmd_stride_max;
+    double dmd_grow_ratio;
 } pcfv_descent_opts;
 
 typedef struct {
@@ -201,6 +211,7 @@ typedef struct {
     int n_dmd_accepted;   /* guesses restarted from an extrapolated state             */
     long long steps_fp32; /* steps taken with the FP32 physical-space stage           */
     int n_learned_accepted; /* restarts from a learned proposal (counted in n_dmd_accepted) */
+    int dmd_stride_final; /* snapshot stride of the last DMD window (pcfv_descend)     */
 } pcfv_descent_report;
 
 /* Advance every guess of u in place with the same dtau.  Returns PCFV_OK when
@@ -350,7 +361,8 @@ pcfv_status pcfv_group_descend(pcfv_group* group, double* const* u, const double
  * non-finite cost; the others go on.  With fp64_below > 0 a PCFV_MIXED
  * member switches to FP64 once below fp64_below (its y-values are rebuilt in
  * FP64; from then on its stages run in the FP64 launches).  dmd_window > 0:
- * every dmd_stride steps each active member's state vector goes into its
+ * every dmd_stride steps (fixed: the adaptive stride of pcfv_descend is not
+ * used here) each active member's state vector goes into its
  * window (dmd_buffers[k]: device, dmd_window * batch_k * n_state_k doubles,
  * caller-owned); a full window is extrapolated as pcfv_dmd_extrapolate does
  * and each guess whose best candidate costs less than dmd_accept times its

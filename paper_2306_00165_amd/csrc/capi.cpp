@@ -656,6 +656,10 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
     const size_t fbytes1 = (size_t)3 * p.nm * p.N * 16;
     double dtau = o->dtau, tau = 0;
     long long steps = 0, steps32 = 0;
+    // snapshot stride of the current DMD window (grows after weak windows)
+    long long stride = o->dmd_stride;
+    const bool adaptive = use_dmd && o->dmd_stride_max > o->dmd_stride;
+    const double grow_ratio = o->dmd_grow_ratio > 0 ? o->dmd_grow_ratio : 0.5;
     int halvings = 0, n_dmd = 0, n_acc = 0, n_lacc = 0;
     std::vector<double> cost, ntot, cost_prev;
     pcfv_descent_report local{};
@@ -678,6 +682,7 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
         rep->n_dmd_accepted = n_acc;
         rep->steps_fp32 = steps32;
         rep->n_learned_accepted = n_lacc;
+        rep->dmd_stride_final = use_dmd ? (int)stride : 0;
         return st;
     };
     // FP32 -> FP64 once every guess is below fp64_below: new y-values and cost
@@ -747,14 +752,14 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
         if (window && steps == next_snap) {
             PCFV_TRY(launch_pack(p, ctx->stream, cd(u), o->dmd_buffer + (size_t)nsnap * B * p.nstate), "pack");
             ++nsnap;
-            next_snap += o->dmd_stride;
+            next_snap += stride;
             if (nsnap == o->dmd_window) {
                 std::vector<double> cnow, nnow, dcost;
                 std::vector<int> drank, dkind;
                 s = cost_and_norm(ctx, u, cnow, nnow);
                 if (s != PCFV_OK) return s;
                 double2* cand = ctx->a;   // scratch: recomputed by every step
-                s = dmd_core(ctx, o->dmd_buffer, o->dmd_window, o->dmd_stride * dtau,
+                s = dmd_core(ctx, o->dmd_buffer, o->dmd_window, stride * dtau,
                              reinterpret_cast<double*>(cand), dcost, drank, dkind);
                 if (s != PCFV_OK) return s;
                 ++n_dmd;
@@ -772,11 +777,13 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
                                      base, reinterpret_cast<double*>(lcand), lcost);
                     if (s != PCFV_OK) return s;
                 }
+                bool weak = false;   // some guess gained less than grow_ratio
                 for (int b = 0; b < B; ++b) {
                     const bool dok = drank[b] > 0 && std::isfinite(dcost[b]);
                     const bool lok = o->learned && std::isfinite(lcost[b]);
                     const bool use_l = lok && (!dok || lcost[b] < dcost[b]);
                     const double best = use_l ? lcost[b] : (dok ? dcost[b] : HUGE_VAL);
+                    if (!(best < grow_ratio * cnow[b])) weak = true;
                     if (!(best < o->dmd_accept * cnow[b])) continue;
                     const double2* src = use_l ? lcand : cand;
                     PCFV_TRY(hipMemcpyAsync(reinterpret_cast<char*>(u) + b * fbytes1,
@@ -796,6 +803,7 @@ pcfv_status pcfv_descend(pcfv_ctx* ctx, double* u, const pcfv_descent_opts* o,
                 if (s != PCFV_OK) return s;
                 window = false;
                 window_start = steps + o->dmd_gap;
+                if (adaptive && weak) stride = std::min<long long>(4 * stride, o->dmd_stride_max);
                 since_check = 0;
                 if (converged()) return report(PCFV_OK);
                 continue;

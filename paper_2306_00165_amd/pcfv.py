@@ -68,7 +68,8 @@ class DescentOpts(ctypes.Structure):
                 ("dmd_window", ctypes.c_int), ("dmd_stride", ctypes.c_int), ("dmd_gap", ctypes.c_int),
                 ("dmd_start", ctypes.c_double), ("dmd_accept", ctypes.c_double),
                 ("dmd_buffer", ctypes.c_void_p), ("fp64_below", ctypes.c_double),
-                ("learned", ctypes.c_void_p), ("no_cost_checks", ctypes.c_int)]
+                ("learned", ctypes.c_void_p), ("no_cost_checks", ctypes.c_int),
+                ("dmd_stride_max", ctypes.c_int), ("dmd_grow_ratio", ctypes.c_double)]
 
 
 class MlpConfig(ctypes.Structure):
@@ -92,7 +93,8 @@ class DescentReport(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_longlong), ("tau", ctypes.c_double), ("cost", ctypes.c_double),
                 ("rel_res", ctypes.c_double), ("dtau_final", ctypes.c_double),
                 ("n_halvings", ctypes.c_int), ("n_dmd", ctypes.c_int), ("n_dmd_accepted", ctypes.c_int),
-                ("steps_fp32", ctypes.c_longlong), ("n_learned_accepted", ctypes.c_int)]
+                ("steps_fp32", ctypes.c_longlong), ("n_learned_accepted", ctypes.c_int),
+                ("dmd_stride_final", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -372,11 +374,13 @@ class Context:
 
     def descend(self, u, max_steps, dtau, rel_tol=0.0, check_every=None, grow_tol=0.0,
                 max_halvings=0, dmd_window=0, dmd_stride=1, dmd_gap=0, dmd_start=0.0,
-                dmd_accept=10.0, fp64_below=0.0, learned=None, no_cost_checks=False):
+                dmd_accept=10.0, fp64_below=0.0, learned=None, no_cost_checks=False, dmd_stride_max=0,
+                dmd_grow_ratio=0.0):
         """Advance u (a contiguous complex128 device tensor) in place; returns
-        (status, report dict).  dmd_window > 0 enables DMD extrapolation;
-        fp64_below > 0 on a MIXED context switches to FP64 below that relative
-        residual."""
+        (status, report dict).  dmd_window > 0 enables DMD extrapolation (with
+        dmd_stride_max > dmd_stride the stride grows fourfold after a window
+        that gained less than dmd_grow_ratio); fp64_below > 0 on a MIXED
+        context switches to FP64 below that relative residual."""
         if not (u.is_contiguous() and u.dtype == self.torch.complex128 and tuple(u.shape) == self.shape):
             raise ValueError("u must be a contiguous complex128 device tensor of the context shape")
         buf = None
@@ -388,7 +392,7 @@ class Context:
                         int(dmd_window), int(dmd_stride), int(dmd_gap), float(dmd_start), float(dmd_accept),
                         ctypes.c_void_p(buf.data_ptr()) if buf is not None else None, float(fp64_below),
                         ctypes.cast(ctypes.pointer(learned.model), ctypes.c_void_p) if learned is not None else None,
-                        int(bool(no_cost_checks)))
+                        int(bool(no_cost_checks)), int(dmd_stride_max), float(dmd_grow_ratio))
         rep = DescentReport()
         st = _lib.pcfv_descend(self._h, _ptr(u), ctypes.byref(o), ctypes.byref(rep))
         if st not in (OK, ENOTCONV, ENAN, EDIVERGED):

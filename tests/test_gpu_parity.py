@@ -404,6 +404,43 @@ def test_descend_with_dmd_equals_composed_entry_points(ctxs):
     assert rel(to_np(u), u_ref) < tol
 
 
+@pytest.mark.parametrize("ratio,strides", [(1e-12, [2, 8, 32]), (1e12, [2, 2, 2])])
+def test_descend_adaptive_dmd_stride_equals_composed_entry_points(ctxs, ratio, strides):
+    """With dmd_stride_max > dmd_stride, a window whose best candidate costs
+    at least dmd_grow_ratio times the current cost makes the next stride four
+    times longer (capped): ratio 1e-12 grows after every window (2 -> 8 -> 32,
+    cap 32), ratio 1e12 never.  The same schedule composed from entry points
+    (pack, descend, dmd_extrapolate, cost) gives the same state."""
+    import torch
+    g, m, c = ctxs("cfg1")
+    W, dtau, accept = 6, 0.02, 10.0
+    u = torch.as_tensor(inputs.config1_guess()).to("cuda:0").contiguous()
+    c.descend(u, max_steps=40, dtau=dtau)
+    v = u.clone()
+    total, after = sum((W - 1) * s for s in strides), 3
+    st, rep = c.descend(u, max_steps=total + after, dtau=dtau, dmd_window=W, dmd_stride=strides[0], dmd_gap=0,
+                        dmd_accept=accept, dmd_stride_max=32, dmd_grow_ratio=ratio)
+    assert rep["n_dmd"] == len(strides)
+    expect_final = min(4 * strides[-1], 32) if ratio < 1 else strides[-1]
+    assert rep["dmd_stride_final"] == expect_final
+    taken = 0
+    for s in strides:
+        snaps = [to_np(c.pack(v))]
+        for k in range(W - 1):
+            c.descend(v, max_steps=s, dtau=dtau)
+            snaps.append(to_np(c.pack(v)))
+        u_s, cost_s, r_s = c.dmd_extrapolate(np.stack(snaps)[:, None, :], s * dtau)
+        cnow = c.cost(v)
+        if r_s > 0 and cost_s < accept * cnow:
+            v.copy_(u_s)
+            taken += 1
+    c.descend(v, max_steps=after, dtau=dtau)
+    assert rep["n_dmd_accepted"] == taken
+    print(f"[gpu] adaptive DMD stride ratio {ratio:g}: strides {strides} -> final {rep['dmd_stride_final']}, "
+          f"state rel diff {rel(to_np(u), to_np(v)):.2e}", flush=True)
+    assert rel(to_np(u), to_np(v)) < 1e-15
+
+
 # -- mixed precision: FP32 transforms and products, FP64 solves --------------------
 
 # The FP32 stage rounds each y-value once and accumulates sums of at most
