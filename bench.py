@@ -225,6 +225,15 @@ def extra_legs(torch, inputs, steps):
         dt = time.perf_counter() - t0
         wide[name] = round(8 * k / dt, 1)
         wide[name + "_algorithmic_GBps"] = round(step_bytes * k / dt / 1e9, 1)
+        if prec == 0:
+            # in-step kernel times (HIP events) and the dominant kernel against the FP64 peak
+            ms = dict(zip(KERNELS[1:], c.time_descent_kernels(U, 0.01, nsteps=20)))
+            dom = max(ms, key=ms.get)
+            flops = 8 * model[dom][0]
+            wide["f64_kernel_ms"] = {k: round(v, 4) for k, v in ms.items()}
+            wide["f64_roofline"] = {"kernel": dom, "achieved": round(flops / (ms[dom] * 1e-3) / 1e12, 3),
+                                    "peak": PEAK_FP64, "unit": "TFLOP/s",
+                                    "frac": round(flops / (ms[dom] * 1e-3) / 1e12 / PEAK_FP64, 4)}
         del c, U
     out["wide96"] = wide
     return out
