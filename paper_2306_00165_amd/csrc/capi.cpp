@@ -70,6 +70,12 @@ bool validate(const pcfv_config* c, std::string& e) {
     return true;
 }
 
+// Default physical-space work-group size for a launch of nmB modes (see base_kp).
+static int plane_threads_default(int prec, long long nmB) {
+    if (nmB <= 1024) return prec == PREC_FP64 ? 576 : 1024;
+    return prec == PREC_FP32 ? 512 : 1024;
+}
+
 KP base_kp(const pcfv_config& c) {
     KP p{};
     p.N = c.Ny;
@@ -98,10 +104,11 @@ KP base_kp(const pcfv_config& c) {
     }
     p.NS = c.Nx / p.XS;
     p.prec = c.precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
-    // 1024-thread physical-space groups, except FP64 launches with few modes:
-    // there 576 threads (9 waves) leave the registers for the inverse z
-    // transform to take two points per work item
-    p.pthreads = (p.prec == PREC_FP64 && p.nmB <= 1024) ? 576 : 1024;
+    // 1024-thread physical-space groups, except FP64 launches with few modes,
+    // where 576 threads (9 waves) leave the registers for the inverse z
+    // transform to take two points per work item, and FP32 launches with many
+    // modes, where 512-thread groups (more of them resident per CU) are faster
+    p.pthreads = plane_threads_default(p.prec, p.nmB);
     // per-mode groups of 256 threads (4 lanes per contraction row): their
     // contractions have no idle waves for Ny up to 64 and several groups share a CU
     p.mthreads = 256;
@@ -1124,7 +1131,8 @@ bool group_ws(pcfv_ctx* const* m, int n, GroupWs& L, std::string& e) {
         L.np = std::max(L.np, m[k]->kp.np);
     }
     L.many = group_modes > 1024;
-    L.pthreads = L.many ? 1024 : m[0]->kp.pthreads;   // the single-context default for many modes
+    L.pthreads = L.many ? plane_threads_default(m[0]->kp.prec, group_modes)   // the single-context default
+                        : m[0]->kp.pthreads;                                   // for many modes
     L.mthreads = m[0]->kp.mthreads;
     size_t o = 0;
     for (int p = 0; p < 2; ++p) {
