@@ -149,6 +149,51 @@ def run_cpu_baseline_only(seconds, threads):
                                 f"NumPy/SciPy FP64, BLAS and FFT threads = {threads}"}))
 
 
+ORACLE_GRIDS = [("16x25x16", (16, 25, 16), {}), ("32x33x32", (32, 33, 32), {}), ("48x49x48", (48, 49, 48), {}),
+                ("96x65x96 wide", (96, 65, 96), {"Lx": 12.566370614359172, "Lz": 6.283185307179586})]
+
+
+def run_oracle_operators(threads, seconds=3.0):
+    """The oracle's residual, J* w, projection and descent step at each grid,
+    seconds per operator at most after one untimed call (setup)."""
+    from oracle import Grid
+    from oracle.method import Method
+    from paper_2306_00165_amd import inputs
+    rows = []
+    for name, dims, box in ORACLE_GRIDS:
+        g = Grid(*dims, **box)
+        t0 = time.perf_counter()
+        m = Method(g)
+        u = inputs.random_field(*dims, g.Lx, g.Lz, energy=1e-3, seed=5)
+        w = inputs.random_field(*dims, g.Lx, g.Lz, energy=1e-3, seed=6)
+        ops = {"residual": lambda: m.residual(u), "adjoint": lambda: m.adjoint(u, w),
+               "project": lambda: m.project(w), "descent_step": lambda: m.descent_step(u, 0.01)}
+        row = {"grid": name, "setup_s": None}
+        for k, f in ops.items():
+            f()   # untimed: builds the per-mode factorisations / projector on first use
+            n, t1 = 0, time.perf_counter()
+            while n < 1 or (time.perf_counter() - t1 < seconds and n < 50):
+                f()
+                n += 1
+            row[k + "_ms"] = round(1e3 * (time.perf_counter() - t1) / n, 2)
+        row["setup_s"] = round(time.perf_counter() - t0, 1)
+        rows.append(row)
+    print(json.dumps({"threads": threads, "rows": rows}))
+
+
+def oracle_operator_table():
+    """run_oracle_operators in child processes with 1 and the host's threads."""
+    out = {"cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+    for threads in sorted({1, _host_threads()}):
+        n = str(threads)
+        env = dict(os.environ, OMP_NUM_THREADS=n, OPENBLAS_NUM_THREADS=n, MKL_NUM_THREADS=n)
+        res = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-operators-child",
+                              "--cpu-threads", n], env=env, capture_output=True, text=True)
+        out[f"threads_{threads}"] = (json.loads(res.stdout.strip().splitlines()[-1]) if res.returncode == 0
+                                     else {"failed": res.stderr[-300:]})
+    print(json.dumps(out))
+
+
 def run_copy_calibration():
     """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
     import torch
@@ -448,12 +493,21 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision and group legs")
     ap.add_argument("--no-time-to-tol", action="store_true", help="skip the time-to-tolerance leg")
+    ap.add_argument("--oracle-operators", action="store_true",
+                    help="only time the CPU oracle's operators at every grid (1 and all host threads)")
+    ap.add_argument("--oracle-operators-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--dmd-schedule", action="store_true",
                     help="only run the 32x33x32 DMD schedule (cost history, plain vs DMD) and print it")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
         run_cpu_baseline_only(args.cpu_seconds, args.cpu_threads)
+        return
+    if args.oracle_operators_child:
+        run_oracle_operators(args.cpu_threads)
+        return
+    if args.oracle_operators:
+        oracle_operator_table()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the descent "
