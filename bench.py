@@ -335,6 +335,48 @@ def dmd_schedule_leg(torch, inputs, steps=20000, every=500, window=50, dtau=0.02
             "dmd": {"seconds": round(t_dmd, 2), "history": hist}}
 
 
+def group_tol_leg(torch, inputs, seconds=60.0):
+    """64 guesses on uneven grids (32 at 32x33x32, 32 at 48x49x48, Re ~
+    U[350, 450], k^-5/3 spectrum, E ~ U[0.01, 0.05], seeds 100-163) in one
+    mixed-precision group, each descending toward ||r||/||u_b+u|| < 1e-10:
+    FP32 physical-space stage until the member is below 1e-5, then FP64, DMD
+    windows of 20 snapshots 200 steps apart (taken when cheaper), for about
+    `seconds` of wall time.  Reports where the members are at the end."""
+    import numpy as np
+    from paper_2306_00165_amd.pcfv import Context, Group, MIXED
+    rng = np.random.default_rng(0)
+    ctxs, fields, dts = [], [], []
+    for i in range(64):
+        dims = (32, 33, 32) if i < 32 else GRID
+        ctxs.append(Context(*dims, Re=float(rng.uniform(350, 450)), precision=MIXED))
+        fields.append(torch.as_tensor(inputs.kolmogorov_guess(*dims, float(rng.uniform(0.01, 0.05)), 100 + i))
+                      .to("cuda:0").contiguous())
+        dts.append(0.02 if i < 32 else DTAU)
+    grp = Group(ctxs)
+    t0 = time.perf_counter()
+    grp.descend(fields, dts, 200)
+    torch.cuda.synchronize()
+    rate = 200 / (time.perf_counter() - t0)          # group steps per second
+    t0 = time.perf_counter()
+    st, stats, reps = grp.descend_tol(fields, dts, max_steps=int(seconds * rate * 0.9), rel_tol=1e-10,
+                                      check_every=500, fp64_below=1e-5, dmd_window=20, dmd_stride=200,
+                                      dmd_accept=1.0)
+    wall = time.perf_counter() - t0
+    rel = np.array([r["rel_res"] for r in reps])
+    fp64 = sum(1 for r in reps if r["steps"] > r["steps_fp32"])
+    out = {"workload": "64 guesses: 32 at 32x33x32 + 32 at 48x49x48, Re ~ U[350,450], k^-5/3, E ~ U[0.01,0.05], "
+                       "mixed precision with the FP64 switch at 1e-5, DMD windows 20 x 200 steps, target 1e-10",
+           "seconds": round(wall, 1), "group_steps": int(max(r["steps"] for r in reps)),
+           "members_in_fp64": fp64, "members_converged": int(sum(1 for x in stats if x == 0)),
+           "dmd_windows": int(sum(r["n_dmd"] for r in reps)), "dmd_taken": int(sum(r["n_dmd_accepted"] for r in reps))}
+    for tol in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        out[f"below_{tol:g}"] = int((rel < tol).sum())
+    out["rel_quantiles"] = {q: float(np.quantile(rel, q)) for q in (0.0, 0.25, 0.5, 0.75, 1.0)}
+    for name, sel in (("32x33x32", slice(0, 32)), ("48x49x48", slice(32, 64))):
+        out[f"rel_median_{name}"] = float(np.median(rel[sel]))
+    return out
+
+
 TOL_LADDER = [1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8, 1e-9, 1e-10]
 
 
@@ -496,6 +538,8 @@ def main():
     ap.add_argument("--oracle-operators", action="store_true",
                     help="only time the CPU oracle's operators at every grid (1 and all host threads)")
     ap.add_argument("--oracle-operators-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--group-tol", action="store_true",
+                    help="only run the 64-guess uneven group toward 1e-10 for a minute and print where it got")
     ap.add_argument("--dmd-schedule", action="store_true",
                     help="only run the 32x33x32 DMD schedule (cost history, plain vs DMD) and print it")
     args = ap.parse_args()
@@ -515,6 +559,11 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         run_copy_calibration()
+        return
+    if args.group_tol:
+        import torch
+        from paper_2306_00165_amd import inputs
+        print(json.dumps(group_tol_leg(torch, inputs)))
         return
     if args.dmd_schedule:
         import torch
