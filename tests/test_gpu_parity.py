@@ -486,6 +486,30 @@ def test_mixed_residual_adjoint_and_step(mixed_ctxs, name):
     assert e_r > 1e-12          # the FP32 stage really ran
 
 
+@pytest.mark.parametrize("shape", [(8, 512, 256), (8, 768, 512), (4, 256, 256)])
+def test_mixed_launch_shapes_match_oracle(shape):
+    """The FP32 physical-space kernels at pinned launch shapes (512 threads is
+    the default for FP32 launches of many modes) against the FP64 oracle at
+    32x33x32, within the mixed-precision bound."""
+    import torch
+    from paper_2306_00165_amd.pcfv import Context, MIXED
+    g = Grid(*GRIDS["cfg2"])
+    m = Method(g)
+    c = Context(*GRIDS["cfg2"], precision=MIXED)
+    c.set_tuning(*shape)
+    assert c.tuning() == shape
+    u, w = guess(g, 21), guess(g, 22)
+    e_r = rel(to_np(c.residual(u)), m.residual(u))
+    e_a = rel(to_np(c.adjoint(u, w)), m.adjoint(u, w))
+    U = torch.as_tensor(u).to("cuda:0").contiguous()
+    c.descend(U, max_steps=1, dtau=0.02)
+    u1, _ = m.descent_step(u, 0.02)
+    e_s = float(np.abs(to_np(U) - u1).max() / np.abs(u1 - u).max())
+    print(f"[gpu] mixed shape {shape}: residual {e_r:.2e} adjoint {e_a:.2e} step {e_s:.2e}")
+    assert e_r < TOL32 and e_a < TOL32 and e_s < TOL32
+    assert e_r > 1e-12
+
+
 def test_mixed_descent_refines_in_fp64(ctxs, mixed_ctxs):
     """fp64_below switches the rest of a call to FP64: always-below gives the
     trajectory of an FP64 context with the same launch shape bit for bit,
