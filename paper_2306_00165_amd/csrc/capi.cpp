@@ -73,7 +73,7 @@ bool validate(const pcfv_config* c, std::string& e) {
 // Default physical-space work-group size for a launch of nmB modes (see base_kp).
 static int plane_threads_default(int prec, long long nmB) {
     if (nmB <= 1024) return prec == PREC_FP64 ? 576 : 1024;
-    return prec == PREC_FP32 ? 512 : 1024;
+    return prec == PREC_FP32 ? 512 : 768;
 }
 
 KP base_kp(const pcfv_config& c) {
@@ -92,8 +92,7 @@ KP base_kp(const pcfv_config& c) {
     // widest x slab (a divisor of Nx) whose physical-space kernels fit the LDS
     // budget, at most 12 when a launch holds few modes (the latency-bound
     // case: more work groups) and at most 16 otherwise (fewer slabs, less
-    // partial traffic); the 1024-thread physical-space groups of both cases
-    // waste the fewest partial passes over the slab's work items
+    // partial traffic)
     p.XS = 1;
     const int xs_max = (p.nmB <= 1024) ? 12 : 16;
     for (int xs = xs_max; xs >= 1; --xs) {
@@ -104,10 +103,10 @@ KP base_kp(const pcfv_config& c) {
     }
     p.NS = c.Nx / p.XS;
     p.prec = c.precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
-    // 1024-thread physical-space groups, except FP64 launches with few modes,
-    // where 576 threads (9 waves) leave the registers for the inverse z
-    // transform to take two points per work item, and FP32 launches with many
-    // modes, where 512-thread groups (more of them resident per CU) are faster
+    // Physical-space group size: FP64 launches take 576 threads (9 waves) with
+    // few modes and 768 with many, sizes at which the registers let the
+    // inverse z transform take two points per work item; FP32 launches take
+    // 1024 with few modes and 512 with many (more groups resident per CU)
     p.pthreads = plane_threads_default(p.prec, p.nmB);
     // per-mode groups of 256 threads (4 lanes per contraction row): their
     // contractions have no idle waves for Ny up to 64 and several groups share a CU

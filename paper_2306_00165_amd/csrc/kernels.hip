@@ -937,10 +937,10 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     // doubled (real field), kz weights applied in the loop, beta at the end;
     // one twiddle load per kz serves every field.
     // The pairing needs a second set of sums: it is compiled where the
-    // registers allow it without spilling (FP32, or at most 576 threads).
+    // registers allow it (FP32, or at most 768 threads).
     const R yj = (R)p.ygl[j];
     constexpr int NA = NG1 > 0 ? NG1 : 1;
-    constexpr bool PAIRABLE = sizeof(R) == 4 || PLANE_THREADS <= 576;
+    constexpr bool PAIRABLE = sizeof(R) == 4 || PLANE_THREADS <= 768;
     const bool pair = PAIRABLE && !(Nz & 1);
     const int hz = pair ? Nz / 2 : Nz, npt = pair ? 2 : 1;
     for (int it = tid; it < XS * hz; it += PLANE_THREADS) {
