@@ -1280,8 +1280,14 @@ __global__ __launch_bounds__(NT) void k_plane(KP p, const C<R>* __restrict__ Y1,
     plane_body<MODE, R, NT>(p, xcd_item(blockIdx.x, gridDim.x), Y1, Y2, out);
 }
 
+// Minimum waves per SIMD the per-mode kernels are compiled for: 4 (at most
+// 128 VGPRs) from NP = 72 up, where launches hold thousands of modes and
+// occupancy pays; below, the register budget is left free (at one 48^3 guess
+// the bound made the kernels spill and run slower).
+template <int NP> constexpr int mode_min_waves() { return NP >= 72 ? 4 : 1; }
+
 template <int NP, int MT, class YT>
-__global__ __launch_bounds__(MT) void k_mode_res(KP p, int flags, const YT* __restrict__ P3,
+__global__ __launch_bounds__(MT, mode_min_waves<NP>()) void k_mode_res(KP p, int flags, const YT* __restrict__ P3,
                                                            const double2* __restrict__ u,
                                                            double2* __restrict__ r, double* __restrict__ cost_part,
                                                            double2* __restrict__ a, YT* __restrict__ Atil) {
@@ -1289,7 +1295,7 @@ __global__ __launch_bounds__(MT) void k_mode_res(KP p, int flags, const YT* __re
 }
 
 template <int NP, int MT, class YT>
-__global__ __launch_bounds__(MT) void k_mode_grad(KP p, int flags, const YT* __restrict__ P6,
+__global__ __launch_bounds__(MT, mode_min_waves<NP>()) void k_mode_grad(KP p, int flags, const YT* __restrict__ P6,
                                                             const double2* __restrict__ a, double dtau,
                                                             double2* __restrict__ uo, YT* __restrict__ Y) {
     mode_grad_body<NP, MT, YT>(p, xcd_item(blockIdx.x, gridDim.x), flags, P6, a, dtau, uo, Y);
@@ -1332,7 +1338,7 @@ __global__ __launch_bounds__(NT) void kg_plane(const GroupMember* __restrict__ g
 }
 
 template <int NP, int MT, class YT>
-__global__ __launch_bounds__(MT) void kg_mode_res(const GroupMember* __restrict__ gm, int n) {
+__global__ __launch_bounds__(MT, mode_min_waves<NP>()) void kg_mode_res(const GroupMember* __restrict__ gm, int n) {
     const int it = xcd_item(blockIdx.x, gridDim.x);
     if (it >= gm[n].item0[GPH_MODE]) return;
     const int k = group_member(gm, n, it, GPH_MODE);
@@ -1342,7 +1348,7 @@ __global__ __launch_bounds__(MT) void kg_mode_res(const GroupMember* __restrict_
 }
 
 template <int NP, int MT, class YT>
-__global__ __launch_bounds__(MT) void kg_mode_grad(const GroupMember* __restrict__ gm, int n) {
+__global__ __launch_bounds__(MT, mode_min_waves<NP>()) void kg_mode_grad(const GroupMember* __restrict__ gm, int n) {
     const int it = xcd_item(blockIdx.x, gridDim.x);
     if (it >= gm[n].item0[GPH_MODE]) return;
     const int k = group_member(gm, n, it, GPH_MODE);
