@@ -881,6 +881,9 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     //  DFT:  work item (g, xl, kz) forms sum_q Z[q] exp(2 pi i q xl / XS).
     constexpr int NZA = NG1 > 0 ? 4 : 3;     // folded arrays per group
     constexpr int GCH = NG3 < 3 ? NG3 : 3;   // groups per chunk
+    // XS-point DFTs (here and in the forward x transform) pair the outputs
+    // q and q + XS/2 (points xl and xl + XS/2) when XS is even
+    const int npx = (XS & 1) ? 1 : 2, hxs = (XS & 1) ? XS : XS / 2, perx = hxs * nkz;
     for (int g0 = 0; g0 < NG3; g0 += GCH) {
         for (int it = tid; it < GCH * per; it += PLANE_THREADS) {
             const int gc = it / per, rem = it - gc * per, q = rem / nkz, kz = rem - q * nkz;
@@ -907,24 +910,38 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             if constexpr (NG1 > 0) zo[3 * pfs] = zA;
         }
         __syncthreads();
-        for (int it = tid; it < GCH * per; it += PLANE_THREADS) {
-            const int gc = it / per, rem = it - gc * per, xl = rem / nkz, kz = rem - xl * nkz;
+        // With XS even an item takes the points xl and xl + XS/2: their
+        // twiddles differ by (-1)^q, so the even- and odd-q sums give both.
+        for (int it = tid; it < GCH * perx; it += PLANE_THREADS) {
+            const int gc = it / perx, rem = it - gc * perx, xl = rem / nkz, kz = rem - xl * nkz;
             const int g = g0 + gc;
             const CR* zi = zb + (size_t)(NZA * gc) * pfs + kz;
             const CR* td = TD + xl * XS;
-            CR aV = mkc(zero, zero), aK = aV, aW = aV, aT = aV;
-            for (int q = 0; q < XS; ++q) {
+            CR e[4], o[4];   // V, kx V, W, A: even- and odd-q sums
+#pragma unroll
+            for (int i = 0; i < 4; ++i) e[i] = o[i] = mkc(zero, zero);
+            auto term = [&](int q, CR (&a)[4]) {
                 const CR tw = td[q];
-                aV = cmac(aV, zi[q * ldz], tw);
-                aK = cmac(aK, zi[pfs + q * ldz], tw);
-                aW = cmac(aW, zi[2 * pfs + q * ldz], tw);
-                if constexpr (NG1 > 0) aT = cmac(aT, zi[3 * pfs + q * ldz], tw);
+#pragma unroll
+                for (int i = 0; i < NZA; ++i) a[i] = cmac(a[i], zi[i * pfs + q * ldz], tw);
+            };
+            for (int q = 0; q + 1 < XS; q += 2) {
+                term(q, e);
+                term(q + 1, o);
             }
-            const int xo = xl * ldz + kz;
-            xb[(3 * g) * pfs + xo] = aV;
-            xb[(3 * g + 1) * pfs + xo] = imul(alpha, aK);
-            xb[(3 * g + 2) * pfs + xo] = aW;
-            if constexpr (NG1 > 0) xb[(3 * NG3 + g) * pfs + xo] = aT;
+            if (XS & 1) term(XS - 1, e);   // odd XS: unpaired, a single point from e + o
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h >= npx) break;
+                const int xo = (xl + h * hxs) * ldz + kz;
+                CR a[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = h ? csub(e[i], o[i]) : cadd(e[i], o[i]);
+                xb[(3 * g) * pfs + xo] = a[0];
+                xb[(3 * g + 1) * pfs + xo] = imul(alpha, a[1]);
+                xb[(3 * g + 2) * pfs + xo] = a[2];
+                if constexpr (NG1 > 0) xb[(3 * NG3 + g) * pfs + xo] = a[3];
+            }
         }
         __syncthreads();
     }
@@ -1083,17 +1100,25 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     // the fields (A_i, B_i, C_i) = xb fields (3 i, 3 i + 1, 3 i + 2).
     constexpr int NOUT = (MODE == PLANE_ADJ) ? 6 : 3;
     constexpr int NIN = (MODE == PLANE_ADJ) ? 9 : 3;
-    for (int it = tid; it < NIN * per; it += PLANE_THREADS) {
-        const int f = it / per, rem = it - f * per, q = rem / nkz, kz = rem - q * nkz;
+    // With XS even an item forms F[q] and F[q + XS/2] from the even- and
+    // odd-xl sums (their twiddles differ by (-1)^xl).
+    for (int it = tid; it < NIN * perx; it += PLANE_THREADS) {
+        const int f = it / perx, rem = it - f * perx, q = rem / nkz, kz = rem - q * nkz;
         const CR* v = xb + f * pfs + kz;
         const CR* td = TD + q * XS;
-        R ar = 0, ai = 0;
-        for (int xl = 0; xl < XS; ++xl) {   // (ar, ai) += v conj(tw)
+        R er = 0, ei = 0, orr = 0, oi = 0;
+        auto term = [&](int xl, R& ar, R& ai) {   // (ar, ai) += v conj(tw)
             const CR tw = td[xl], x = v[xl * ldz];
             ar = fmar(x.y, tw.y, fmar(x.x, tw.x, ar));
             ai = fmar(-x.x, tw.y, fmar(x.y, tw.x, ai));
+        };
+        for (int xl = 0; xl + 1 < XS; xl += 2) {
+            term(xl, er, ei);
+            term(xl + 1, orr, oi);
         }
-        zb[f * pfs + q * ldz + kz] = mkc(ar, ai);
+        if (XS & 1) term(XS - 1, er, ei);
+        zb[f * pfs + q * ldz + kz] = mkc(er + orr, ei + oi);
+        if (npx == 2) zb[f * pfs + (q + hxs) * ldz + kz] = mkc(er - orr, ei - oi);
     }
     __syncthreads();
     for (int mm = tid; mm < nm; mm += PLANE_THREADS) {
