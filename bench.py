@@ -32,6 +32,11 @@ PEAK_HBM = 8000.0         # GB/s
 KERNELS = ["synth", "plane_fwd", "mode_res", "plane_adj", "mode_grad"]
 
 
+def _note(msg):
+    """Progress of a long run, on stderr (stdout carries the one JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_model(Nx, Ny, Nz):
     """Algorithmic FLOPs and bytes per launch of each kernel (one launch
     processes all Ny planes or all Fourier modes of one field set).
@@ -484,10 +489,12 @@ def time_to_tol_leg(torch, inputs, plain_s=20.0, chosen_s=40.0, late_s=10.0):
                      "after a window gaining < 10%, accept if cheaper)"}
     cp = Context(*dims, batch=B)
     plain = _trace(torch, cp, U0.clone(), dtau, plain_s, 4000, 2000)
+    _note("time to tolerance: plain FP64 run done")
     cc = Context(*dims, batch=B, precision=MIXED)
     Uc = U0.clone()
     chosen = _ladder_trace(torch, cc, Uc, dtau, chosen_s, 200, check_every=500, fp64_below=1e-3,
                            dmd_window=20, dmd_gap=0, dmd_accept=1.0, dmd_stride_max=6400, dmd_grow_ratio=0.9)
+    _note("time to tolerance: chosen-form run done")
     late = _trace(torch, cp, Uc.clone(), dtau, late_s, 4000, 2000)
     r_plain, r_late = _rate(plain), _rate(late)
     t_p_end, _, rel_p_end = plain[-1]
@@ -572,6 +579,8 @@ def main():
         return
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+    if cpu is not None:
+        _note("CPU oracle baseline done")
 
     import torch
     from paper_2306_00165_amd import inputs
@@ -590,6 +599,7 @@ def main():
         raise RuntimeError(f"descent returned status {st}: {rep}")
     steps_per_s = args.steps / dt
     _, rep = c.descend(u, max_steps=0, dtau=DTAU)     # cost of the final state, after the timed region
+    _note(f"timed region done: {steps_per_s:.1f} steps/s")
 
     # per-kernel device time inside consecutive descent steps (HIP events on
     # the context stream), over steps that continue the timed trajectory
@@ -607,6 +617,8 @@ def main():
                 "avg_launch_ms": round(ms[KERNELS.index(dom)], 5),
                 "hbm_GBps_algorithmic": round(nbytes / t_dom / 1e9, 2)}
     extra = {} if args.no_extra else extra_legs(torch, inputs, args.steps)
+    if not args.no_extra:
+        _note("context legs done")
     if not args.no_extra and not args.no_time_to_tol:
         extra["time_to_tol"] = time_to_tol_leg(torch, inputs)
     out = {

@@ -72,8 +72,7 @@ bool validate(const pcfv_config* c, std::string& e) {
 
 // Default physical-space work-group size for a launch of nmB modes (see base_kp).
 static int plane_threads_default(int prec, long long nmB) {
-    if (nmB <= 1024) return prec == PREC_FP64 ? 576 : 1024;
-    return prec == PREC_FP32 ? 512 : 768;
+    return (prec == PREC_FP32 && nmB > 1024) ? 512 : 1024;
 }
 
 KP base_kp(const pcfv_config& c) {
@@ -103,10 +102,8 @@ KP base_kp(const pcfv_config& c) {
     }
     p.NS = c.Nx / p.XS;
     p.prec = c.precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
-    // Physical-space group size: FP64 launches take 576 threads (9 waves) with
-    // few modes and 768 with many, sizes at which the registers let the
-    // inverse z transform take two points per work item; FP32 launches take
-    // 1024 with few modes and 512 with many (more groups resident per CU)
+    // Physical-space group size: 1024 threads, except FP32 launches with many
+    // modes, which take 512 (more groups resident per CU)
     p.pthreads = plane_threads_default(p.prec, p.nmB);
     // per-mode groups of 256 threads (4 lanes per contraction row): their
     // contractions have no idle waves for Ny up to 64 and several groups share a CU

@@ -142,6 +142,15 @@ template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
+
+// v in the partner lane (lane ^ 1) of a lane pair
+template <class R> __device__ __forceinline__ R lane_pair_swap(R v) {
+    if constexpr (sizeof(R) == 8)
+        return dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    else
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, false));
+}
+
 __device__ __forceinline__ double swap16_max(double v) {
     const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
     const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
@@ -828,20 +837,21 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     const int nmB = p.nmB, mo = b * nm;                // y-value arrays are [f][j][b * nm + m]
     const int Kx = p.Kx;
     const int tid = threadIdx.x;
-    const int per = XS * nkz, tzs = nkz + 1;
-    // LDS rows are padded by one entry (x-slab rows of the spectral buffer xb
-    // to nkz + 1, of the products pb to Nz + 1): lanes at neighbouring x read
-    // rows that start in different banks instead of the same one
-    const int ldz = nkz + 1, pfs = XS * ldz, ldq = Nz + 1, pz = XS * ldq;
+    // LDS rows are padded: the kz rows of the spectral buffer xb and of the z
+    // twiddles to kz_row(nkz) entries (twice an odd number), the products pb
+    // to Nz + 1.  Lanes at neighbouring x or z then start in different banks,
+    // also where the two lanes of a pair read neighbouring kz.
+    const int per = XS * nkz, tzs = kz_row(nkz);
+    const int ldz = kz_row(nkz), pfs = XS * ldz, ldq = Nz + 1, pz = XS * ldq;
     // The slab holds the points x = s + NS xl (xl < XS): since
     //   exp(2 pi i kx x / Nx) = exp(2 pi i kx s / Nx) exp(2 pi i (kx mod XS) xl / XS),
     // its x transforms split into a fold of the retained kx by kx mod XS (with
     // the slab's phase) and an XS-point DFT.
     // Twiddle tables: TS[ikx] = exp(2 pi i kx s / Nx) for every retained kx,
     // TD[xl][q] = exp(2 pi i q xl / XS) (symmetric), TZ[z][kz] =
-    // exp(2 pi i kz z / Nz) with rows padded to nkz + 1 entries, so that lanes
-    // running over kz (forward z transform) and lanes running over z (inverse
-    // z transform) both read distinct LDS banks.  With Nz even TZ holds the
+    // exp(2 pi i kz z / Nz) with padded rows, so that lanes running over kz
+    // (forward z transform) and lanes running over z (inverse z transform)
+    // both read distinct LDS banks.  With Nz even TZ holds the
     // rows z < Nz/2 only: the twiddles of z + Nz/2 are (-1)^kz times those of z.
     const int nzt = (Nz & 1) ? Nz : Nz / 2;
     CR* TS = sm;
@@ -853,24 +863,29 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     // products buffer, which is not live at those times: array a at
     // zb[a * pfs + q * ldz + kz].
     CR* zb = reinterpret_cast<CR*>(pb);
-    {
-        const int ntd = XS * XS, ntz = nzt * nkz;
-        const int nset = max(max(nkx, ntd), ntz);
-#pragma unroll 1
-        for (int i = tid; i < nset; i += PLANE_THREADS) {
-            double2 vs = make_double2(0.0, 0.0), vd = vs, vz = vs;
-            const int kx = (i <= Kx) ? i : i - nkx;
-            const int xl = i / XS, q = i - xl * XS;
-            const int z = i / nkz, kz = i - z * nkz;
-            if (i < nkx) vs = p.twx[(kx + Nx) * s % Nx];
-            if (i < ntd) vd = p.twx[(q * xl) % XS * p.NS];
-            if (i < ntz) vz = p.twz[(kz * z) % Nz];
-            if (i < nkx) TS[i] = narrow<CR>(vs);
-            if (i < ntd) TD[i] = narrow<CR>(vd);
-            if (i < ntz) TZ[z * tzs + kz] = narrow<CR>(vz);
-        }
-    }
-    __syncthreads();
+    // Set-up of the twiddle tables, entry i of each.  Every index is reduced
+    // mod Nx or Nz, so the loads are in bounds for any i and only the stores
+    // are guarded.  The first pass's loads are issued here and its stores
+    // made after the fold below, so the two sets of global reads are in
+    // flight together; the tables are published by the fold's barrier (the
+    // fold itself reads the slab phases from global memory).
+    const int ntd = XS * XS, ntz = nzt * nkz, nset = max(max(nkx, ntd), ntz);
+    auto tw_load = [&](int i, double2 (&v)[3]) {
+        const int kx = (i <= Kx) ? i : i - nkx;   // kx + Nx > 0 for every i
+        const int xl = i / XS, q = i - xl * XS;
+        const int z = i / nkz, kz = i - z * nkz;
+        v[0] = p.twx[(kx + Nx) * s % Nx];
+        v[1] = p.twx[(q * xl) % XS * p.NS];
+        v[2] = p.twz[(kz * z) % Nz];
+    };
+    auto tw_store = [&](int i, const double2 (&v)[3]) {
+        const int z = i / nkz, kz = i - z * nkz;
+        if (i < nkx) TS[i] = narrow<CR>(v[0]);
+        if (i < ntd) TD[i] = narrow<CR>(v[1]);
+        if (i < ntz) TZ[z * tzs + kz] = narrow<CR>(v[2]);
+    };
+    double2 tw0[3];
+    tw_load(tid, tw0);
 
     // Inverse transform in x for the slab's points, all retained kz, in chunks
     // of up to three velocity groups g (fields V, i a V, W; in the adjoint
@@ -894,20 +909,56 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
             const CR* Wp = src + ((size_t)(3 + comp) * N + j) * nmB + mo + kz;
             const CR* Ap = (NG1 > 0) ? Y2 + ((size_t)g * N + j) * nmB + mo + kz : nullptr;
             CR zV = mkc(zero, zero), zK = zV, zW = zV, zA = zV;
-            for (int kx = -Kx + (q + Kx) % XS; kx <= Kx; kx += XS) {
-                const int ikx = (kx >= 0) ? kx : kx + nkx;
-                const CR tw = TS[ikx];
-                const CR vt = cmul(Vp[(size_t)ikx * nkz], tw);
-                zV = cadd(zV, vt);
-                zK = mkc(fmar((R)kx, vt.x, zK.x), fmar((R)kx, vt.y, zK.y));
-                zW = cmac(zW, Wp[(size_t)ikx * nkz], tw);
-                if constexpr (NG1 > 0) zA = cmac(zA, Ap[(size_t)ikx * nkz], tw);
+            // the retained kx = q (mod XS) are kx0 + XS t (t < cnt), with slab
+            // phase exp(2 pi i kx s / Nx) at twx[ti], ti stepping by XS s < Nx;
+            // the terms go in batches of FB whose loads issue together: past
+            // the last term the index is clamped and the phase set to zero, so
+            // no use of a load is conditional (the compiler would otherwise
+            // sink each load to its use and wait for it there)
+            constexpr int FB = 4;
+            const int kx0 = -Kx + (q + Kx) % XS;
+            const int cnt = (kx0 <= Kx) ? (Kx - kx0) / XS + 1 : 0;
+            const int dts = XS * s;
+            int ti = (kx0 + Nx) * s % Nx;
+            for (int t0 = 0; t0 < cnt; t0 += FB) {
+                CR tw[FB], yv[FB], yw[FB], ya[FB];
+#pragma unroll
+                for (int u = 0; u < FB; ++u) {
+                    const int kx = kx0 + XS * min(t0 + u, cnt - 1);
+                    const size_t ikx = (size_t)((kx >= 0) ? kx : kx + nkx) * nkz;
+                    const CR t = narrow<CR>(p.twx[ti]);
+                    const bool live = t0 + u < cnt;
+                    tw[u] = mkc(live ? t.x : zero, live ? t.y : zero);
+                    ti += dts;
+                    if (ti >= Nx) ti -= Nx;
+                    yv[u] = Vp[ikx];
+                    yw[u] = Wp[ikx];
+                    if constexpr (NG1 > 0) ya[u] = Ap[ikx];
+                }
+#pragma unroll
+                for (int u = 0; u < FB; ++u) {
+                    const R kx = (R)(kx0 + XS * (t0 + u));
+                    const CR vt = cmul(yv[u], tw[u]);
+                    zV = cadd(zV, vt);
+                    zK = mkc(fmar(kx, vt.x, zK.x), fmar(kx, vt.y, zK.y));
+                    zW = cmac(zW, yw[u], tw[u]);
+                    if constexpr (NG1 > 0) zA = cmac(zA, ya[u], tw[u]);
+                }
             }
             CR* zo = zb + (size_t)(NZA * gc) * pfs + q * ldz + kz;
             zo[0] = zV;
             zo[pfs] = zK;
             zo[2 * pfs] = zW;
             if constexpr (NG1 > 0) zo[3 * pfs] = zA;
+        }
+        if (g0 == 0) {
+            tw_store(tid, tw0);
+#pragma unroll 1
+            for (int i = tid + PLANE_THREADS; i < nset; i += PLANE_THREADS) {
+                double2 v[3];
+                tw_load(i, v);
+                tw_store(i, v);
+            }
         }
         __syncthreads();
         // With XS even an item takes the points xl and xl + XS/2: their
@@ -946,37 +997,35 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
         __syncthreads();
     }
 
-    // inverse (complex-to-real) transform in z, then the products.  With Nz
-    // even a work item takes the points z and z + Nz/2 of one x: their
-    // twiddles differ by (-1)^kz, so sums over the odd and the even kz give
-    // both points from one pass over the coefficients.  Per velocity field the
-    // sums give U, dU/dx, dU/dy, dU/dz: Re of the kz sums, the kz > 0 terms
-    // doubled (real field), kz weights applied in the loop, beta at the end;
-    // one twiddle load per kz serves every field.
-    // The pairing needs a second set of sums: it is compiled where the
-    // registers allow it (FP32, or at most 768 threads).
+    // inverse (complex-to-real) transform in z, then the products.  Per
+    // velocity field the kz sums give U, dU/dx, dU/dy, dU/dz: Re of the sums,
+    // the kz > 0 terms doubled (real field), kz weights applied in the loop,
+    // beta at the end; one twiddle load per kz serves every field.  With Nz
+    // even the lanes 2k and 2k + 1 take the points z and z + Nz/2 of one x,
+    // whose twiddles differ by (-1)^kz: the first sums the odd kz, its partner
+    // the even kz > 0, and an exchange of the sums between the two lanes gives
+    // each its point (even + odd, even - odd).  With Nz odd a lane takes one
+    // point and sums every kz.
     const R yj = (R)p.ygl[j];
     constexpr int NA = NG1 > 0 ? NG1 : 1;
-    constexpr bool PAIRABLE = sizeof(R) == 4 || PLANE_THREADS <= 768;
-    const bool pair = PAIRABLE && !(Nz & 1);
-    const int hz = pair ? Nz / 2 : Nz, npt = pair ? 2 : 1;
-    for (int it = tid; it < XS * hz; it += PLANE_THREADS) {
-        const int xl = it / hz, z = it - xl * hz;
+    const bool pair = !(Nz & 1);
+    const int hz = pair ? Nz / 2 : Nz;   // = nzt: the twiddle rows cover z < hz
+    // items XS * Nz (even with Nz even): lane pairs are active together
+    for (int it = tid; it < XS * Nz; it += PLANE_THREADS) {
+        const int h = pair ? (it & 1) : 0, pr = pair ? (it >> 1) : it;
+        const int xl = pr / hz, z = pr - xl * hz;
         const CR* c0 = xb + xl * ldz;   // field f at c0[f * pfs + kz]
-        // an unpaired point z >= Nz/2 (Nz even) reads row z - Nz/2 with the
-        // odd-kz twiddles negated
-        const bool up = z >= nzt;
-        const CR* tz = TZ + (up ? z - nzt : z) * tzs;
-        const R so = up ? (R)-1 : (R)1;
-        R ve[NG3][4], vo[NG3][4], ae[NA], ao[NA];   // even- and odd-kz sums
+        const CR* tz = TZ + z * tzs;
+        R v[NG3][4], a[NA];
 #pragma unroll
         for (int g = 0; g < NG3; ++g)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) ve[g][q] = vo[g][q] = 0;
+            for (int q = 0; q < 4; ++q) v[g][q] = 0;
 #pragma unroll
-        for (int i = 0; i < NA; ++i) ae[i] = ao[i] = 0;
-        auto term = [&](int kz, R (&v)[NG3][4], R (&a)[NA], R sgn) {
-            const CR t0 = tz[kz], tw = mkc(sgn * t0.x, sgn * t0.y);
+        for (int i = 0; i < NA; ++i) a[i] = 0;
+        const int kst = pair ? 2 : 1;
+        for (int kz = 1 + h; kz < nkz; kz += kst) {
+            const CR tw = tz[kz];
             const R kzr = (R)kz;
 #pragma unroll
             for (int g = 0; g < NG3; ++g) {
@@ -991,91 +1040,90 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
                 const CR cc = c0[(3 * NG3 + i) * pfs + kz];
                 a[i] = fmar(-cc.y, tw.y, fmar(cc.x, tw.x, a[i]));
             }
-        };
-        for (int kz = 1; kz < nkz; kz += 2) {
-            term(kz, vo, ao, so);
-            if (kz + 1 < nkz) {
-                if constexpr (PAIRABLE)
-                    term(kz + 1, ve, ae, (R)1);
-                else
-                    term(kz + 1, vo, ao, (R)1);   // one point per item: a single set of sums
-            }
+        }
+        // own sums S and the partner's P: point z is S + P (h = 0, S odd),
+        // point z + Nz/2 is S - P (h = 1, S even)
+        const R sg = h ? (R)-1 : (R)1;
+        auto tot = [&](R own) { return pair ? own + sg * lane_pair_swap(own) : own; };
+        R val[NG3][4], at[NA];
+#pragma unroll
+        for (int g = 0; g < NG3; ++g) {
+            val[g][0] = c0[(3 * g) * pfs].x + two * tot(v[g][0]);
+            val[g][1] = c0[(3 * g + 1) * pfs].x + two * tot(v[g][1]);
+            val[g][2] = c0[(3 * g + 2) * pfs].x + two * tot(v[g][2]);
+            val[g][3] = -two * beta * tot(v[g][3]);
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {   // h = 0: point z, h = 1: point z + Nz/2
-            if (h >= npt) break;
-            const R sg = h ? (R)-1 : (R)1;
-            const int pt = xl * ldq + z + h * hz;
-            R val[NG3][4], at[NA];
-#pragma unroll
-            for (int g = 0; g < NG3; ++g) {
-                val[g][0] = c0[(3 * g) * pfs].x + two * (ve[g][0] + sg * vo[g][0]);
-                val[g][1] = c0[(3 * g + 1) * pfs].x + two * (ve[g][1] + sg * vo[g][1]);
-                val[g][2] = c0[(3 * g + 2) * pfs].x + two * (ve[g][2] + sg * vo[g][2]);
-                val[g][3] = -two * beta * (ve[g][3] + sg * vo[g][3]);
-            }
-#pragma unroll
-            for (int i = 0; i < NG1; ++i) at[i] = c0[(3 * NG3 + i) * pfs].x + two * (ae[i] + sg * ao[i]);
-            val[0][0] += yj;   // base flow u_b = y e_x
-            val[0][2] += (R)1; // d(u_b)_x / dy = 1
-            if (MODE == PLANE_FWD) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    pb[i * pz + pt] = val[0][0] * val[i][1] + val[1][0] * val[i][2] + val[2][0] * val[i][3];
-            } else if (MODE == PLANE_JVP) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    R q = 0;
-#pragma unroll
-                    for (int jj = 0; jj < 3; ++jj)
-                        q += val[jj][0] * val[3 + i][1 + jj] + val[3 + jj][0] * val[i][1 + jj];
-                    pb[i * pz + pt] = q;
-                }
+        for (int i = 0; i < NG1; ++i) at[i] = c0[(3 * NG3 + i) * pfs].x + two * tot(a[i]);
+        val[0][0] += yj;   // base flow u_b = y e_x
+        val[0][2] += (R)1; // d(u_b)_x / dy = 1
+        // product f at this point; a lane pair stores the sum of its two
+        // products at z and their difference at z + Nz/2, which the forward z
+        // transform reads for even and odd kz respectively
+        const int pt = xl * ldq + z + h * hz;
+        auto put = [&](int f, R q) {
+            if (pair) {
+                const R w = lane_pair_swap(q);
+                pb[f * pz + pt] = h ? w - q : q + w;
             } else {
+                pb[f * pz + pt] = q;
+            }
+        };
+        if (MODE == PLANE_FWD) {
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
+                put(i, val[0][0] * val[i][1] + val[1][0] * val[i][2] + val[2][0] * val[i][3]);
+        } else if (MODE == PLANE_JVP) {
 #pragma unroll
-                    for (int jj = 0; jj < 3; ++jj) pb[(3 * i + jj) * pz + pt] = val[jj][0] * at[i];
+            for (int i = 0; i < 3; ++i) {
+                R q = 0;
 #pragma unroll
                 for (int jj = 0; jj < 3; ++jj)
-                    pb[(9 + jj) * pz + pt] =
-                        val[0][1 + jj] * at[0] + val[1][1 + jj] * at[1] + val[2][1 + jj] * at[2];
+                    q += val[jj][0] * val[3 + i][1 + jj] + val[3 + jj][0] * val[i][1 + jj];
+                put(i, q);
             }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) put(3 * i + jj, val[jj][0] * at[i]);
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj)
+                put(9 + jj, val[0][1 + jj] * at[0] + val[1][1 + jj] * at[1] + val[2][1 + jj] * at[2]);
         }
     }
     __syncthreads();
 
     // forward transform in z (normalised), into xb.  Adjoint variant: work item
     // (i, xl, kz) forms the three outputs of component i, sharing the twiddles.
-    // With Nz even the sum runs over z < Nz/2 of q[z] + (-1)^kz q[z + Nz/2].
+    // With Nz even the sum runs over z < Nz/2 of q[z] + (-1)^kz q[z + Nz/2],
+    // which the products stage stored (at z for even kz, at z + Nz/2 for odd).
     const R invNz = (R)1 / (R)Nz, invNx = (R)1 / (R)Nx;
-    const int zo = (Nz & 1) ? 0 : Nz / 2;
     constexpr int NZI = (MODE == PLANE_ADJ) ? 3 : NZF;
     for (int it = tid; it < NZI * per; it += PLANE_THREADS) {
         const int o = it / per, rem = it - o * per, xl = rem / nkz, kz = rem - xl * nkz;
         const CR* tzk = TZ + kz;   // tzk[z * tzs] = exp(2 pi i kz z / Nz)
-        const R sk = zo ? ((kz & 1) ? (R)-1 : (R)1) : (R)0;   // q[z + zo] weight (zo = 0: q[z] alone)
+        const int ko = xl * ldq + ((pair && (kz & 1)) ? hz : 0);   // row of the stored sums
         if (MODE != PLANE_ADJ) {
-            const R* q = pb + o * pz + xl * ldq;
+            const R* q = pb + o * pz + ko;
             R ar = 0, ai = 0;
             for (int z = 0; z < nzt; ++z) {
                 const CR tw = tzk[z * tzs];
-                const R v = fmar(sk, q[z + zo], q[z]);
+                const R v = q[z];
                 ar = fmar(v, tw.x, ar);
                 ai = fmar(-v, tw.y, ai);
             }
             xb[o * pfs + xl * ldz + kz] = mkc(ar * invNz, ai * invNz);
         } else {
             const int i = o;
-            const R* q1 = pb + (9 + i) * pz + xl * ldq;      // Q_i
-            const R* q2 = pb + (3 * i + 2) * pz + xl * ldq;  // P_{i,z}
-            const R* qx = pb + (3 * i) * pz + xl * ldq;      // P_{i,x}
-            const R* qy = pb + (3 * i + 1) * pz + xl * ldq;  // P_{i,y}
+            const R* q1 = pb + (9 + i) * pz + ko;      // Q_i
+            const R* q2 = pb + (3 * i + 2) * pz + ko;  // P_{i,z}
+            const R* qx = pb + (3 * i) * pz + ko;      // P_{i,x}
+            const R* qy = pb + (3 * i + 1) * pz + ko;  // P_{i,y}
             R ar = 0, ai = 0, br = 0, bi = 0, xr = 0, xi = 0, yr = 0, yi = 0;
             for (int z = 0; z < nzt; ++z) {
                 const CR tw = tzk[z * tzs];
-                const R v1 = fmar(sk, q1[z + zo], q1[z]), v2 = fmar(sk, q2[z + zo], q2[z]);
-                const R vx = fmar(sk, qx[z + zo], qx[z]), vy = fmar(sk, qy[z + zo], qy[z]);
+                const R v1 = q1[z], v2 = q2[z], vx = qx[z], vy = qy[z];
                 ar = fmar(v1, tw.x, ar);
                 ai = fmar(-v1, tw.y, ai);
                 br = fmar(v2, tw.x, br);
@@ -1768,10 +1816,10 @@ size_t plane_lds_bytes(const KP& p, int mode) {
     const int npf = (mode == PLANE_ADJ) ? 12 : 3;
     const size_t nxf = 3 * ng3 + ng1, r = p.prec == PREC_FP32 ? 4 : 8;
     const size_t products = (size_t)npf * p.XS * (p.Nz + 1) * r;
-    const size_t row = (size_t)p.XS * (p.nkz + 1) * 2 * r;   // one x-slab array of nkz + 1 complex per x
+    const size_t row = (size_t)p.XS * kz_row(p.nkz) * 2 * r;   // one x-slab array of kz_row(nkz) complex per x
     const size_t folded = (size_t)(ng1 > 0 ? 12 : 9) * row;    // aliases products, as does the x DFT (<= 9 arrays)
     const size_t nzt = (p.Nz & 1) ? p.Nz : p.Nz / 2;   // rows of the z twiddle table
-    const size_t twiddles = (size_t)p.nkx + (size_t)p.XS * p.XS + nzt * (p.nkz + 1);
+    const size_t twiddles = (size_t)p.nkx + (size_t)p.XS * p.XS + nzt * kz_row(p.nkz);
     return twiddles * 2 * r + nxf * row + std::max(products, folded);
 }
 

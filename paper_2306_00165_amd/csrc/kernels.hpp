@@ -88,6 +88,10 @@ int padded_ny(int N);
 // Row stride (doubles) of the fixed-matrix slots for padded Ny np: a multiple
 // of 16 so that every aligned 8-row chunk a wave loads lies in one 128-byte line.
 constexpr int mat_ld(int np) { return (np + 15) / 16 * 16; }
+// Row length (complex entries) of the kz rows in the physical-space kernels'
+// LDS: the smallest length >= nkz that is twice an odd number, so that rows
+// z and z + 1 (or x and x + 1) start 2 mod 4 complex entries apart.
+constexpr int kz_row(int nkz) { return nkz + (6 - nkz % 4) % 4; }
 
 size_t plane_lds_bytes(const KP& p, int mode);
 size_t mode_lds_bytes(const KP& p);
