@@ -309,8 +309,9 @@ pcfv_status pcfv_autotune(pcfv_ctx* ctx, const double* u, int steps, pcfv_tune_e
 /* The launch shape in use (x-slab width, physical-space and per-mode work-group
  * sizes; any pointer may be NULL).  Without pcfv_autotune: the widest slab
  * that fits, up to 12 (16 when the context holds more than 1024 modes over all
- * guesses), 1024-thread physical-space groups (512 for mixed-precision
- * contexts of more than 1024 modes) and 256-thread per-mode groups. */
+ * guesses), physical-space groups of 768 threads in FP64 and of 1024 in
+ * mixed precision (512 for more than 1024 modes), and 256-thread per-mode
+ * groups. */
 pcfv_status pcfv_get_tuning(const pcfv_ctx* ctx, int* xs, int* plane_threads, int* mode_threads);
 /* Sets the launch shape explicitly: xs must be one of the slab widths the
  * autotuner considers, plane_threads one of 256, 512, 576, 768, 1024 and

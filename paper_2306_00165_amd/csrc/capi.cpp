@@ -72,7 +72,8 @@ bool validate(const pcfv_config* c, std::string& e) {
 
 // Default physical-space work-group size for a launch of nmB modes (see base_kp).
 static int plane_threads_default(int prec, long long nmB) {
-    return (prec == PREC_FP32 && nmB > 1024) ? 512 : 1024;
+    if (prec == PREC_FP64) return 768;
+    return nmB > 1024 ? 512 : 1024;
 }
 
 KP base_kp(const pcfv_config& c) {
@@ -102,8 +103,9 @@ KP base_kp(const pcfv_config& c) {
     }
     p.NS = c.Nx / p.XS;
     p.prec = c.precision == PCFV_MIXED ? PREC_FP32 : PREC_FP64;
-    // Physical-space group size: 1024 threads, except FP32 launches with many
-    // modes, which take 512 (more groups resident per CU)
+    // Physical-space group size: 768 threads in FP64 (1024 would spill a few
+    // registers of the forward kernel); in FP32 1024, or 512 with many modes
+    // (more groups resident per CU)
     p.pthreads = plane_threads_default(p.prec, p.nmB);
     // per-mode groups of 256 threads (4 lanes per contraction row): their
     // contractions have no idle waves for Ny up to 64 and several groups share a CU

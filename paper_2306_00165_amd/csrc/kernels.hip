@@ -1001,7 +1001,8 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     // velocity field the kz sums give U, dU/dx, dU/dy, dU/dz: Re of the sums,
     // the kz > 0 terms doubled (real field), kz weights applied in the loop,
     // beta at the end; one twiddle load per kz serves every field.  With Nz
-    // even the lanes 2k and 2k + 1 take the points z and z + Nz/2 of one x,
+    // even but not a multiple of 4 (a multiple of 4: mirrored points, below)
+    // the lanes 2k and 2k + 1 take the points z and z + Nz/2 of one x,
     // whose twiddles differ by (-1)^kz: the first sums the odd kz, its partner
     // the even kz > 0, and an exchange of the sums between the two lanes gives
     // each its point (even + odd, even - odd).  With Nz odd a lane takes one
@@ -1010,86 +1011,192 @@ __device__ __forceinline__ void plane_body(const KP& p, int item, const C<R>* __
     constexpr int NA = NG1 > 0 ? NG1 : 1;
     const bool pair = !(Nz & 1);
     const int hz = pair ? Nz / 2 : Nz;   // = nzt: the twiddle rows cover z < hz
-    // items XS * Nz (even with Nz even): lane pairs are active together
-    for (int it = tid; it < XS * Nz; it += PLANE_THREADS) {
-        const int h = pair ? (it & 1) : 0, pr = pair ? (it >> 1) : it;
-        const int xl = pr / hz, z = pr - xl * hz;
-        const CR* c0 = xb + xl * ldz;   // field f at c0[f * pfs + kz]
-        const CR* tz = TZ + z * tzs;
-        R v[NG3][4], a[NA];
-#pragma unroll
-        for (int g = 0; g < NG3; ++g)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[g][q] = 0;
-#pragma unroll
-        for (int i = 0; i < NA; ++i) a[i] = 0;
-        const int kst = pair ? 2 : 1;
-        for (int kz = 1 + h; kz < nkz; kz += kst) {
-            const CR tw = tz[kz];
-            const R kzr = (R)kz;
+    // With Nz a multiple of 4 a lane pair takes the four points z, Nz - z,
+    // z + Nz/2 and Nz/2 - z (0 <= z <= Nz/4) of one x.  With
+    // w = exp(2 pi i kz z / Nz) their twiddles are w, conj(w), (-1)^kz w and
+    // (-1)^kz conj(w), so Re(c w) = c.x cos - c.y sin and its mirror
+    // c.x cos + c.y sin share one read of c and of w: lane pc sums the kz of
+    // parity pc (0 even, 1 odd) as c.x cos and c.y sin per value field and as
+    // kz c.y cos and kz c.x sin per velocity field (dU/dz), and an exchange
+    // of the combined sums between the two lanes gives lane 0 the points z
+    // and Nz - z, lane 1 the points z + Nz/2 and Nz/2 - z.  For z = 0 and
+    // z = Nz/4 the second points repeat first ones and are not stored.
+    const bool mirror = !(Nz & 3);
+    if (mirror) {
+        const int q4 = Nz / 4, nq = q4 + 1;
+        for (int it = tid; it < 2 * XS * nq; it += PLANE_THREADS) {
+            const int pc = it & 1, qd = it >> 1;
+            const int xl = qd / nq, z = qd - xl * nq;
+            const CR* c0 = xb + xl * ldz;   // field f at c0[f * pfs + kz]
+            const CR* tz = TZ + z * tzs;
+            R va[NG3][3], vb[NG3][3], vc[NG3], vd[NG3], aa[NA], ab[NA];
 #pragma unroll
             for (int g = 0; g < NG3; ++g) {
-                const CR cV = c0[(3 * g) * pfs + kz], cA = c0[(3 * g + 1) * pfs + kz], cW = c0[(3 * g + 2) * pfs + kz];
-                v[g][0] = fmar(-cV.y, tw.y, fmar(cV.x, tw.x, v[g][0]));
-                v[g][3] = fmar(kzr, fmar(cV.y, tw.x, cV.x * tw.y), v[g][3]);
-                v[g][1] = fmar(-cA.y, tw.y, fmar(cA.x, tw.x, v[g][1]));
-                v[g][2] = fmar(-cW.y, tw.y, fmar(cW.x, tw.x, v[g][2]));
+                vc[g] = vd[g] = 0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) va[g][q] = vb[g][q] = 0;
             }
 #pragma unroll
-            for (int i = 0; i < NG1; ++i) {
-                const CR cc = c0[(3 * NG3 + i) * pfs + kz];
-                a[i] = fmar(-cc.y, tw.y, fmar(cc.x, tw.x, a[i]));
+            for (int i = 0; i < NA; ++i) aa[i] = ab[i] = 0;
+            for (int kz = 2 - pc; kz < nkz; kz += 2) {
+                const CR tw = tz[kz];
+                const R kc = (R)kz * tw.x, ks = (R)kz * tw.y;
+#pragma unroll
+                for (int g = 0; g < NG3; ++g) {
+                    const CR cV = c0[(3 * g) * pfs + kz], cA = c0[(3 * g + 1) * pfs + kz], cW = c0[(3 * g + 2) * pfs + kz];
+                    va[g][0] = fmar(cV.x, tw.x, va[g][0]);
+                    vb[g][0] = fmar(cV.y, tw.y, vb[g][0]);
+                    vd[g] = fmar(cV.y, kc, vd[g]);
+                    vc[g] = fmar(cV.x, ks, vc[g]);
+                    va[g][1] = fmar(cA.x, tw.x, va[g][1]);
+                    vb[g][1] = fmar(cA.y, tw.y, vb[g][1]);
+                    va[g][2] = fmar(cW.x, tw.x, va[g][2]);
+                    vb[g][2] = fmar(cW.y, tw.y, vb[g][2]);
+                }
+#pragma unroll
+                for (int i = 0; i < NG1; ++i) {
+                    const CR cc = c0[(3 * NG3 + i) * pfs + kz];
+                    aa[i] = fmar(cc.x, tw.x, aa[i]);
+                    ab[i] = fmar(cc.y, tw.y, ab[i]);
+                }
+            }
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {   // first point (z or z + Nz/2), then its mirror
+                const R m = h2 ? (R)1 : (R)-1;
+                // own parity's sum for this point, then the parities add (lane 0)
+                // or subtract (lane 1) with the partner's
+                auto tot = [&](R u) {
+                    const R y = lane_pair_swap(u);
+                    return pc ? y - u : u + y;
+                };
+                R val[NG3][4], at[NA];
+#pragma unroll
+                for (int g = 0; g < NG3; ++g) {
+                    val[g][0] = c0[(3 * g) * pfs].x + two * tot(fmar(m, vb[g][0], va[g][0]));
+                    val[g][1] = c0[(3 * g + 1) * pfs].x + two * tot(fmar(m, vb[g][1], va[g][1]));
+                    val[g][2] = c0[(3 * g + 2) * pfs].x + two * tot(fmar(m, vb[g][2], va[g][2]));
+                    val[g][3] = -two * beta * tot(fmar(-m, vc[g], vd[g]));
+                }
+#pragma unroll
+                for (int i = 0; i < NG1; ++i) at[i] = c0[(3 * NG3 + i) * pfs].x + two * tot(fmar(m, ab[i], aa[i]));
+                val[0][0] += yj;   // base flow u_b = y e_x
+                val[0][2] += (R)1; // d(u_b)_x / dy = 1
+                // the point z' < Nz/2 of each (z', z' + Nz/2) pair stores the sum
+                // of the two products, the other the difference, as the forward
+                // z transform reads them
+                const bool lower = pc == h2, wr = !(h2 && (z == 0 || z == q4));
+                const int zp = pc ? (h2 ? Nz / 2 - z : z + Nz / 2) : (h2 ? Nz - z : z);
+                const int pt = xl * ldq + zp;
+                auto put = [&](int f, R q) {
+                    const R w = lane_pair_swap(q);
+                    if (wr) pb[f * pz + pt] = lower ? q + w : w - q;
+                };
+                if (MODE == PLANE_FWD) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        put(i, val[0][0] * val[i][1] + val[1][0] * val[i][2] + val[2][0] * val[i][3]);
+                } else if (MODE == PLANE_JVP) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        R q = 0;
+#pragma unroll
+                        for (int jj = 0; jj < 3; ++jj)
+                            q += val[jj][0] * val[3 + i][1 + jj] + val[3 + jj][0] * val[i][1 + jj];
+                        put(i, q);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int jj = 0; jj < 3; ++jj) put(3 * i + jj, val[jj][0] * at[i]);
+#pragma unroll
+                    for (int jj = 0; jj < 3; ++jj)
+                        put(9 + jj, val[0][1 + jj] * at[0] + val[1][1 + jj] * at[1] + val[2][1 + jj] * at[2]);
+                }
             }
         }
-        // own sums S and the partner's P: point z is S + P (h = 0, S odd),
-        // point z + Nz/2 is S - P (h = 1, S even)
-        const R sg = h ? (R)-1 : (R)1;
-        auto tot = [&](R own) { return pair ? own + sg * lane_pair_swap(own) : own; };
-        R val[NG3][4], at[NA];
-#pragma unroll
-        for (int g = 0; g < NG3; ++g) {
-            val[g][0] = c0[(3 * g) * pfs].x + two * tot(v[g][0]);
-            val[g][1] = c0[(3 * g + 1) * pfs].x + two * tot(v[g][1]);
-            val[g][2] = c0[(3 * g + 2) * pfs].x + two * tot(v[g][2]);
-            val[g][3] = -two * beta * tot(v[g][3]);
-        }
-#pragma unroll
-        for (int i = 0; i < NG1; ++i) at[i] = c0[(3 * NG3 + i) * pfs].x + two * tot(a[i]);
-        val[0][0] += yj;   // base flow u_b = y e_x
-        val[0][2] += (R)1; // d(u_b)_x / dy = 1
-        // product f at this point; a lane pair stores the sum of its two
-        // products at z and their difference at z + Nz/2, which the forward z
-        // transform reads for even and odd kz respectively
-        const int pt = xl * ldq + z + h * hz;
-        auto put = [&](int f, R q) {
-            if (pair) {
-                const R w = lane_pair_swap(q);
-                pb[f * pz + pt] = h ? w - q : q + w;
+    } else {
+        // items XS * Nz (even with Nz even): lane pairs are active together
+        for (int it = tid; it < XS * Nz; it += PLANE_THREADS) {
+            const int h = pair ? (it & 1) : 0, pr = pair ? (it >> 1) : it;
+            const int xl = pr / hz, z = pr - xl * hz;
+            const CR* c0 = xb + xl * ldz;   // field f at c0[f * pfs + kz]
+            const CR* tz = TZ + z * tzs;
+            R v[NG3][4], a[NA];
+    #pragma unroll
+            for (int g = 0; g < NG3; ++g)
+    #pragma unroll
+                for (int q = 0; q < 4; ++q) v[g][q] = 0;
+    #pragma unroll
+            for (int i = 0; i < NA; ++i) a[i] = 0;
+            const int kst = pair ? 2 : 1;
+            for (int kz = 1 + h; kz < nkz; kz += kst) {
+                const CR tw = tz[kz];
+                const R kzr = (R)kz;
+    #pragma unroll
+                for (int g = 0; g < NG3; ++g) {
+                    const CR cV = c0[(3 * g) * pfs + kz], cA = c0[(3 * g + 1) * pfs + kz], cW = c0[(3 * g + 2) * pfs + kz];
+                    v[g][0] = fmar(-cV.y, tw.y, fmar(cV.x, tw.x, v[g][0]));
+                    v[g][3] = fmar(kzr, fmar(cV.y, tw.x, cV.x * tw.y), v[g][3]);
+                    v[g][1] = fmar(-cA.y, tw.y, fmar(cA.x, tw.x, v[g][1]));
+                    v[g][2] = fmar(-cW.y, tw.y, fmar(cW.x, tw.x, v[g][2]));
+                }
+    #pragma unroll
+                for (int i = 0; i < NG1; ++i) {
+                    const CR cc = c0[(3 * NG3 + i) * pfs + kz];
+                    a[i] = fmar(-cc.y, tw.y, fmar(cc.x, tw.x, a[i]));
+                }
+            }
+            // own sums S and the partner's P: point z is S + P (h = 0, S odd),
+            // point z + Nz/2 is S - P (h = 1, S even)
+            const R sg = h ? (R)-1 : (R)1;
+            auto tot = [&](R own) { return pair ? own + sg * lane_pair_swap(own) : own; };
+            R val[NG3][4], at[NA];
+    #pragma unroll
+            for (int g = 0; g < NG3; ++g) {
+                val[g][0] = c0[(3 * g) * pfs].x + two * tot(v[g][0]);
+                val[g][1] = c0[(3 * g + 1) * pfs].x + two * tot(v[g][1]);
+                val[g][2] = c0[(3 * g + 2) * pfs].x + two * tot(v[g][2]);
+                val[g][3] = -two * beta * tot(v[g][3]);
+            }
+    #pragma unroll
+            for (int i = 0; i < NG1; ++i) at[i] = c0[(3 * NG3 + i) * pfs].x + two * tot(a[i]);
+            val[0][0] += yj;   // base flow u_b = y e_x
+            val[0][2] += (R)1; // d(u_b)_x / dy = 1
+            // product f at this point; a lane pair stores the sum of its two
+            // products at z and their difference at z + Nz/2, which the forward z
+            // transform reads for even and odd kz respectively
+            const int pt = xl * ldq + z + h * hz;
+            auto put = [&](int f, R q) {
+                if (pair) {
+                    const R w = lane_pair_swap(q);
+                    pb[f * pz + pt] = h ? w - q : q + w;
+                } else {
+                    pb[f * pz + pt] = q;
+                }
+            };
+            if (MODE == PLANE_FWD) {
+    #pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    put(i, val[0][0] * val[i][1] + val[1][0] * val[i][2] + val[2][0] * val[i][3]);
+            } else if (MODE == PLANE_JVP) {
+    #pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    R q = 0;
+    #pragma unroll
+                    for (int jj = 0; jj < 3; ++jj)
+                        q += val[jj][0] * val[3 + i][1 + jj] + val[3 + jj][0] * val[i][1 + jj];
+                    put(i, q);
+                }
             } else {
-                pb[f * pz + pt] = q;
-            }
-        };
-        if (MODE == PLANE_FWD) {
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-                put(i, val[0][0] * val[i][1] + val[1][0] * val[i][2] + val[2][0] * val[i][3]);
-        } else if (MODE == PLANE_JVP) {
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                R q = 0;
-#pragma unroll
+    #pragma unroll
+                for (int i = 0; i < 3; ++i)
+    #pragma unroll
+                    for (int jj = 0; jj < 3; ++jj) put(3 * i + jj, val[jj][0] * at[i]);
+    #pragma unroll
                 for (int jj = 0; jj < 3; ++jj)
-                    q += val[jj][0] * val[3 + i][1 + jj] + val[3 + jj][0] * val[i][1 + jj];
-                put(i, q);
+                    put(9 + jj, val[0][1 + jj] * at[0] + val[1][1 + jj] * at[1] + val[2][1 + jj] * at[2]);
             }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int jj = 0; jj < 3; ++jj) put(3 * i + jj, val[jj][0] * at[i]);
-#pragma unroll
-            for (int jj = 0; jj < 3; ++jj)
-                put(9 + jj, val[0][1 + jj] * at[0] + val[1][1 + jj] * at[1] + val[2][1 + jj] * at[2]);
         }
     }
     __syncthreads();
